@@ -1,0 +1,229 @@
+/*
+ * zx.h -- C ABI of libzx: bit-packed GF(2) work on graph-like ZX diagrams
+ * for AMD MI355X (gfx950).
+ *
+ * Paper: "Tsim: Fast Universal Simulator for Quantum Error Correction"
+ * (arXiv 2604.01059).  Operations and the passages that define them:
+ *   local complementation  appendix "Rewrite rules", equation local_comp
+ *   pivoting               appendix "Rewrite rules", equation pivoting
+ *   simplification         stops when no interior pi/2 spider and no pair of
+ *                          adjacent interior pi spiders remains (appendix
+ *                          "Stabilizer decompositions", first paragraph);
+ *                          cost cubic in the spider count (section
+ *                          "Complexity", paragraph "Compilation")
+ *   GF(2) elimination      Gaussian elimination over F2 to a linearly
+ *                          independent basis (section on the repetition-code
+ *                          example, sentence after equation detector_sampling)
+ *   Pauli encoding         two bits per qubit, (x,z) = (1,0) X, (1,1) Y,
+ *                          (0,1) Z (appendix "Pauli channels", equation
+ *                          channel_pauli1 and the sentence after it)
+ *
+ * Conventions for every call
+ *   - Device memory is owned by the caller.  The library allocates no device
+ *     memory; scratch space comes from caller workspaces whose size the
+ *     matching *_workspace_bytes() call returns.  Host pointers are read
+ *     during the call only.
+ *   - Calls are asynchronous on the given stream unless documented as
+ *     synchronising.  The stream may be NULL (the null stream).
+ *   - Return value: ZX_OK or a negative zx_status.  Argument errors are
+ *     detected on the host and returned immediately; errors found by a
+ *     kernel (a rule whose precondition does not hold, a capacity overflow,
+ *     a spin-wait time-out) are recorded in a sticky status word that the
+ *     *_status() calls read.  zx_last_error() describes the most recent host
+ *     error of the calling thread.  No C++ exception crosses this boundary.
+ *   - Bit matrices are row-major arrays of uint64_t words: bit c of row r is
+ *     bit (c % 64) of word r * ld + c / 64.
+ */
+#ifndef ZX_H
+#define ZX_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t zx_status;
+#define ZX_OK 0
+#define ZX_EINVAL (-1)     /* bad argument (host-detected) */
+#define ZX_ENOMATCH (-2)   /* rule precondition false (device-detected) */
+#define ZX_ECAPACITY (-3)  /* size beyond what a kernel or workspace supports */
+#define ZX_EDEVICE (-4)    /* HIP runtime error or device spin-wait time-out */
+#define ZX_EBUSY (-5)      /* admission refused: budget exhausted */
+
+/* flags */
+#define ZX_GRAPH_ONLY 0x1u   /* rewrites: only the edge toggles, keep vertices/phases */
+#define ZX_SYNC 0x100u       /* synchronise the stream before returning */
+
+/* Version of the ABI (major * 100 + minor). */
+int32_t zx_version(void);
+/* Thread-local description of the last host-side error ("" if none). */
+const char* zx_last_error(void);
+/* Number of kernels and the device name the library will launch on. */
+zx_status zx_device_info(char* name, int32_t name_len, int32_t* n_cu);
+
+/* ======================================================================
+ * Graph-like diagrams
+ *
+ * A diagram lives in one caller-allocated device arena of zx_graph_bytes()
+ * bytes.  It holds:
+ *   - the SOURCE diagram given to zx_graph_create (read-only afterwards);
+ *   - the CURRENT diagram: adjacency n x W (W = ceil(n/64)), phases k
+ *     (int8, units of pi/4, 0..7), alive mask, scalar
+ *     omega^phase8 * sqrt(2)^pow_sqrt2 (omega = e^{i pi/4}) multiplying the
+ *     diagram's linear map;
+ *   - the rewrite trace and the extracted output frontier.
+ * Spiders are Z spiders joined by Hadamard edges.  Boundary wires are kept
+ * outside the adjacency: input i attaches to spider in_spider[i], output j to
+ * out_spider[j]; a spider carrying a boundary wire is never rewritten.
+ * ==================================================================== */
+typedef struct zx_graph zx_graph;
+
+typedef struct {
+  int64_t pow_sqrt2;   /* scalar: power of sqrt(2) */
+  int32_t phase8;      /* scalar: power of omega, 0..7 */
+  int32_t status;      /* sticky device status of this graph (zx_status) */
+  int32_t n;           /* spiders (rows of the adjacency) */
+  int32_t n_alive;     /* spiders still present */
+  int64_t n_edges;     /* Hadamard edges among present spiders */
+  int32_t n_trace;     /* rewrites recorded by the last zx_simplify */
+  int32_t rounds;      /* rewrite rounds of the last zx_simplify */
+  int64_t fill_in;     /* edges toggled on by rewrites */
+  int32_t rank;        /* rank of the output frontier (-1 if not extracted) */
+  int32_t pad;
+  int64_t rowops;      /* row additions of the frontier elimination */
+} zx_graph_info;
+
+/* Arena size for a diagram of n spiders with n_in inputs and n_out outputs. */
+size_t zx_graph_bytes(int32_t n, int32_t n_in, int32_t n_out);
+
+/* Create a diagram in dev_arena (device memory, >= zx_graph_bytes, 256-byte
+ * aligned).  adj_host: n x ceil(n/64) words, symmetric, zero diagonal, bits
+ * >= n zero.  phase_host: n values in 0..7.  in_spider/out_spider: distinct
+ * spider ids per boundary wire.  bnd_is_hadamard: n_in + n_out flags (NULL =
+ * all plain wires).  The host handle *g is freed by zx_graph_destroy; the
+ * arena stays the caller's.  Copies host->device on stream s. */
+zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
+                          const uint64_t* adj_host, const int8_t* phase_host,
+                          const int32_t* in_spider, int32_t n_in,
+                          const int32_t* out_spider, int32_t n_out,
+                          const uint8_t* bnd_is_hadamard, hipStream_t s);
+/* Attach a handle to an arena already initialised by zx_graph_create. */
+zx_status zx_graph_attach(zx_graph** g, void* dev_arena, size_t arena_bytes);
+void zx_graph_destroy(zx_graph* g);   /* host handle only */
+void* zx_graph_arena(const zx_graph* g);
+
+/* Copy the CURRENT diagram to host buffers (any may be NULL).  Synchronises s.
+ * adj: n x W words; phase: n bytes; alive: W words. */
+zx_status zx_graph_read(const zx_graph* g, uint64_t* adj, int8_t* phase, uint64_t* alive,
+                        zx_graph_info* info, hipStream_t s);
+/* Trace of the last zx_simplify: n_trace entries {round, rule, u, v},
+ * rule 0 = local complementation (v = -1), 1 = pivot.  Synchronises s. */
+zx_status zx_graph_read_trace(const zx_graph* g, int32_t* trace, int32_t cap,
+                              int32_t* n_trace, hipStream_t s);
+/* Output frontier after zx_simplify with extraction: n_out x W words in
+ * reduced row echelon form and n_out pivot columns (-1 padded).  Synchronises. */
+zx_status zx_graph_read_frontier(const zx_graph* g, uint64_t* rows, int32_t* pivots,
+                                 hipStream_t s);
+/* Sticky device status of the graph (synchronises s). */
+zx_status zx_graph_status(const zx_graph* g, hipStream_t s);
+/* Make the CURRENT diagram equal to the SOURCE diagram again (async). */
+zx_status zx_graph_reset(zx_graph* g, hipStream_t s);
+
+/* Local complementation at spider u on the CURRENT diagram (rule above).
+ * Precondition (checked on the device): u present, no boundary wire, phase
+ * pi/2 or 3pi/2.  If it fails nothing changes and the graph's status becomes
+ * ZX_ENOMATCH.  flags & ZX_GRAPH_ONLY: complement the edges among N(u) only
+ * (u must be present; phases, scalar and u are kept). */
+zx_status zx_local_comp(zx_graph* g, int32_t u, uint32_t flags, hipStream_t s);
+/* Pivot on the edge u-v of the CURRENT diagram (rule above).  Precondition
+ * (device): u ~ v, both present without boundary wire, phases 0 or pi.
+ * ZX_GRAPH_ONLY: complete tripartite toggle between N(u) only, N(v) only and
+ * common neighbours; u and v are kept. */
+zx_status zx_pivot(zx_graph* g, int32_t u, int32_t v, uint32_t flags, hipStream_t s);
+
+/* ======================================================================
+ * Simplification to the rules' fixed point
+ *
+ * zx_simplify starts from each graph's SOURCE diagram (so it can be re-run),
+ * writes the result into the CURRENT diagram, the trace, and with extract=1
+ * the reduced output frontier.  Schedule (deterministic, bit-exact with the
+ * CPU reference): local-complementation rounds, then pivot rounds.  An LC
+ * round takes, in ascending spider id, every candidate not adjacent to one
+ * already taken; a pivot round takes, in lexicographic order, every
+ * candidate edge whose ends are distinct from and not adjacent to the ends
+ * already taken.  All rewrites of a round are applied together.
+ * ==================================================================== */
+#define ZX_POLICY_GREEDY 0
+
+typedef struct {
+  int32_t policy;     /* ZX_POLICY_GREEDY */
+  int32_t extract;    /* 1 = also reduce the output frontier */
+  int32_t tune_id;    /* kernel variant, -1 = autotuned / default */
+  uint32_t flags;     /* ZX_SYNC */
+} zx_simplify_opts;
+
+/* Number of kernel variants and a short description of variant id. */
+int32_t zx_simplify_variants(void);
+const char* zx_simplify_variant_name(int32_t id);
+
+/* Workspace for a batch of n_graphs diagrams. */
+size_t zx_simplify_workspace_bytes(int32_t n_graphs);
+
+/* One persistent launch over all graphs (uploads the batch descriptor into
+ * ws first, synchronously).  Larger diagrams are scheduled first. */
+zx_status zx_simplify(zx_graph* const* graphs, int32_t n_graphs, const zx_simplify_opts* o,
+                      void* ws, size_t ws_bytes, hipStream_t s);
+
+/* Batch plans: prepare once (uploads the descriptor table into ws,
+ * synchronous), then launch any number of times with zx_batch_simplify,
+ * which only enqueues kernels and may be captured into a HIP graph. */
+typedef struct zx_batch zx_batch;
+zx_status zx_batch_prepare(zx_batch** b, zx_graph* const* graphs, int32_t n_graphs,
+                           void* ws, size_t ws_bytes, hipStream_t s);
+zx_status zx_batch_simplify(zx_batch* b, const zx_simplify_opts* o, hipStream_t s);
+/* Worst sticky status over the batch's graphs (synchronises). */
+zx_status zx_batch_status(zx_batch* b, hipStream_t s);
+/* Time every variant on this batch (reps launches each, after one warm-up)
+ * and return the fastest id; results are cached per (device, size class). */
+zx_status zx_batch_autotune(zx_batch* b, int32_t extract, int32_t reps, int32_t* best_id,
+                            float* best_ms, hipStream_t s);
+void zx_batch_destroy(zx_batch* b);
+
+/* ======================================================================
+ * GF(2) reduced row echelon form
+ *
+ * R = RREF(A) for an m x n_cols bit matrix (ld words per row; bits >= n_cols
+ * are ignored and written as zero).  A and R may be the same buffer (in
+ * place); otherwise they must not overlap.  rank_dev: one device int32.
+ * pivot_cols_dev: m device int32, pivot column of output row i, -1 for rows
+ * beyond the rank.  One cooperative persistent launch: every word column
+ * lives in one workgroup's LDS, so m * 8 bytes per column must fit
+ * (m <= 16384) and the grid must be co-resident; otherwise ZX_ECAPACITY.
+ * ==================================================================== */
+size_t zx_gf2_workspace_bytes(int32_t m, int32_t n_cols);
+zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
+                           int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
+                           void* ws, size_t ws_bytes, hipStream_t s);
+/* Sticky status of the last elimination that used this workspace (syncs). */
+zx_status zx_gf2_status(const void* ws, hipStream_t s);
+
+/* ======================================================================
+ * Symplectic commutation table of Pauli strings
+ *
+ * X, Z: n_paulis x ld_q words (device); qubit b of string i is bit b of the
+ * X and Z rows.  C: n_paulis x ld_c words (device, ld_c >= ceil(n/64)),
+ * C[i][j] = parity of sum_b x_i[b] z_j[b] + z_i[b] x_j[b], i.e. 1 when
+ * strings i and j anticommute.  Bits beyond n_paulis in a row are zero.
+ * ==================================================================== */
+#define ZX_PAULI_AUTO 0u
+zx_status zx_pauli_commute(const uint64_t* X, const uint64_t* Z, int64_t n_paulis,
+                           int32_t n_qubits, int64_t ld_q, uint64_t* C, int64_t ld_c,
+                           uint32_t flags, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZX_H */

@@ -1,0 +1,123 @@
+// Symplectic commutation table of Pauli strings.
+//
+// A Pauli string is stored as two bit vectors x, z (the paper's per-qubit
+// encoding (1,0) = X, (1,1) = Y, (0,1) = Z, (0,0) = I).  Strings i and j
+// anticommute exactly when  sum_b x_i[b] z_j[b] + z_i[b] x_j[b]  is odd.
+//
+// Kernel: the table is symmetric, so only 64 x 64 tiles (i-tile it, j-word
+// jw) with jw >= it are computed.  A wavefront owns one tile: lane l holds
+// string j = 64 jw + l in registers, the tile's 64 strings i are staged in
+// LDS and read as broadcasts, and v_bitop3_b32 folds
+// acc ^= (x_i & z_j) ^ (z_i & x_j) in two instructions per 32-bit half.
+// Lane l accumulates the 64 parities of its string as a bit mask over i:
+// that mask is word it of row j (the mirrored tile), and 64 ballots give
+// word jw of the tile's rows i.  Qubits are processed 1024 at a time.
+#include "zx_internal.h"
+
+namespace {
+
+constexpr int BS = 256;              // 4 wavefronts
+constexpr int QCH = 16;              // 64-bit words of qubits per chunk
+constexpr int JW_PER_BLOCK = 16;     // j-words per block (4 per wavefront)
+
+__device__ __forceinline__ uint32_t xor_and(uint32_t acc, uint32_t a, uint32_t b) {
+  // acc ^ (a & b): truth table over (acc, a, b) = (0xF0, 0xCC, 0xAA) -> 0x78
+  return __builtin_amdgcn_bitop3_b32(acc, a, b, 0x78);
+}
+
+__global__ __launch_bounds__(BS) void pauli_kernel(const uint64_t* __restrict__ X,
+                                                   const uint64_t* __restrict__ Z, int64_t n,
+                                                   int qw, int64_t ldq, uint64_t* __restrict__ C,
+                                                   int64_t ldc) {
+  __shared__ uint64_t xi_s[64][QCH];
+  __shared__ uint64_t zi_s[64][QCH];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t it = blockIdx.y;
+  const int64_t nwj = (n + 63) / 64;
+  const int64_t jw_begin = (int64_t)blockIdx.x * JW_PER_BLOCK;
+  if (jw_begin + JW_PER_BLOCK - 1 < it) return;  // block entirely below the diagonal
+  const int64_t i0 = it * 64;
+
+  for (int64_t jw = jw_begin + wv; jw < jw_begin + JW_PER_BLOCK; jw += BS / 64) {
+    // every wave runs the same number of iterations (barriers inside)
+    const bool active = jw < nwj && jw >= it;
+    const int64_t j = jw * 64 + lane;
+    uint64_t pbits = 0;  // bit i: parity of (i0 + i, j)
+    for (int q0 = 0; q0 < qw; q0 += QCH) {
+      const int nq = qw - q0 < QCH ? qw - q0 : QCH;
+      __syncthreads();
+      for (int t = threadIdx.x; t < 64 * QCH; t += BS) {
+        const int r = t / QCH, w = t % QCH;
+        const int64_t i = i0 + r;
+        const bool in = i < n && w < nq;
+        xi_s[r][w] = in ? X[i * ldq + q0 + w] : 0;
+        zi_s[r][w] = in ? Z[i * ldq + q0 + w] : 0;
+      }
+      __syncthreads();
+      if (!active) continue;
+      uint32_t xj[2 * QCH], zj[2 * QCH];
+#pragma unroll
+      for (int w = 0; w < QCH; ++w) {
+        uint64_t xv = 0, zv = 0;
+        if (w < nq && j < n) {
+          xv = X[j * ldq + q0 + w];
+          zv = Z[j * ldq + q0 + w];
+        }
+        xj[2 * w] = (uint32_t)xv;
+        xj[2 * w + 1] = (uint32_t)(xv >> 32);
+        zj[2 * w] = (uint32_t)zv;
+        zj[2 * w + 1] = (uint32_t)(zv >> 32);
+      }
+      for (int r = 0; r < 64; ++r) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < QCH; ++w) {
+          const uint64_t xi = xi_s[r][w], zi = zi_s[r][w];
+          acc = xor_and(acc, (uint32_t)xi, zj[2 * w]);
+          acc = xor_and(acc, (uint32_t)zi, xj[2 * w]);
+          acc = xor_and(acc, (uint32_t)(xi >> 32), zj[2 * w + 1]);
+          acc = xor_and(acc, (uint32_t)(zi >> 32), xj[2 * w + 1]);
+        }
+        pbits ^= (uint64_t)(__popc(acc) & 1) << r;
+      }
+    }
+    if (!active) continue;
+    // mirrored tile: row j, word it
+    const uint64_t valid_i = (n - i0) >= 64 ? ~0ull : ((1ull << (n - i0)) - 1);
+    if (j < n) C[j * ldc + it] = pbits & valid_i;
+    // tile rows: row i0 + r, word jw
+    uint64_t mine = 0;
+    for (int r = 0; r < 64; ++r) {
+      const uint64_t wrd = __ballot((pbits >> r) & 1);
+      if (lane == r) mine = wrd;
+    }
+    const int64_t i = i0 + lane;
+    if (i < n) C[i * ldc + jw] = mine;  // lanes j >= n contribute zeros
+  }
+}
+
+__global__ void clear_tail(uint64_t* C, int64_t n, int64_t ldc) {
+  // words beyond ceil(n/64) in each row are left untouched; nothing to do
+  (void)C; (void)n; (void)ldc;
+}
+
+}  // namespace
+
+extern "C" zx_status zx_pauli_commute(const uint64_t* X, const uint64_t* Z, int64_t n_paulis,
+                                      int32_t n_qubits, int64_t ld_q, uint64_t* C, int64_t ld_c,
+                                      uint32_t flags, hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(X && Z && C, "null argument");
+  ZX_CHECK_ARG(n_paulis > 0 && n_qubits > 0, "empty input");
+  const int qw = (n_qubits + 63) / 64;
+  ZX_CHECK_ARG(ld_q >= qw, "ld_q too small");
+  const int64_t nwj = (n_paulis + 63) / 64;
+  ZX_CHECK_ARG(ld_c >= nwj, "ld_c too small");
+  ZX_CHECK_ARG(nwj <= 65535 * (int64_t)JW_PER_BLOCK && nwj <= 65535, "too many strings");
+  (void)flags;
+  dim3 grid((unsigned)((nwj + JW_PER_BLOCK - 1) / JW_PER_BLOCK), (unsigned)nwj);
+  hipLaunchKernelGGL(pauli_kernel, grid, dim3(BS), 0, s, X, Z, n_paulis, qw, ld_q, C, ld_c);
+  ZX_HIP(hipGetLastError());
+  if (flags & ZX_SYNC) ZX_HIP(hipStreamSynchronize(s));
+  return ZX_OK;
+}

@@ -1,0 +1,116 @@
+// Internal definitions shared by the libzx sources: arena layout, error
+// plumbing, small device helpers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/zx.h"
+
+#define ZX_ABI_VERSION 100
+
+// ---------------------------------------------------------------- arena --
+// One diagram arena: a 256-byte header followed by 256-byte aligned sections.
+// Offsets are relative to the arena base.
+#define ZX_MAGIC 0x5A584731  // "ZXG1"
+
+struct ZxHeader {
+  int32_t magic;
+  int32_t n, n_in, n_out;
+  int32_t W;            // words per adjacency row
+  int32_t status;       // sticky zx_status
+  int32_t n_trace;
+  int32_t rounds;
+  int32_t rank;         // frontier rank, -1 before extraction
+  int32_t n_alive;
+  int64_t pow_sqrt2;
+  int32_t phase8;
+  int32_t pad0;
+  int64_t fill_in;
+  int64_t rowops;
+  int64_t n_edges;
+  // section offsets
+  int64_t off_src_adj, off_src_phase, off_in, off_out, off_is_h, off_bndmask;
+  int64_t off_adj, off_phase, off_alive, off_trace, off_front, off_fpiv;
+  int64_t bytes;
+  int64_t reserved[7];
+};
+static_assert(sizeof(ZxHeader) <= 256, "header fits 256 bytes");
+
+static inline __host__ __device__ int64_t zx_align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+struct ZxLayout {
+  int64_t off_src_adj, off_src_phase, off_in, off_out, off_is_h, off_bndmask;
+  int64_t off_adj, off_phase, off_alive, off_trace, off_front, off_fpiv, bytes;
+};
+
+static inline __host__ __device__ ZxLayout zx_layout(int32_t n, int32_t n_in, int32_t n_out) {
+  ZxLayout L;
+  int64_t W = (n + 63) / 64;
+  int64_t o = 256;
+  L.off_src_adj = o;   o = zx_align256(o + (int64_t)n * W * 8);
+  L.off_src_phase = o; o = zx_align256(o + n);
+  L.off_in = o;        o = zx_align256(o + 4 * (int64_t)n_in);
+  L.off_out = o;       o = zx_align256(o + 4 * (int64_t)n_out);
+  L.off_is_h = o;      o = zx_align256(o + n_in + n_out);
+  L.off_bndmask = o;   o = zx_align256(o + W * 8);
+  L.off_adj = o;       o = zx_align256(o + (int64_t)n * W * 8);
+  L.off_phase = o;     o = zx_align256(o + n);
+  L.off_alive = o;     o = zx_align256(o + W * 8);
+  L.off_trace = o;     o = zx_align256(o + 16 * (int64_t)(n + 1));
+  L.off_front = o;     o = zx_align256(o + (int64_t)n_out * W * 8);
+  L.off_fpiv = o;      o = zx_align256(o + 4 * (int64_t)(n_out + 1));
+  L.bytes = o;
+  return L;
+}
+
+// Host handle of a diagram arena.
+struct zx_graph {
+  uint8_t* arena;  // device
+  size_t bytes;
+  int32_t n, n_in, n_out, W;
+  ZxLayout L;
+};
+
+// ------------------------------------------------------------ errors --
+void zx_set_error(const char* fmt, ...);
+void zx_clear_error();
+
+#define ZX_CHECK_ARG(cond, ...)            \
+  do {                                     \
+    if (!(cond)) {                         \
+      zx_set_error(__VA_ARGS__);           \
+      return ZX_EINVAL;                    \
+    }                                      \
+  } while (0)
+
+#define ZX_HIP(call)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess) {                                                \
+      zx_set_error("%s failed: %s", #call, hipGetErrorString(e_));         \
+      return ZX_EDEVICE;                                                   \
+    }                                                                      \
+  } while (0)
+
+// device properties cached per device
+struct ZxDevice {
+  int id;
+  int n_cu;
+  size_t lds_per_block;  // max dynamic LDS per workgroup
+  char name[128];
+};
+const ZxDevice* zx_device();
+
+// ---------------------------------------------------- device helpers --
+// Device-side status update: keep the first error.
+__device__ static inline void zx_dev_fail(int32_t* status, int32_t code) {
+  atomicCAS(status, 0, code);
+}
+
+// Sticky status word of a workspace (first 256 bytes of every workspace).
+struct ZxWsHeader {
+  int32_t status;
+  int32_t pad[63];
+};

@@ -1,0 +1,321 @@
+"""ctypes binding of libzx (include/zx.h): argument marshalling only.
+
+Device buffers are torch tensors on a ROCm device (their data_ptr() is passed
+through); host arrays are numpy.  Every computation happens in the HIP
+library; if libzx.so is missing this module raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzx.so")
+
+ZX_OK, ZX_EINVAL, ZX_ENOMATCH, ZX_ECAPACITY, ZX_EDEVICE, ZX_EBUSY = 0, -1, -2, -3, -4, -5
+ZX_GRAPH_ONLY = 0x1
+ZX_SYNC = 0x100
+STATUS_NAMES = {0: "ZX_OK", -1: "ZX_EINVAL", -2: "ZX_ENOMATCH", -3: "ZX_ECAPACITY",
+                -4: "ZX_EDEVICE", -5: "ZX_EBUSY"}
+
+
+class ZxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [("pow_sqrt2", C.c_int64), ("phase8", C.c_int32), ("status", C.c_int32),
+                ("n", C.c_int32), ("n_alive", C.c_int32), ("n_edges", C.c_int64),
+                ("n_trace", C.c_int32), ("rounds", C.c_int32), ("fill_in", C.c_int64),
+                ("rank", C.c_int32), ("pad", C.c_int32), ("rowops", C.c_int64)]
+
+
+class SimplifyOpts(C.Structure):
+    _fields_ = [("policy", C.c_int32), ("extract", C.c_int32), ("tune_id", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libzx.so (built by ``python -m paper_2604_01059_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libzx.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
+    sigs = {
+        "zx_version": ([], i32),
+        "zx_last_error": ([], C.c_char_p),
+        "zx_device_info": ([C.c_char_p, i32, C.POINTER(i32)], i32),
+        "zx_graph_bytes": ([i32, i32, i32], sz),
+        "zx_graph_create": ([C.POINTER(P), P, sz, i32, P, P, P, i32, P, i32, P, P], i32),
+        "zx_graph_attach": ([C.POINTER(P), P, sz], i32),
+        "zx_graph_destroy": ([P], None),
+        "zx_graph_arena": ([P], P),
+        "zx_graph_read": ([P, P, P, P, C.POINTER(GraphInfo), P], i32),
+        "zx_graph_read_trace": ([P, P, i32, C.POINTER(i32), P], i32),
+        "zx_graph_read_frontier": ([P, P, P, P], i32),
+        "zx_graph_status": ([P, P], i32),
+        "zx_graph_reset": ([P, P], i32),
+        "zx_local_comp": ([P, i32, u32, P], i32),
+        "zx_pivot": ([P, i32, i32, u32, P], i32),
+        "zx_simplify_variants": ([], i32),
+        "zx_simplify_variant_name": ([i32], C.c_char_p),
+        "zx_simplify_workspace_bytes": ([i32], sz),
+        "zx_simplify": ([P, i32, C.POINTER(SimplifyOpts), P, sz, P], i32),
+        "zx_batch_prepare": ([C.POINTER(P), P, i32, P, sz, P], i32),
+        "zx_batch_simplify": ([P, C.POINTER(SimplifyOpts), P], i32),
+        "zx_batch_status": ([P, P], i32),
+        "zx_batch_autotune": ([P, i32, i32, C.POINTER(i32), C.POINTER(C.c_float), P], i32),
+        "zx_batch_destroy": ([P], None),
+        "zx_gf2_workspace_bytes": ([i32, i32], sz),
+        "zx_gf2_eliminate": ([P, P, i32, i32, i64, P, P, P, sz, P], i32),
+        "zx_gf2_status": ([P, P], i32),
+        "zx_pauli_commute": ([P, P, i64, i32, i64, P, i64, u32, P], i32),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["zx_version", "zx_last_error", "zx_device_info", "zx_graph_bytes", "zx_graph_create",
+            "zx_graph_attach", "zx_graph_destroy", "zx_graph_arena", "zx_graph_read",
+            "zx_graph_read_trace", "zx_graph_read_frontier", "zx_graph_status", "zx_graph_reset",
+            "zx_local_comp", "zx_pivot", "zx_simplify_variants", "zx_simplify_variant_name",
+            "zx_simplify_workspace_bytes", "zx_simplify", "zx_batch_prepare", "zx_batch_simplify",
+            "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
+            "zx_gf2_eliminate", "zx_gf2_status", "zx_pauli_commute"]
+
+
+def _check(rc):
+    if rc < 0:
+        raise ZxError(rc, load().zx_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def version():
+    return load().zx_version()
+
+
+def device_info():
+    buf = C.create_string_buffer(128)
+    cu = C.c_int32(0)
+    _check(load().zx_device_info(buf, 128, C.byref(cu)))
+    return buf.value.decode(), cu.value
+
+
+# ---------------------------------------------------------------- graphs --
+
+class Graph:
+    """Host handle of a diagram arena (torch uint8 device tensor)."""
+
+    def __init__(self, handle, arena, n, n_in, n_out):
+        self.h = handle
+        self.arena = arena
+        self.n, self.n_in, self.n_out = n, n_in, n_out
+        self.W = (n + 63) // 64
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zx_graph_destroy(self.h)
+            self.h = None
+
+    @staticmethod
+    def bytes_for(n, n_in, n_out):
+        return load().zx_graph_bytes(n, n_in, n_out)
+
+    @classmethod
+    def create(cls, adj, phase, inputs, outputs, bnd_is_h=None, arena=None, stream=None):
+        import torch
+        adj = np.ascontiguousarray(adj, dtype=np.uint64)
+        phase = np.ascontiguousarray(phase, dtype=np.int8)
+        inputs = np.ascontiguousarray(inputs, dtype=np.int32)
+        outputs = np.ascontiguousarray(outputs, dtype=np.int32)
+        n = int(adj.shape[0])
+        nb = cls.bytes_for(n, len(inputs), len(outputs))
+        if arena is None:
+            arena = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        bh = None if bnd_is_h is None else np.ascontiguousarray(bnd_is_h, dtype=np.uint8)
+        h = C.c_void_p()
+        _check(load().zx_graph_create(C.byref(h), _ptr(arena), arena.numel(), n, _np(adj), _np(phase),
+                                      _np(inputs), len(inputs), _np(outputs), len(outputs), _np(bh),
+                                      _stream(stream)))
+        return cls(h, arena, n, len(inputs), len(outputs))
+
+    @classmethod
+    def from_diagram(cls, d, arena=None, stream=None):
+        return cls.create(d.adj, d.phase, d.inputs, d.outputs, d.bnd_is_h, arena=arena, stream=stream)
+
+    def read(self, stream=None):
+        adj = np.zeros((self.n, self.W), np.uint64)
+        ph = np.zeros(self.n, np.int8)
+        al = np.zeros(self.W, np.uint64)
+        info = GraphInfo()
+        _check(load().zx_graph_read(self.h, _np(adj), _np(ph), _np(al), C.byref(info), _stream(stream)))
+        return adj, ph, al, info
+
+    def info(self, stream=None):
+        info = GraphInfo()
+        _check(load().zx_graph_read(self.h, None, None, None, C.byref(info), _stream(stream)))
+        return info
+
+    def trace(self, stream=None):
+        cap = self.n + 1
+        tr = np.zeros((cap, 4), np.int32)
+        nt = C.c_int32(0)
+        _check(load().zx_graph_read_trace(self.h, _np(tr), cap, C.byref(nt), _stream(stream)))
+        return tr[: nt.value].copy()
+
+    def frontier(self, stream=None):
+        rows = np.zeros((self.n_out, self.W), np.uint64)
+        piv = np.zeros(max(self.n_out, 1), np.int32)
+        _check(load().zx_graph_read_frontier(self.h, _np(rows), _np(piv), _stream(stream)))
+        return rows, piv[: self.n_out].copy()
+
+    def status(self, stream=None):
+        return load().zx_graph_status(self.h, _stream(stream))
+
+    def reset(self, stream=None):
+        _check(load().zx_graph_reset(self.h, _stream(stream)))
+
+    def local_comp(self, u, graph_only=False, stream=None):
+        _check(load().zx_local_comp(self.h, int(u), ZX_GRAPH_ONLY if graph_only else 0, _stream(stream)))
+
+    def pivot(self, u, v, graph_only=False, stream=None):
+        _check(load().zx_pivot(self.h, int(u), int(v), ZX_GRAPH_ONLY if graph_only else 0, _stream(stream)))
+
+
+def simplify_workspace_bytes(n_graphs):
+    return load().zx_simplify_workspace_bytes(n_graphs)
+
+
+def _graph_array(graphs):
+    arr = (C.c_void_p * len(graphs))(*[g.h.value if isinstance(g.h, C.c_void_p) else g.h for g in graphs])
+    return arr
+
+
+def simplify(graphs, extract=True, tune_id=-1, ws=None, stream=None):
+    import torch
+    n = len(graphs)
+    nb = simplify_workspace_bytes(n)
+    if ws is None:
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    opts = SimplifyOpts(0, 1 if extract else 0, tune_id, 0)
+    _check(load().zx_simplify(_graph_array(graphs), n, C.byref(opts), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+class Batch:
+    """A prepared batch: one persistent launch per ``run`` (capturable)."""
+
+    def __init__(self, graphs, stream=None):
+        import torch
+        self.graphs = list(graphs)
+        n = len(self.graphs)
+        self.ws = torch.empty(simplify_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        _check(load().zx_batch_prepare(C.byref(h), _graph_array(self.graphs), n, _ptr(self.ws),
+                                       self.ws.numel(), _stream(stream)))
+        self.h = h
+
+    def run(self, extract=True, tune_id=-1, stream=None):
+        opts = SimplifyOpts(0, 1 if extract else 0, tune_id, 0)
+        _check(load().zx_batch_simplify(self.h, C.byref(opts), _stream(stream)))
+
+    def status(self, stream=None):
+        return load().zx_batch_status(self.h, _stream(stream))
+
+    def autotune(self, extract=True, reps=3, stream=None):
+        best = C.c_int32(-1)
+        ms = C.c_float(0)
+        _check(load().zx_batch_autotune(self.h, 1 if extract else 0, reps, C.byref(best), C.byref(ms),
+                                        _stream(stream)))
+        return best.value, ms.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zx_batch_destroy(self.h)
+            self.h = None
+
+
+def simplify_variants():
+    lib = load()
+    return [lib.zx_simplify_variant_name(i).decode() for i in range(lib.zx_simplify_variants())]
+
+
+# ------------------------------------------------------------------ GF(2) --
+
+def gf2_workspace_bytes(m, n_cols):
+    return load().zx_gf2_workspace_bytes(m, n_cols)
+
+
+def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, stream=None):
+    """RREF of A (torch int64/uint64-view device tensor, m x ld words).
+    Returns (R, rank tensor, pivots tensor, ws)."""
+    import torch
+    m, ld = A.shape
+    n_cols = 64 * ld if n_cols is None else n_cols
+    if R is None:
+        R = torch.empty_like(A)
+    if rank is None:
+        rank = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if pivots is None:
+        pivots = torch.zeros(m, dtype=torch.int32, device=A.device)
+    if ws is None:
+        ws = torch.empty(gf2_workspace_bytes(m, n_cols), dtype=torch.uint8, device=A.device)
+    _check(load().zx_gf2_eliminate(_ptr(A), _ptr(R), m, n_cols, ld, _ptr(rank), _ptr(pivots),
+                                   _ptr(ws), ws.numel(), _stream(stream)))
+    return R, rank, pivots, ws
+
+
+def gf2_status(ws, stream=None):
+    return load().zx_gf2_status(_ptr(ws), _stream(stream))
+
+
+# ------------------------------------------------------------------ Pauli --
+
+def pauli_commute(X, Z, n_qubits, C_out=None, stream=None):
+    import torch
+    n, ldq = X.shape
+    ldc = (n + 63) // 64
+    if C_out is None:
+        C_out = torch.empty((n, ldc), dtype=X.dtype, device=X.device)
+    _check(load().zx_pauli_commute(_ptr(X), _ptr(Z), n, n_qubits, ldq, _ptr(C_out), C_out.shape[1], 0,
+                                   _stream(stream)))
+    return C_out
+
+
+def to_device_words(a: np.ndarray):
+    """numpy uint64 array -> torch int64 device tensor with the same bits."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def to_host_words(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
