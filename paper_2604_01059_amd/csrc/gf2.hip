@@ -7,42 +7,61 @@
 // strips.  For strip s:
 //   1. the workgroup that owns word column s picks up to 128 candidate rows
 //      (not yet pivots, non-zero in the strip) and reduces them in one
-//      wavefront: for each bit b, a ballot finds the first candidate with bit
-//      b set, its word is broadcast and XORed into every other candidate
-//      holding b.  This yields up to 64 pivot rows, their bit positions and,
-//      per pivot, a 64-bit mask L saying which ORIGINAL pivot rows combine
-//      into the reduced pivot row;
+//      wavefront: for each bit b a ballot finds the first candidate holding
+//      b, its word is broadcast through scalar registers and XORed into every
+//      other candidate holding b.  This yields up to 64 pivot rows, their bit
+//      positions and, per pivot, a 64-bit mask L of the ORIGINAL pivot rows
+//      that combine into the reduced pivot row;
 //   2. it publishes that "pass" (rows, bits, masks) plus a snapshot of its
-//      column to the other workgroups through a small ring in the workspace
-//      (release/acquire flags, cumulative acknowledgement counters);
+//      column through a ring in the workspace;
 //   3. every workgroup applies the pass to each of its columns c > s:
-//      reduced pivot words P'_j = XOR of L_j-selected original pivot words,
-//      then every other row r gets XOR of P' over the pivot bits set in its
-//      strip word (Four-Russians: 16 tables of 16 nibble combinations, one
-//      lookup per nibble, conflict-free in LDS), and pivot rows become P'.
-// If a pass found fewer than 64 pivots while more non-zero rows existed
-// than candidates, the owner runs further passes on the residual rows.  The
-// pivot columns found are always leading bits of row-space vectors, and the
-// passes only stop when every non-pivot row is zero in the strip, so the
-// final rows are the unique RREF basis.  Rows stay in place; the output is
-// written at the end, pivot rows in pivot-column order, then zero rows.
+//      reduced pivot words P'_j = XOR of the L_j-selected original pivot
+//      words; every other row r gets the XOR of P' over the pivot bits set in
+//      its strip word (Four-Russians: 16 tables of 16 nibble combinations,
+//      conflict-free in LDS), and pivot rows become P'.
+// The owner of strip s + 1 writes the snapshot and collects the candidates of
+// its strip while it applies the last pass of strip s, so its factorisation
+// starts as soon as that pass is applied.
+//
+// If a pass found fewer than 64 pivots while more non-zero rows existed than
+// candidates, the owner runs further passes on the residual rows.  Pivot
+// columns found are always leading bits of row-space vectors and a strip ends
+// only when every non-pivot row is zero in it, so the final rows are the
+// unique RREF basis.  Rows stay in place; at the end the pivot rows are
+// written in pivot-column order, then zero rows.
+//
+// Cross-workgroup hand-off.  The L2 caches of the eight XCDs are not coherent
+// with each other, so everything another workgroup reads (flags, records,
+// snapshots) is written and read with device-scope relaxed atomics: on
+// gfx950 those are vector loads/stores with the sc1 cache policy, which go
+// to the device coherence point without the whole-L2 write-back/invalidate
+// of acquire/release fences.  A producer makes every wave wait for its
+// stores (s_waitcnt 0) before the barrier that precedes its flag store; a
+// consumer issues its payload loads only after it has seen the flag.
+#include <stdlib.h>
 #include <string.h>
 
 #include "zx_internal.h"
 
 namespace {
 
-constexpr int BS = 512;       // threads per workgroup
-constexpr int RING = 8;       // pass records in flight
-constexpr int NCAND = 128;    // candidate rows per pass
-constexpr int MAX_M = 16384;  // rows that fit one column per workgroup in LDS
-constexpr int MAX_CW = 4;     // word columns per workgroup
+constexpr int BS = 512;           // threads per workgroup
+constexpr int NWAVE = BS / 64;
+constexpr int RING = 8;           // pass records in flight
+constexpr int NCAND = 128;        // candidate rows per pass
+constexpr int MAX_M = 16384;      // rows that fit one column per workgroup in LDS
+constexpr int MAX_SL = MAX_M / BS;  // row slices per thread
+constexpr int MAX_CW = 4;         // word columns per workgroup
+constexpr int MAX_STRIPS = 4096;  // strips with profile slots
+constexpr int PROF_SLOTS = 8;     // timestamps per strip (profiling only)
+constexpr int GROUP = 8;          // row slices whose multipliers are loaded together
 
 struct PassRec {
   int32_t strip;
   int32_t k;       // pivots in this pass (0 for an end-of-strip marker)
   int32_t last;    // strip finished with this record
   int32_t pad0;
+  uint64_t pivmask;  // strip bit positions that hold pivots
   int32_t rows[64];
   int32_t bits[64];
   uint64_t L[64];
@@ -56,7 +75,7 @@ struct Ctl {
 };
 
 struct WsLayout {
-  size_t ctl, recs, snaps, piv_row, piv_col, bytes;
+  size_t ctl, recs, snaps, piv_row, piv_col, prof, bytes;
 };
 
 WsLayout ws_layout(int m) {
@@ -67,6 +86,7 @@ WsLayout ws_layout(int m) {
   L.snaps = o;   o += (((size_t)m * 8 * RING) + 255) & ~size_t(255);
   L.piv_row = o; o += (((size_t)m * 4) + 255) & ~size_t(255);
   L.piv_col = o; o += (((size_t)m * 4) + 255) & ~size_t(255);
+  L.prof = o;    o += ((size_t)MAX_STRIPS * PROF_SLOTS * 8 + 255) & ~size_t(255);
   L.bytes = o;
   return L;
 }
@@ -85,20 +105,35 @@ struct Args {
   int32_t* piv_row;
   int32_t* piv_col;
   uint64_t spin_ticks;  // time-out of one spin wait, in s_memrealtime ticks
+  uint64_t* prof;       // optional per-strip timestamps (NULL = off)
 };
 
-__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_dev32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev32(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// every store this wave issued has been acknowledged
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Spin (thread 0 only) until *p >= target; false on time-out or abort.
+// Spin (one thread) until *p >= target; false on time-out or abort.
 __device__ bool spin_until(const uint32_t* p, uint32_t target, const Args& a) {
-  uint64_t t0 = wall_clock64();
+  const uint64_t t0 = wall_clock64();
   for (;;) {
-    if (ld_acquire(p) >= target) return true;
+    if (ld_dev(p) >= target) return true;
     if (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     if (wall_clock64() - t0 > a.spin_ticks) {
       zx_dev_fail(a.status, ZX_EDEVICE);
@@ -109,170 +144,232 @@ __device__ bool spin_until(const uint32_t* p, uint32_t target, const Args& a) {
 }
 
 __global__ void rref_init(Ctl* ctl, int32_t* status) {
-  int t = threadIdx.x;
+  const int t = threadIdx.x;
   uint32_t* c = (uint32_t*)ctl;
   for (int i = t; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
   if (t == 0) *status = 0;
 }
 
 struct Smem {
-  // fixed part (after the columns)
-  uint64_t tab[16 * 16];   // nibble tables of the column being updated
-  uint64_t orig[64];       // original pivot words of the column
-  uint64_t pp[64];         // reduced pivot words
-  uint64_t Q[64];          // reduced pivot word by strip bit position (0 = no pivot)
+  uint64_t tab[MAX_CW][256];   // nibble tables per owned column
+  uint64_t orig[MAX_CW][64];   // original pivot words per column
+  uint64_t pp[MAX_CW][64];     // reduced pivot words per column
+  uint64_t Q[MAX_CW][64];      // reduced pivot word by strip bit position
   uint64_t L[64];
+  uint64_t cmask[MAX_SL][NWAVE];  // candidate ballots by (slice, wave)
+  uint64_t pivmask;
   int32_t rows[64];
   int32_t bits[64];
   int32_t cand[NCAND];
-  int32_t scan[BS / 64 + 1];
-  int32_t k, last, strip, ncand, total, flag, pad[2];
-  uint64_t pivmask;
+  int32_t prow[64];            // sorted pivot list of a multi-pass strip
+  int32_t pcol[64];
+  int32_t k, last, strip, total, flag, cnt, pad[2];
 };
 
-// Block-wide: first NCAND rows that are non-pivot and non-zero in column
-// `col`; returns the total number of such rows.
-__device__ int gather_candidates(const uint64_t* col, const uint64_t* pivflag, int m, Smem& S) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int per = (m + BS - 1) / BS;  // contiguous rows per thread (<= 32)
-  const int r0 = tid * per;
-  uint32_t mask = 0;
-  for (int i = 0; i < per; ++i) {
-    int r = r0 + i;
-    if (r < m && !((pivflag[r >> 6] >> (r & 63)) & 1) && col[r] != 0) mask |= 1u << i;
-  }
-  int cnt = __popc(mask);
-  // inclusive scan within the wave
-  int x = cnt;
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) S.scan[wv] = x;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int w = 0; w < BS / 64; ++w) {
-      int v = S.scan[w];
-      S.scan[w] = acc;
-      acc += v;
-    }
-    S.scan[BS / 64] = acc;
-  }
-  __syncthreads();
-  int pos = S.scan[wv] + x - cnt;
-  while (mask && pos < NCAND) {
-    int i = __ffs(mask) - 1;
-    mask &= mask - 1;
-    S.cand[pos++] = r0 + i;
-  }
-  int total = S.scan[BS / 64];
-  __syncthreads();
-  return total;
+__device__ __forceinline__ void prof_mark(const Args& a, int s, int slot) {
+  if (a.prof && s < MAX_STRIPS) st_dev64(&a.prof[(size_t)s * PROF_SLOTS + slot], wall_clock64());
 }
 
-// Wave 0: reduce the candidates of strip `col`; fills S.k, rows, bits, L.
-__device__ void factor_candidates(const uint64_t* col, int nc, Smem& S) {
+__device__ __forceinline__ bool bit_of(const uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1; }
+
+// Candidates in row order from per-thread flags (bit i = row tid + i*BS):
+// the first NCAND go to S.cand, the count of all to S.total.
+__device__ void compact_candidates(uint32_t flags, int nsl, Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = 0; i < nsl; ++i) {
+    const uint64_t b = __ballot((flags >> i) & 1);
+    if (lane == 0) S.cmask[i][wv] = b;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // entries e = i * NWAVE + w are in row order; 64 entries per round
+    const int ne = nsl * NWAVE;
+    int base = 0;
+    for (int e0 = 0; e0 < ne; e0 += 64) {
+      const int e = e0 + lane;
+      const uint64_t msk = e < ne ? S.cmask[e / NWAVE][e % NWAVE] : 0;
+      const int c = __popcll(msk);
+      int x = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      int pos = base + x - c;
+      uint64_t mm = msk;
+      while (mm && pos < NCAND) {
+        const int b = __ffsll((long long)mm) - 1;
+        mm &= mm - 1;
+        S.cand[pos++] = (e / NWAVE) * BS + (e % NWAVE) * 64 + b;
+      }
+      base += __shfl(x, 63);
+    }
+    if (lane == 0) S.total = base;
+  }
+  __syncthreads();
+}
+
+// Value of lane `src` (wave-uniform) in every lane, through scalar registers.
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Wave 0: reduce the candidates (S.cand, min(S.total, NCAND) of them) of the
+// strip column `col`; fills S.k, rows, bits, L, pivmask.  All bookkeeping
+// stays in registers during the bit loop.
+__device__ void factor_candidates(const uint64_t* col, Smem& S) {
   const int lane = threadIdx.x & 63;
+  const int nc = S.total < NCAND ? S.total : NCAND;
   uint64_t w0 = lane < nc ? col[S.cand[lane]] : 0;
   uint64_t w1 = 64 + lane < nc ? col[S.cand[64 + lane]] : 0;
   uint64_t L0 = 0, L1 = 0;
-  bool p0 = false, p1 = false;
-  int j0 = -1, j1 = -1;
+  uint64_t P0 = 0, P1 = 0;  // lanes already chosen as pivots (uniform)
+  uint64_t pm = 0;          // pivot bit positions (uniform)
+  int j0 = -1, j1 = -1, b0 = 0, b1 = 0;
   int k = 0;
-  for (int b = 0; b < 64 && k < 64; ++b) {
+  const uint64_t me = 1ull << lane;
+  for (int b = 0; b < 64; ++b) {
     const uint64_t bit = 1ull << b;
-    uint64_t bal0 = __ballot(!p0 && (w0 & bit));
-    uint64_t bal1 = __ballot(!p1 && (w1 & bit));
-    if ((bal0 | bal1) == 0) continue;
-    const bool hi = bal0 == 0;
-    const int src = __ffsll((long long)(hi ? bal1 : bal0)) - 1;
-    const uint64_t pw = __shfl(hi ? w1 : w0, src);
-    const uint64_t pl = __shfl(hi ? L1 : L0, src) | (1ull << k);
-    const bool me0 = !hi && lane == src, me1 = hi && lane == src;
-    if (me0) { p0 = true; j0 = k; L0 |= 1ull << k; }
-    if (me1) { p1 = true; j1 = k; L1 |= 1ull << k; }
-    if ((w0 & bit) && !me0) { w0 ^= pw; L0 ^= pl; }
-    if ((w1 & bit) && !me1) { w1 ^= pw; L1 ^= pl; }
-    if (lane == 0) {
-      S.rows[k] = S.cand[(hi ? 64 : 0) + src];
-      S.bits[k] = b;
+    const uint64_t h0 = __ballot((w0 & bit) != 0);
+    const uint64_t h1 = __ballot((w1 & bit) != 0);
+    const uint64_t c0 = h0 & ~P0, c1 = h1 & ~P1;
+    if ((c0 | c1) == 0) continue;
+    if (c0) {
+      const int src = __builtin_ctzll(c0);
+      const uint64_t pw = bcast64(w0, src);
+      const uint64_t pl = bcast64(L0, src) | (1ull << k);
+      P0 |= 1ull << src;
+      if (lane == src) { j0 = k; b0 = b; L0 = pl; }
+      if ((h0 & ~(1ull << src)) & me) { w0 ^= pw; L0 ^= pl; }
+      if (h1 & me) { w1 ^= pw; L1 ^= pl; }
+    } else {
+      const int src = __builtin_ctzll(c1);
+      const uint64_t pw = bcast64(w1, src);
+      const uint64_t pl = bcast64(L1, src) | (1ull << k);
+      P1 |= 1ull << src;
+      if (lane == src) { j1 = k; b1 = b; L1 = pl; }
+      if (h0 & me) { w0 ^= pw; L0 ^= pl; }
+      if ((h1 & ~(1ull << src)) & me) { w1 ^= pw; L1 ^= pl; }
     }
-    ++k;
+    pm |= bit;
+    if (++k == 64) break;
   }
-  if (j0 >= 0) S.L[j0] = L0;
-  if (j1 >= 0) S.L[j1] = L1;
-  if (lane == 0) S.k = k;
-}
-
-// Apply the pass held in S (k, rows, bits, L, pivmask) to one LDS column,
-// with multipliers taken from snapshot `snap` (strip words before the pass).
-__device__ void apply_pass(uint64_t* col, const uint64_t* snap, int m, Smem& S) {
-  const int tid = threadIdx.x;
-  const int k = S.k;
-  if (tid < k) S.orig[tid] = col[S.rows[tid]];
-  if (tid < 64) S.Q[tid] = 0;
-  __syncthreads();
-  if (tid < k) {
-    uint64_t Lm = S.L[tid], x = 0;
-    while (Lm) {
-      int i = __ffsll((long long)Lm) - 1;
-      Lm &= Lm - 1;
-      x ^= S.orig[i];
-    }
-    S.pp[tid] = x;
-    S.Q[S.bits[tid]] = x;
-  }
-  __syncthreads();
-  if (tid < 256) {
-    const int t = tid >> 4, e = tid & 15;
-    uint64_t v = 0;
-    for (int i = 0; i < 4; ++i)
-      if ((e >> i) & 1) v ^= S.Q[4 * t + i];
-    S.tab[tid] = v;
-  }
-  __syncthreads();
-  const uint64_t pm = S.pivmask;
-  for (int r = tid; r < m; r += BS) {
-    uint64_t mr = snap[r] & pm;
-    if (mr) {
-      uint64_t acc = 0;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) acc ^= S.tab[16 * t + ((mr >> (4 * t)) & 15)];
-      col[r] ^= acc;
-    }
-  }
-  __syncthreads();
-  if (tid < k) col[S.rows[tid]] = S.pp[tid];
-  __syncthreads();
-}
-
-__device__ void load_record(const PassRec* rec, Smem& S) {
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    S.k = rec->k;
-    S.last = rec->last;
-    S.strip = rec->strip;
-  }
-  __syncthreads();
-  const int k = S.k;
-  if (tid < k) {
-    S.rows[tid] = rec->rows[tid];
-    S.bits[tid] = rec->bits[tid];
-    S.L[tid] = rec->L[tid];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint64_t pm = 0;
-    for (int j = 0; j < k; ++j) pm |= 1ull << S.bits[j];
+  if (j0 >= 0) { S.L[j0] = L0; S.rows[j0] = S.cand[lane]; S.bits[j0] = b0; }
+  if (j1 >= 0) { S.L[j1] = L1; S.rows[j1] = S.cand[64 + lane]; S.bits[j1] = b1; }
+  if (lane == 0) {
+    S.k = k;
     S.pivmask = pm;
   }
+}
+
+// Reduced pivot words and nibble tables of `nc` columns for the pass in S.
+__device__ void make_tables(uint64_t* const* cols, int nc, Smem& S) {
+  const int tid = threadIdx.x, k = S.k;
+  for (int x = tid; x < nc * 64; x += BS) {
+    const int j = x >> 6, t = x & 63;
+    S.Q[j][t] = 0;
+    if (t < k) S.orig[j][t] = cols[j][S.rows[t]];
+  }
+  __syncthreads();
+  for (int x = tid; x < nc * 64; x += BS) {
+    const int j = x >> 6, t = x & 63;
+    if (t < k) {
+      const uint64_t Lm = S.L[t];
+      uint64_t v = 0;
+#pragma unroll 16
+      for (int i = 0; i < 64; ++i) v ^= ((Lm >> i) & 1) ? S.orig[j][i] : 0;
+      S.pp[j][t] = v;
+      S.Q[j][S.bits[t]] = v;
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < nc * 256; x += BS) {
+    const int j = x >> 8, e = x & 255, t = e >> 4, sel = e & 15;
+    uint64_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if ((sel >> i) & 1) v ^= S.Q[j][4 * t + i];
+    S.tab[j][e] = v;
+  }
   __syncthreads();
 }
 
-__device__ void mark_pivots(uint64_t* pivflag, Smem& S) {
+__device__ __forceinline__ uint64_t lookup16(const uint64_t* tab, uint64_t mr) {
+  uint64_t acc = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc ^= tab[16 * t + ((mr >> (4 * t)) & 15)];
+  return acc;
+}
+
+// Apply the pass in S to `nc` LDS columns.  Multipliers: strip words of every
+// row before the pass, from the global snapshot `snap` (consumers) or from
+// the LDS strip column `strip` (the owner; the strip column may be one of
+// `cols`: each row's multiplier is read before that row is updated).
+// newpiv must hold this pass's pivot rows.  With fuse >= 0, column cols[fuse]
+// is also written to `snap_out` and its non-pivot non-zero rows after the
+// update are returned as candidate flags (bit i = row tid + i*BS).  `pre`
+// (optional) holds the first GROUP multipliers already loaded.
+// On return pivot rows hold P' and pivflag includes them.
+__device__ uint32_t apply_record(uint64_t* const* cols, int nc, const uint64_t* snap, const uint64_t* strip,
+                                 int m, uint64_t* pivflag, uint64_t* newpiv, int fuse, uint64_t* snap_out,
+                                 const uint64_t* pre, Smem& S) {
   const int tid = threadIdx.x;
-  if (tid < S.k) atomicOr((unsigned long long*)&pivflag[S.rows[tid] >> 6], 1ull << (S.rows[tid] & 63));
+  const int nsl = (m + BS - 1) / BS;
+  const uint64_t pm = S.pivmask;
+  uint32_t flags = 0;
+  for (int i0 = 0; i0 < nsl; i0 += GROUP) {
+    uint64_t mv[GROUP];
+#pragma unroll
+    for (int q = 0; q < GROUP; ++q) {
+      const int r = (i0 + q) * BS + tid;
+      if (i0 == 0 && pre) mv[q] = pre[q];
+      else if (r >= m) mv[q] = 0;
+      else mv[q] = snap ? ld_dev64(&snap[r]) : strip[r];
+    }
+#pragma unroll
+    for (int q = 0; q < GROUP; ++q) {
+      const int i = i0 + q;
+      const int r = i * BS + tid;
+      if (r >= m) continue;
+      const uint64_t mr = mv[q] & pm;
+      const bool np = bit_of(newpiv, r);
+      for (int j = 0; j < nc; ++j) {
+        uint64_t v = cols[j][r];
+        if (mr && !np) {
+          v ^= lookup16(S.tab[j], mr);
+          cols[j][r] = v;
+        }
+        if (j == fuse && !np) {
+          st_dev64(&snap_out[r], v);
+          if (v != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int k = S.k;
+  for (int x = tid; x < nc * 64; x += BS) {
+    const int j = x >> 6, t = x & 63;
+    if (t < k) {
+      cols[j][S.rows[t]] = S.pp[j][t];
+      if (j == fuse) st_dev64(&snap_out[S.rows[t]], S.pp[j][t]);
+    }
+  }
+  if (tid < k) {
+    const int r = S.rows[tid];
+    atomicOr((unsigned long long*)&pivflag[r >> 6], 1ull << (r & 63));
+    atomicAnd((unsigned long long*)&newpiv[r >> 6], ~(1ull << (r & 63)));
+  }
+  __syncthreads();
+  return flags;
+}
+
+__device__ void mark_newpiv(uint64_t* newpiv, Smem& S) {
+  if ((int)threadIdx.x < S.k) {
+    const int r = S.rows[threadIdx.x];
+    atomicOr((unsigned long long*)&newpiv[r >> 6], 1ull << (r & 63));
+  }
   __syncthreads();
 }
 
@@ -281,129 +378,207 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   const int tid = threadIdx.x;
   const int g = blockIdx.x, G = gridDim.x;
   const int m = a.m;
+  const int nsl = (m + BS - 1) / BS;
   const int nown = (a.nw - g + G - 1) / G;  // columns owned: g, g+G, ...
-  uint64_t* cols = smem;                                  // [cw][m]
-  uint64_t* pivflag = cols + (size_t)a.cw * m;            // [ceil(m/64)]
   const int pw = (m + 63) / 64;
-  Smem& S = *reinterpret_cast<Smem*>(pivflag + pw);
+  uint64_t* cols = smem;                              // [cw][m]
+  uint64_t* pivflag = cols + (size_t)a.cw * m;        // [pw]
+  uint64_t* newpiv = pivflag + pw;                    // [pw]
+  Smem& S = *reinterpret_cast<Smem*>(newpiv + pw);
 
-  // load owned columns (bits >= n_cols masked off)
   for (int j = 0; j < nown; ++j) {
     const int c = g + j * G;
     const int tail = a.n_cols - 64 * c;
     const uint64_t cm = tail >= 64 ? ~0ull : ((1ull << tail) - 1);
     for (int r = tid; r < m; r += BS) cols[(size_t)j * m + r] = a.A[(size_t)r * a.ld + c] & cm;
   }
-  for (int i = tid; i < pw; i += BS) pivflag[i] = 0;
+  for (int i = tid; i < pw; i += BS) {
+    pivflag[i] = 0;
+    newpiv[i] = 0;
+  }
   __syncthreads();
 
-  uint32_t seq = 0;  // next record index
+  uint32_t seq = 0;      // next record index
   int rank = 0;
   bool ok = true;
+  bool prepared = false;  // snapshot of the next own strip written, candidates in S
   for (int s = 0; s < a.nw && rank < m && ok; ++s) {
     const int owner = s % G;
     if (owner == g) {
       // ---------------- produce strip s ----------------
-      uint64_t* col = cols + (size_t)(s / G) * m;
+      const int js = s / G;
+      uint64_t* col = cols + (size_t)js * m;
       const int rank0 = rank;
-      bool published_any = false;
+      bool multi = false;
+      if (tid == 0) prof_mark(a, s, 0);
       for (;;) {
-        const int total = gather_candidates(col, pivflag, m, S);
-        const int nc = total < NCAND ? total : NCAND;
-        int k = 0, last = 1;
-        if (total > 0) {
-          if (tid < 64) factor_candidates(col, nc, S);
-          __syncthreads();
-          k = S.k;
-          last = (k == 64 || total <= NCAND) ? 1 : 0;
-        } else if (published_any) {
-          // residual pass found nothing: strip ends with an empty marker
-          k = 0;
-          last = 1;
-        } else {
-          k = 0;
-          last = 1;
-        }
-        // pivot list entries (global), sorted by column at the strip end
-        if (tid < k) {
-          a.piv_row[rank + tid] = S.rows[tid];
-          a.piv_col[rank + tid] = 64 * s + S.bits[tid];
-        }
-        __syncthreads();
-        if (last && published_any && tid == 0) {
-          // multi-pass strip: sort this strip's pivots by column
-          const int lo = rank0, hi = rank + k;
-          for (int i = lo + 1; i < hi; ++i) {
-            int kc = a.piv_col[i], kr = a.piv_row[i], j = i - 1;
-            while (j >= lo && a.piv_col[j] > kc) {
-              a.piv_col[j + 1] = a.piv_col[j];
-              a.piv_row[j + 1] = a.piv_row[j];
-              --j;
-            }
-            a.piv_col[j + 1] = kc;
-            a.piv_row[j + 1] = kr;
-          }
-        }
-        // wait until the ring slot is free
         const int slot = seq % RING;
-        if (tid == 0) {
-          const uint32_t need = (seq / RING) * (uint32_t)(G - 1);
-          S.flag = spin_until(&a.ctl->ack[slot], need, a) ? 1 : 0;
-        }
-        __syncthreads();
-        if (!S.flag) { ok = false; break; }
         PassRec* rec = a.recs + slot;
         uint64_t* snap = a.snaps + (size_t)slot * m;
-        if (k > 0)
-          for (int r = tid; r < m; r += BS) snap[r] = col[r];
+        if (!prepared) {
+          if (tid == 0) {
+            const uint32_t need = (seq / RING) * (uint32_t)(G - 1);
+            S.flag = spin_until(&a.ctl->ack[slot], need, a) ? 1 : 0;
+          }
+          __syncthreads();
+          if (!S.flag) { ok = false; break; }
+          uint32_t flags = 0;
+          for (int i = 0; i < nsl; ++i) {
+            const int r = i * BS + tid;
+            if (r < m) {
+              const uint64_t v = col[r];
+              st_dev64(&snap[r], v);
+              if (v != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
+            }
+          }
+          compact_candidates(flags, nsl, S);
+        }
+        prepared = false;
+        if (tid == 0) prof_mark(a, s, 1);
+        const int total = S.total;
+        if (tid < 64) {
+          if (total > 0) factor_candidates(col, S);
+          else if (tid == 0) { S.k = 0; S.pivmask = 0; }
+        }
+        __syncthreads();
+        if (tid == 0) prof_mark(a, s, 6);
+        const int k = S.k;
+        const int last = (total == 0 || k == 64 || total <= NCAND) ? 1 : 0;
         if (tid < k) {
-          rec->rows[tid] = S.rows[tid];
-          rec->bits[tid] = S.bits[tid];
-          rec->L[tid] = S.L[tid];
+          st_dev32(&rec->rows[tid], S.rows[tid]);
+          st_dev32(&rec->bits[tid], S.bits[tid]);
+          st_dev64(&rec->L[tid], S.L[tid]);
+          st_dev32(&a.piv_row[rank + tid], S.rows[tid]);
+          st_dev32(&a.piv_col[rank + tid], 64 * s + S.bits[tid]);
         }
         if (tid == 0) {
-          rec->strip = s;
-          rec->k = k;
-          rec->last = last;
-          S.k = k;
-          S.last = last;
-          uint64_t pm = 0;
-          for (int j = 0; j < k; ++j) pm |= 1ull << S.bits[j];
-          S.pivmask = pm;
+          st_dev32(&rec->strip, s);
+          st_dev32(&rec->k, k);
+          st_dev32(&rec->last, last);
+          st_dev64(&rec->pivmask, S.pivmask);
         }
-        __threadfence();
+        if (last && multi && tid == 64) {
+          // multi-pass strip (rare): sort its pivot list by column.  A strip
+          // holds at most 64 pivots; earlier passes' entries are read back,
+          // this pass's come from the factor output.
+          int cnt = 0;
+          for (int i = rank0; i < rank; ++i) {
+            S.prow[cnt] = ld_dev32(&a.piv_row[i]);
+            S.pcol[cnt] = ld_dev32(&a.piv_col[i]);
+            ++cnt;
+          }
+          for (int j = 0; j < k; ++j) {
+            S.prow[cnt] = S.rows[j];
+            S.pcol[cnt] = 64 * s + S.bits[j];
+            ++cnt;
+          }
+          for (int i = 1; i < cnt; ++i) {
+            const int kc = S.pcol[i], kr = S.prow[i];
+            int j = i - 1;
+            while (j >= 0 && S.pcol[j] > kc) {
+              S.pcol[j + 1] = S.pcol[j];
+              S.prow[j + 1] = S.prow[j];
+              --j;
+            }
+            S.pcol[j + 1] = kc;
+            S.prow[j + 1] = kr;
+          }
+          S.cnt = cnt;
+        }
+        wait_stores();
         __syncthreads();
-        if (tid == 0) st_release(&a.ctl->seq, seq + 1);
+        if (last && multi) {
+          if (tid < S.cnt) {
+            st_dev32(&a.piv_row[rank0 + tid], S.prow[tid]);
+            st_dev32(&a.piv_col[rank0 + tid], S.pcol[tid]);
+          }
+          wait_stores();
+          __syncthreads();
+        }
+        if (tid == 0) {
+          st_dev(&a.ctl->seq, seq + 1);
+          prof_mark(a, s, 2);
+        }
         ++seq;
-        published_any = true;
         if (k > 0) {
-          // own columns c >= s (this strip first)
-          for (int j = s / G; j < nown; ++j) apply_pass(cols + (size_t)j * m, snap, m, S);
-          mark_pivots(pivflag, S);
+          uint64_t* list[MAX_CW];
+          int nc = 0;
+          for (int j = js; j < nown; ++j) list[nc++] = cols + (size_t)j * m;
+          mark_newpiv(newpiv, S);
+          make_tables(list, nc, S);
+          apply_record(list, nc, nullptr, col, m, pivflag, newpiv, -1, nullptr, nullptr, S);
           rank += k;
         }
+        if (tid == 0) prof_mark(a, s, 3);
         if (last) break;
+        multi = true;
       }
     } else {
       // ---------------- consume strip s ----------------
+      const bool own_next = (s + 1 < a.nw) && ((s + 1) % G) == g;
       for (;;) {
         const int slot = seq % RING;
         if (tid == 0) S.flag = spin_until(&a.ctl->seq, seq + 1, a) ? 1 : 0;
         __syncthreads();
         if (!S.flag) { ok = false; break; }
         const PassRec* rec = a.recs + slot;
-        load_record(rec, S);
         const uint64_t* snap = a.snaps + (size_t)slot * m;
-        const int k = S.k, last = S.last;
-        if (k > 0) {
-          // owned columns with index > s
-          int j0 = (s - g) >= 0 ? (s - g) / G + 1 : 0;
-          for (int j = j0; j < nown; ++j) apply_pass(cols + (size_t)j * m, snap, m, S);
-          mark_pivots(pivflag, S);
-          rank += k;
+        // the record and the first multipliers are loaded together
+        uint64_t pre[GROUP];
+#pragma unroll
+        for (int q = 0; q < GROUP; ++q) {
+          const int r = q * BS + tid;
+          pre[q] = r < m ? ld_dev64(&snap[r]) : 0;
+        }
+        if (tid == 0) {
+          S.k = ld_dev32(&rec->k);
+          S.last = ld_dev32(&rec->last);
+          S.pivmask = ld_dev64(&rec->pivmask);
+        }
+        if (tid < 64) {
+          S.rows[tid] = ld_dev32(&rec->rows[tid]);
+          S.bits[tid] = ld_dev32(&rec->bits[tid]);
+          S.L[tid] = ld_dev64(&rec->L[tid]);
         }
         __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int k = S.k, last = S.last;
+        const bool fused = own_next && last && k > 0;
+        if (tid == 0 && own_next && last) prof_mark(a, s, 4);
+        if (fused) {
+          const uint32_t nseq = seq + 1;
+          if (tid == 0) {
+            const uint32_t need = (nseq / RING) * (uint32_t)(G - 1);
+            S.flag = spin_until(&a.ctl->ack[nseq % RING], need, a) ? 1 : 0;
+          }
+          __syncthreads();
+          if (!S.flag) { ok = false; break; }
+        }
+        if (k > 0) {
+          // owned columns with index > s
+          uint64_t* list[MAX_CW];
+          int nc = 0, fuse = -1;
+          for (int j = (s - g) >= 0 ? (s - g) / G + 1 : 0; j < nown; ++j) {
+            if (fused && g + j * G == s + 1) fuse = nc;
+            list[nc++] = cols + (size_t)j * m;
+          }
+          rank += k;  // every workgroup tracks the rank (the loops end together)
+          if (nc > 0) {
+            mark_newpiv(newpiv, S);
+            make_tables(list, nc, S);
+            uint64_t* snap_out = a.snaps + (size_t)((seq + 1) % RING) * m;
+            const uint32_t flags = apply_record(list, nc, snap, nullptr, m, pivflag, newpiv, fuse,
+                                                snap_out, pre, S);
+            if (fused) {
+              compact_candidates(flags, nsl, S);
+              prepared = true;
+            }
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (own_next && last) prof_mark(a, s, 5);
+        }
         ++seq;
         if (last) break;
       }
@@ -411,19 +586,17 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   }
   if (!ok) return;
   // ---------------- write the result ----------------
-  __threadfence();
-  __syncthreads();
   for (int j = 0; j < nown; ++j) {
     const int c = g + j * G;
     const uint64_t* col = cols + (size_t)j * m;
     for (int i = tid; i < m; i += BS) {
       uint64_t v = 0;
-      if (i < rank) v = col[a.piv_row[i]];
+      if (i < rank) v = col[ld_dev32(&a.piv_row[i])];
       a.R[(size_t)i * a.ld + c] = v;
     }
   }
   if (g == 0) {
-    for (int i = tid; i < m; i += BS) a.piv_dev[i] = i < rank ? a.piv_col[i] : -1;
+    for (int i = tid; i < m; i += BS) a.piv_dev[i] = i < rank ? ld_dev32(&a.piv_col[i]) : -1;
     if (tid == 0) *a.rank_dev = rank;
   }
 }
@@ -442,7 +615,7 @@ int co_resident_blocks(size_t lds) {
 }
 
 size_t smem_bytes(int m, int cw) {
-  return (size_t)cw * m * 8 + (size_t)((m + 63) / 64) * 8 + sizeof(Smem);
+  return (size_t)cw * m * 8 + 2 * (size_t)((m + 63) / 64) * 8 + sizeof(Smem);
 }
 
 }  // namespace
@@ -492,7 +665,7 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
     zx_set_error("no HIP device");
     return ZX_EDEVICE;
   }
-  // choose columns per workgroup so that the grid is co-resident
+  // columns per workgroup: the smallest count whose grid is co-resident
   int cw = 1, G = 0;
   size_t lds = 0;
   for (cw = 1; cw <= MAX_CW; ++cw) {
@@ -525,6 +698,8 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
   a.piv_row = (int32_t*)(base + W.piv_row);
   a.piv_col = (int32_t*)(base + W.piv_col);
   a.spin_ticks = 100000000ull * 5;  // 5 s at the 100 MHz real-time counter
+  static const bool prof_on = getenv("ZX_RREF_PROFILE") && getenv("ZX_RREF_PROFILE")[0] == '1';
+  a.prof = prof_on ? (uint64_t*)(base + W.prof) : nullptr;
   hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.status);
   ZX_HIP(hipGetLastError());
   void* args[] = {&a};
