@@ -3,27 +3,29 @@
 //
 // Method.  Gauss-Jordan elimination over F2 (the paper keeps a linearly
 // independent basis of a binary matrix this way; detectors/observables
-// section, after equation detector_sampling), organised by 64-column word
-// strips.  For strip s:
-//   1. the workgroup that owns word column s picks up to 128 candidate rows
-//      (not yet pivots, non-zero in the strip) and reduces them in one
-//      wavefront: for each bit b a ballot finds the first candidate holding
-//      b, its word is broadcast through scalar registers and XORed into every
-//      other candidate holding b.  This yields up to 64 pivot rows, their bit
-//      positions and, per pivot, a 64-bit mask L of the ORIGINAL pivot rows
-//      that combine into the reduced pivot row;
-//   2. it publishes that "pass" (rows, bits, masks) plus a snapshot of its
-//      column through a ring in the workspace;
-//   3. every workgroup applies the pass to each of its columns c > s:
-//      reduced pivot words P'_j = XOR of the L_j-selected original pivot
-//      words; every other row r gets the XOR of P' over the pivot bits set in
-//      its strip word (Four-Russians: 16 tables of 16 nibble combinations,
-//      conflict-free in LDS), and pivot rows become P'.
-// The owner of strip s + 1 writes the snapshot and collects the candidates of
-// its strip while it applies the last pass of strip s, so its factorisation
+// section, after equation detector_sampling), organised by 32-column strips
+// (half a word column; both halves of a word column belong to the same
+// workgroup).  For strip t:
+//   1. its owner picks up to 64 candidate rows (not yet pivots, non-zero in
+//      the strip) and reduces their 32-bit strip words in one wavefront: for
+//      each bit b a ballot finds the first candidate holding b, its word is
+//      broadcast through scalar registers and XORed into every other
+//      candidate holding b.  This gives up to 32 pivot rows, their bit
+//      positions and, per pivot, a 32-bit mask L of the ORIGINAL pivot rows
+//      that combine into the reduced pivot row.  64 random rows have rank 32
+//      with probability 1 - 2^-32;
+//   2. the owner publishes that "pass" (rows, bits, masks) and a snapshot of
+//      the strip word of every row through a ring in the workspace;
+//   3. every workgroup applies the pass to each of its word columns at or
+//      after the strip: reduced pivot words P'_j = XOR of the L_j-selected
+//      original pivot words; every other row r gets the XOR of P' over the
+//      pivot bits set in its snapshot word (Four-Russians: 8 tables of 16
+//      nibble combinations, conflict-free in LDS); pivot rows become P'.
+// The owner of strip t + 1 writes that strip's snapshot and collects its
+// candidates while it applies the last pass of strip t, so its reduction
 // starts as soon as that pass is applied.
 //
-// If a pass found fewer than 64 pivots while more non-zero rows existed than
+// If a pass found fewer than 32 pivots while more non-zero rows existed than
 // candidates, the owner runs further passes on the residual rows.  Pivot
 // columns found are always leading bits of row-space vectors and a strip ends
 // only when every non-pivot row is zero in it, so the final rows are the
@@ -47,24 +49,24 @@ namespace {
 
 constexpr int BS = 512;           // threads per workgroup
 constexpr int NWAVE = BS / 64;
+constexpr int SW = 32;            // columns per strip
 constexpr int RING = 8;           // pass records in flight
-constexpr int NCAND = 128;        // candidate rows per pass
+constexpr int NCAND = 64;         // candidate rows per pass (one per lane)
 constexpr int MAX_M = 16384;      // rows that fit one column per workgroup in LDS
 constexpr int MAX_SL = MAX_M / BS;  // row slices per thread
 constexpr int MAX_CW = 4;         // word columns per workgroup
-constexpr int MAX_STRIPS = 4096;  // strips with profile slots
+constexpr int MAX_STRIPS = 8192;  // strips with profile slots
 constexpr int PROF_SLOTS = 8;     // timestamps per strip (profiling only)
 constexpr int GROUP = 8;          // row slices whose multipliers are loaded together
 
 struct PassRec {
   int32_t strip;
-  int32_t k;       // pivots in this pass (0 for an end-of-strip marker)
-  int32_t last;    // strip finished with this record
-  int32_t pad0;
-  uint64_t pivmask;  // strip bit positions that hold pivots
-  int32_t rows[64];
-  int32_t bits[64];
-  uint64_t L[64];
+  int32_t k;         // pivots in this pass (0 for an end-of-strip marker)
+  int32_t last;      // strip finished with this record
+  uint32_t pivmask;  // strip bit positions that hold pivots
+  int32_t rows[SW];
+  int32_t bits[SW];
+  uint32_t L[SW];
 };
 
 struct Ctl {
@@ -83,7 +85,7 @@ WsLayout ws_layout(int m) {
   size_t o = 256;  // ZxWsHeader
   L.ctl = o;     o += (sizeof(Ctl) + 255) & ~size_t(255);
   L.recs = o;    o += ((sizeof(PassRec) * RING) + 255) & ~size_t(255);
-  L.snaps = o;   o += (((size_t)m * 8 * RING) + 255) & ~size_t(255);
+  L.snaps = o;   o += (((size_t)m * 4 * RING) + 255) & ~size_t(255);
   L.piv_row = o; o += (((size_t)m * 4) + 255) & ~size_t(255);
   L.piv_col = o; o += (((size_t)m * 4) + 255) & ~size_t(255);
   L.prof = o;    o += ((size_t)MAX_STRIPS * PROF_SLOTS * 8 + 255) & ~size_t(255);
@@ -94,14 +96,14 @@ WsLayout ws_layout(int m) {
 struct Args {
   const uint64_t* A;
   uint64_t* R;
-  int32_t m, n_cols, nw, cw;
+  int32_t m, n_cols, nw, cw, nstrips;
   int64_t ld;
   int32_t* rank_dev;
   int32_t* piv_dev;
   int32_t* status;
   Ctl* ctl;
   PassRec* recs;
-  uint64_t* snaps;
+  uint32_t* snaps;
   int32_t* piv_row;
   int32_t* piv_col;
   uint64_t spin_ticks;  // time-out of one spin wait, in s_memrealtime ticks
@@ -113,9 +115,6 @@ __device__ __forceinline__ uint32_t ld_dev(const uint32_t* p) {
 }
 __device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -151,19 +150,21 @@ __global__ void rref_init(Ctl* ctl, int32_t* status) {
 }
 
 struct Smem {
-  uint64_t tab[MAX_CW][256];   // nibble tables per owned column
-  uint64_t orig[MAX_CW][64];   // original pivot words per column
-  uint64_t pp[MAX_CW][64];     // reduced pivot words per column
-  uint64_t Q[MAX_CW][64];      // reduced pivot word by strip bit position
-  uint64_t L[64];
-  uint64_t cmask[MAX_SL][NWAVE];  // candidate ballots by (slice, wave)
-  uint64_t pivmask;
-  int32_t rows[64];
-  int32_t bits[64];
+  uint64_t tab[MAX_CW][128];   // 8 nibble tables of reduced pivot words, per column
+  uint64_t otab[MAX_CW][128];  // 8 nibble tables of original pivot words, per column
+  uint64_t orig[MAX_CW][SW];
+  uint64_t pp[MAX_CW][SW];
+  uint64_t Q[MAX_CW][SW];      // reduced pivot word by strip bit position
+  uint64_t cmask[MAX_SL * NWAVE];  // candidate ballots by (slice, wave) = row order
+  int32_t cpre[MAX_SL * NWAVE];    // exclusive prefix of their popcounts
+  uint32_t L[SW];
+  int32_t rows[SW];
+  int32_t bits[SW];
   int32_t cand[NCAND];
-  int32_t prow[64];            // sorted pivot list of a multi-pass strip
-  int32_t pcol[64];
-  int32_t k, last, strip, total, flag, cnt, pad[2];
+  int32_t prow[SW];            // sorted pivot list of a multi-pass strip
+  int32_t pcol[SW];
+  uint32_t pivmask;
+  int32_t k, last, total, flag, cnt, efirst, pad;
 };
 
 __device__ __forceinline__ void prof_mark(const Args& a, int s, int slot) {
@@ -172,91 +173,111 @@ __device__ __forceinline__ void prof_mark(const Args& a, int s, int slot) {
 
 __device__ __forceinline__ bool bit_of(const uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1; }
 
+// Position of the n-th (0-based) set bit of x; x must have more than n bits.
+__device__ __forceinline__ int select_bit(uint64_t x, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t lowmask = (w == 64) ? ~0ull : ((1ull << w) - 1);
+    const int c = __popcll(x & lowmask);
+    if (n >= c) {
+      n -= c;
+      x >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// Exclusive prefix sum over the wavefront of values in [0, 127] and their
+// total, from one ballot per bit and the lane-prefix bit count (v_mbcnt).
+__device__ __forceinline__ void wave_exclusive_scan7(int v, int& ex, int& tot) {
+  ex = 0;
+  tot = 0;
+#pragma unroll
+  for (int bit = 0; bit < 7; ++bit) {
+    const uint64_t b = __ballot((v >> bit) & 1);
+    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
+    ex += below << bit;
+    tot += __popcll(b) << bit;
+  }
+}
+
 // Candidates in row order from per-thread flags (bit i = row tid + i*BS):
 // the first NCAND go to S.cand, the count of all to S.total.
 __device__ void compact_candidates(uint32_t flags, int nsl, Smem& S) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = 0; i < nsl; ++i) {
     const uint64_t b = __ballot((flags >> i) & 1);
-    if (lane == 0) S.cmask[i][wv] = b;
+    if (lane == 0) S.cmask[i * NWAVE + wv] = b;
   }
   __syncthreads();
   if (tid < 64) {
-    // entries e = i * NWAVE + w are in row order; 64 entries per round
     const int ne = nsl * NWAVE;
-    int base = 0;
+    int base = 0, efirst = -1;
     for (int e0 = 0; e0 < ne; e0 += 64) {
       const int e = e0 + lane;
-      const uint64_t msk = e < ne ? S.cmask[e / NWAVE][e % NWAVE] : 0;
+      const uint64_t msk = e < ne ? S.cmask[e] : 0;
       const int c = __popcll(msk);
-      int x = c;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
+      int ex, tot;
+      wave_exclusive_scan7(c, ex, tot);
+      if (e < ne) S.cpre[e] = base + ex;
+      const uint64_t nz = __ballot(c > 0);
+      if (efirst < 0 && nz) efirst = e0 + __builtin_ctzll(nz);
+      base += tot;
+    }
+    // lane p fills candidate slot p: scan entries from the first non-empty one
+    const int p = lane;
+    if (efirst >= 0) {
+      for (int e = efirst; e < ne; ++e) {
+        const int pe = S.cpre[e];
+        if (pe >= NCAND) break;
+        const uint64_t msk = S.cmask[e];
+        const int c = __popcll(msk);
+        if (p >= pe && p < pe + c) S.cand[p] = (e / NWAVE) * BS + (e % NWAVE) * 64 + select_bit(msk, p - pe);
       }
-      int pos = base + x - c;
-      uint64_t mm = msk;
-      while (mm && pos < NCAND) {
-        const int b = __ffsll((long long)mm) - 1;
-        mm &= mm - 1;
-        S.cand[pos++] = (e / NWAVE) * BS + (e % NWAVE) * 64 + b;
-      }
-      base += __shfl(x, 63);
     }
     if (lane == 0) S.total = base;
   }
   __syncthreads();
 }
 
-// Value of lane `src` (wave-uniform) in every lane, through scalar registers.
-__device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Wave 0: reduce the candidates (S.cand, min(S.total, NCAND) of them) of the
-// strip column `col`; fills S.k, rows, bits, L, pivmask.  All bookkeeping
-// stays in registers during the bit loop.
-__device__ void factor_candidates(const uint64_t* col, Smem& S) {
+// Wave 0: reduce the candidates (S.cand, min(S.total, NCAND) of them), using
+// bits [shift, shift + 32) of the LDS column `col`.  Fills S.k, rows, bits,
+// L, pivmask.  The bit loop is unrolled and branch-free: a bit with no
+// candidate is a no-op, every other bit costs one ballot, one s_ff1, two
+// readlanes and a few selects.
+__device__ void factor_candidates(const uint64_t* col, int shift, Smem& S) {
   const int lane = threadIdx.x & 63;
   const int nc = S.total < NCAND ? S.total : NCAND;
-  uint64_t w0 = lane < nc ? col[S.cand[lane]] : 0;
-  uint64_t w1 = 64 + lane < nc ? col[S.cand[64 + lane]] : 0;
-  uint64_t L0 = 0, L1 = 0;
-  uint64_t P0 = 0, P1 = 0;  // lanes already chosen as pivots (uniform)
-  uint64_t pm = 0;          // pivot bit positions (uniform)
-  int j0 = -1, j1 = -1, b0 = 0, b1 = 0;
-  int k = 0;
-  const uint64_t me = 1ull << lane;
-  for (int b = 0; b < 64; ++b) {
-    const uint64_t bit = 1ull << b;
-    const uint64_t h0 = __ballot((w0 & bit) != 0);
-    const uint64_t h1 = __ballot((w1 & bit) != 0);
-    const uint64_t c0 = h0 & ~P0, c1 = h1 & ~P1;
-    if ((c0 | c1) == 0) continue;
-    if (c0) {
-      const int src = __builtin_ctzll(c0);
-      const uint64_t pw = bcast64(w0, src);
-      const uint64_t pl = bcast64(L0, src) | (1ull << k);
-      P0 |= 1ull << src;
-      if (lane == src) { j0 = k; b0 = b; L0 = pl; }
-      if ((h0 & ~(1ull << src)) & me) { w0 ^= pw; L0 ^= pl; }
-      if (h1 & me) { w1 ^= pw; L1 ^= pl; }
-    } else {
-      const int src = __builtin_ctzll(c1);
-      const uint64_t pw = bcast64(w1, src);
-      const uint64_t pl = bcast64(L1, src) | (1ull << k);
-      P1 |= 1ull << src;
-      if (lane == src) { j1 = k; b1 = b; L1 = pl; }
-      if (h0 & me) { w0 ^= pw; L0 ^= pl; }
-      if ((h1 & ~(1ull << src)) & me) { w1 ^= pw; L1 ^= pl; }
-    }
-    pm |= bit;
-    if (++k == 64) break;
+  uint32_t w = lane < nc ? (uint32_t)(col[S.cand[lane]] >> shift) : 0;
+  uint32_t L = 0, pm = 0;
+  uint64_t P = 0;  // lanes already chosen as pivots (uniform)
+  int j = -1, bb = 0, k = 0;
+#pragma unroll
+  for (int b = 0; b < SW; ++b) {
+    const bool mine = (w >> b) & 1;
+    const uint64_t h = __ballot(mine);
+    const uint64_t c = h & ~P;
+    const bool valid = c != 0;
+    const int src = valid ? (int)__builtin_ctzll(c) : 0;
+    const uint32_t pw = __builtin_amdgcn_readlane(w, src);
+    const uint32_t pl = __builtin_amdgcn_readlane(L, src) | (1u << (k & 31));
+    const bool is_src = valid && lane == src;
+    const bool elim = valid && mine && !is_src;
+    w ^= elim ? pw : 0u;
+    L = is_src ? pl : (L ^ (elim ? pl : 0u));
+    j = is_src ? k : j;
+    bb = is_src ? b : bb;
+    P |= valid ? (1ull << src) : 0ull;
+    pm |= valid ? (1u << b) : 0u;
+    k += valid ? 1 : 0;
   }
-  if (j0 >= 0) { S.L[j0] = L0; S.rows[j0] = S.cand[lane]; S.bits[j0] = b0; }
-  if (j1 >= 0) { S.L[j1] = L1; S.rows[j1] = S.cand[64 + lane]; S.bits[j1] = b1; }
+  if (j >= 0) {
+    S.L[j] = L;
+    S.rows[j] = S.cand[lane];
+    S.bits[j] = bb;
+  }
   if (lane == 0) {
     S.k = k;
     S.pivmask = pm;
@@ -266,94 +287,105 @@ __device__ void factor_candidates(const uint64_t* col, Smem& S) {
 // Reduced pivot words and nibble tables of `nc` columns for the pass in S.
 __device__ void make_tables(uint64_t* const* cols, int nc, Smem& S) {
   const int tid = threadIdx.x, k = S.k;
-  for (int x = tid; x < nc * 64; x += BS) {
-    const int j = x >> 6, t = x & 63;
+  for (int x = tid; x < nc * SW; x += BS) {
+    const int j = x / SW, t = x % SW;
     S.Q[j][t] = 0;
-    if (t < k) S.orig[j][t] = cols[j][S.rows[t]];
+    S.orig[j][t] = t < k ? cols[j][S.rows[t]] : 0;
   }
   __syncthreads();
-  for (int x = tid; x < nc * 64; x += BS) {
-    const int j = x >> 6, t = x & 63;
+  for (int x = tid; x < nc * 128; x += BS) {
+    const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
+    uint64_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if ((sel >> i) & 1) v ^= S.orig[j][4 * q + i];
+    S.otab[j][e] = v;
+  }
+  __syncthreads();
+  for (int x = tid; x < nc * SW; x += BS) {
+    const int j = x / SW, t = x % SW;
     if (t < k) {
-      const uint64_t Lm = S.L[t];
+      const uint32_t Lm = S.L[t];
       uint64_t v = 0;
-#pragma unroll 16
-      for (int i = 0; i < 64; ++i) v ^= ((Lm >> i) & 1) ? S.orig[j][i] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v ^= S.otab[j][16 * q + ((Lm >> (4 * q)) & 15)];
       S.pp[j][t] = v;
       S.Q[j][S.bits[t]] = v;
     }
   }
   __syncthreads();
-  for (int x = tid; x < nc * 256; x += BS) {
-    const int j = x >> 8, e = x & 255, t = e >> 4, sel = e & 15;
+  for (int x = tid; x < nc * 128; x += BS) {
+    const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
     uint64_t v = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      if ((sel >> i) & 1) v ^= S.Q[j][4 * t + i];
+      if ((sel >> i) & 1) v ^= S.Q[j][4 * q + i];
     S.tab[j][e] = v;
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ uint64_t lookup16(const uint64_t* tab, uint64_t mr) {
+__device__ __forceinline__ uint64_t lookup8(const uint64_t* tab, uint32_t mr) {
   uint64_t acc = 0;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc ^= tab[16 * t + ((mr >> (4 * t)) & 15)];
+  for (int q = 0; q < 8; ++q) acc ^= tab[16 * q + ((mr >> (4 * q)) & 15)];
   return acc;
 }
 
-// Apply the pass in S to `nc` LDS columns.  Multipliers: strip words of every
-// row before the pass, from the global snapshot `snap` (consumers) or from
-// the LDS strip column `strip` (the owner; the strip column may be one of
-// `cols`: each row's multiplier is read before that row is updated).
-// newpiv must hold this pass's pivot rows.  With fuse >= 0, column cols[fuse]
-// is also written to `snap_out` and its non-pivot non-zero rows after the
-// update are returned as candidate flags (bit i = row tid + i*BS).  `pre`
-// (optional) holds the first GROUP multipliers already loaded.
+// Apply the pass in S to `nc` LDS word columns.  Multipliers (the strip word
+// of every row before the pass) come from the global snapshot `snap`
+// (consumers) or from bits [shift, shift+32) of the LDS column `strip` (the
+// owner; that column may be one of `cols`: each row's multiplier is read
+// before the row is updated).  newpiv must hold this pass's pivot rows.
+// With fuse >= 0, bits [fshift, fshift+32) of column cols[fuse] after the
+// update are written to `snap_out` and the non-pivot rows where they are
+// non-zero are returned as candidate flags (bit i = row tid + i*BS).  `pre`
+// (optional) holds the first GROUP multipliers, already loaded.
 // On return pivot rows hold P' and pivflag includes them.
-__device__ uint32_t apply_record(uint64_t* const* cols, int nc, const uint64_t* snap, const uint64_t* strip,
-                                 int m, uint64_t* pivflag, uint64_t* newpiv, int fuse, uint64_t* snap_out,
-                                 const uint64_t* pre, Smem& S) {
+__device__ uint32_t apply_record(uint64_t* const* cols, int nc, const uint32_t* snap, const uint64_t* strip,
+                                 int shift, int m, uint64_t* pivflag, uint64_t* newpiv, int fuse,
+                                 int fshift, uint32_t* snap_out, const uint32_t* pre, Smem& S) {
   const int tid = threadIdx.x;
   const int nsl = (m + BS - 1) / BS;
-  const uint64_t pm = S.pivmask;
+  const uint32_t pm = S.pivmask;
   uint32_t flags = 0;
   for (int i0 = 0; i0 < nsl; i0 += GROUP) {
-    uint64_t mv[GROUP];
+    uint32_t mv[GROUP];
 #pragma unroll
     for (int q = 0; q < GROUP; ++q) {
       const int r = (i0 + q) * BS + tid;
       if (i0 == 0 && pre) mv[q] = pre[q];
       else if (r >= m) mv[q] = 0;
-      else mv[q] = snap ? ld_dev64(&snap[r]) : strip[r];
+      else mv[q] = snap ? ld_dev(&snap[r]) : (uint32_t)(strip[r] >> shift);
     }
 #pragma unroll
     for (int q = 0; q < GROUP; ++q) {
       const int i = i0 + q;
       const int r = i * BS + tid;
       if (r >= m) continue;
-      const uint64_t mr = mv[q] & pm;
+      const uint32_t mr = mv[q] & pm;
       const bool np = bit_of(newpiv, r);
       for (int j = 0; j < nc; ++j) {
         uint64_t v = cols[j][r];
         if (mr && !np) {
-          v ^= lookup16(S.tab[j], mr);
+          v ^= lookup8(S.tab[j], mr);
           cols[j][r] = v;
         }
         if (j == fuse && !np) {
-          st_dev64(&snap_out[r], v);
-          if (v != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
+          const uint32_t h = (uint32_t)(v >> fshift);
+          st_dev(&snap_out[r], h);
+          if (h != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
         }
       }
     }
   }
   __syncthreads();
   const int k = S.k;
-  for (int x = tid; x < nc * 64; x += BS) {
-    const int j = x >> 6, t = x & 63;
+  for (int x = tid; x < nc * SW; x += BS) {
+    const int j = x / SW, t = x % SW;
     if (t < k) {
       cols[j][S.rows[t]] = S.pp[j][t];
-      if (j == fuse) st_dev64(&snap_out[S.rows[t]], S.pp[j][t]);
+      if (j == fuse) st_dev(&snap_out[S.rows[t]], (uint32_t)(S.pp[j][t] >> fshift));
     }
   }
   if (tid < k) {
@@ -373,13 +405,23 @@ __device__ void mark_newpiv(uint64_t* newpiv, Smem& S) {
   __syncthreads();
 }
 
+// Thread 0 waits until ring slot `slot` may be overwritten by record `idx`.
+__device__ bool wait_slot(uint32_t idx, int G, const Args& a, Smem& S) {
+  if (threadIdx.x == 0) {
+    const uint32_t need = (idx / RING) * (uint32_t)(G - 1);
+    S.flag = spin_until(&a.ctl->ack[idx % RING], need, a) ? 1 : 0;
+  }
+  __syncthreads();
+  return S.flag != 0;
+}
+
 __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   extern __shared__ __align__(16) uint64_t smem[];
   const int tid = threadIdx.x;
   const int g = blockIdx.x, G = gridDim.x;
   const int m = a.m;
   const int nsl = (m + BS - 1) / BS;
-  const int nown = (a.nw - g + G - 1) / G;  // columns owned: g, g+G, ...
+  const int nown = (a.nw - g + G - 1) / G;  // word columns owned: g, g+G, ...
   const int pw = (m + 63) / 64;
   uint64_t* cols = smem;                              // [cw][m]
   uint64_t* pivflag = cols + (size_t)a.cw * m;        // [pw]
@@ -398,68 +440,63 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   }
   __syncthreads();
 
-  uint32_t seq = 0;      // next record index
+  uint32_t seq = 0;       // next record index
   int rank = 0;
   bool ok = true;
-  bool prepared = false;  // snapshot of the next own strip written, candidates in S
-  for (int s = 0; s < a.nw && rank < m && ok; ++s) {
-    const int owner = s % G;
+  bool prepared = false;  // snapshot of my next strip written, its candidates in S
+  for (int t = 0; t < a.nstrips && rank < m && ok; ++t) {
+    const int wc = t >> 1, shift = SW * (t & 1);
+    const int owner = wc % G;
     if (owner == g) {
-      // ---------------- produce strip s ----------------
-      const int js = s / G;
+      // ---------------- produce strip t ----------------
+      const int js = wc / G;
       uint64_t* col = cols + (size_t)js * m;
       const int rank0 = rank;
       bool multi = false;
-      if (tid == 0) prof_mark(a, s, 0);
+      if (tid == 0) prof_mark(a, t, 0);
       for (;;) {
-        const int slot = seq % RING;
-        PassRec* rec = a.recs + slot;
-        uint64_t* snap = a.snaps + (size_t)slot * m;
+        PassRec* rec = a.recs + seq % RING;
+        uint32_t* snap = a.snaps + (size_t)(seq % RING) * m;
         if (!prepared) {
-          if (tid == 0) {
-            const uint32_t need = (seq / RING) * (uint32_t)(G - 1);
-            S.flag = spin_until(&a.ctl->ack[slot], need, a) ? 1 : 0;
-          }
-          __syncthreads();
-          if (!S.flag) { ok = false; break; }
+          if (!wait_slot(seq, G, a, S)) { ok = false; break; }
           uint32_t flags = 0;
           for (int i = 0; i < nsl; ++i) {
             const int r = i * BS + tid;
             if (r < m) {
-              const uint64_t v = col[r];
-              st_dev64(&snap[r], v);
+              const uint32_t v = (uint32_t)(col[r] >> shift);
+              st_dev(&snap[r], v);
               if (v != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
             }
           }
           compact_candidates(flags, nsl, S);
         }
         prepared = false;
-        if (tid == 0) prof_mark(a, s, 1);
+        if (tid == 0) prof_mark(a, t, 1);
         const int total = S.total;
         if (tid < 64) {
-          if (total > 0) factor_candidates(col, S);
+          if (total > 0) factor_candidates(col, shift, S);
           else if (tid == 0) { S.k = 0; S.pivmask = 0; }
         }
         __syncthreads();
-        if (tid == 0) prof_mark(a, s, 6);
+        if (tid == 0) prof_mark(a, t, 6);
         const int k = S.k;
-        const int last = (total == 0 || k == 64 || total <= NCAND) ? 1 : 0;
+        const int last = (total == 0 || k == SW || total <= NCAND) ? 1 : 0;
         if (tid < k) {
           st_dev32(&rec->rows[tid], S.rows[tid]);
           st_dev32(&rec->bits[tid], S.bits[tid]);
-          st_dev64(&rec->L[tid], S.L[tid]);
+          st_dev(&rec->L[tid], S.L[tid]);
           st_dev32(&a.piv_row[rank + tid], S.rows[tid]);
-          st_dev32(&a.piv_col[rank + tid], 64 * s + S.bits[tid]);
+          st_dev32(&a.piv_col[rank + tid], SW * t + S.bits[tid]);
         }
         if (tid == 0) {
-          st_dev32(&rec->strip, s);
+          st_dev32(&rec->strip, t);
           st_dev32(&rec->k, k);
           st_dev32(&rec->last, last);
-          st_dev64(&rec->pivmask, S.pivmask);
+          st_dev(&rec->pivmask, S.pivmask);
         }
         if (last && multi && tid == 64) {
           // multi-pass strip (rare): sort its pivot list by column.  A strip
-          // holds at most 64 pivots; earlier passes' entries are read back,
+          // holds at most 32 pivots; earlier passes' entries are read back,
           // this pass's come from the factor output.
           int cnt = 0;
           for (int i = rank0; i < rank; ++i) {
@@ -469,7 +506,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           }
           for (int j = 0; j < k; ++j) {
             S.prow[cnt] = S.rows[j];
-            S.pcol[cnt] = 64 * s + S.bits[j];
+            S.pcol[cnt] = SW * t + S.bits[j];
             ++cnt;
           }
           for (int i = 1; i < cnt; ++i) {
@@ -497,77 +534,80 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         }
         if (tid == 0) {
           st_dev(&a.ctl->seq, seq + 1);
-          prof_mark(a, s, 2);
+          prof_mark(a, t, 2);
         }
         ++seq;
         if (k > 0) {
+          // the high half of this word column is my next strip: write its
+          // snapshot and candidates while applying this pass
+          const bool fused = last && (t & 1) == 0 && t + 1 < a.nstrips;
+          if (fused && !wait_slot(seq, G, a, S)) { ok = false; break; }
           uint64_t* list[MAX_CW];
           int nc = 0;
           for (int j = js; j < nown; ++j) list[nc++] = cols + (size_t)j * m;
           mark_newpiv(newpiv, S);
           make_tables(list, nc, S);
-          apply_record(list, nc, nullptr, col, m, pivflag, newpiv, -1, nullptr, nullptr, S);
+          const uint32_t flags = apply_record(list, nc, nullptr, col, shift, m, pivflag, newpiv,
+                                              fused ? 0 : -1, SW, a.snaps + (size_t)(seq % RING) * m,
+                                              nullptr, S);
           rank += k;
+          if (fused) {
+            compact_candidates(flags, nsl, S);
+            prepared = true;
+          }
         }
-        if (tid == 0) prof_mark(a, s, 3);
+        if (tid == 0) prof_mark(a, t, 3);
         if (last) break;
         multi = true;
       }
     } else {
-      // ---------------- consume strip s ----------------
-      const bool own_next = (s + 1 < a.nw) && ((s + 1) % G) == g;
+      // ---------------- consume strip t ----------------
+      // my next strip follows directly when t is the high half of the word
+      // column just before one of mine
+      const bool own_next = (t + 1 < a.nstrips) && (((t + 1) >> 1) % G) == g && ((t + 1) & 1) == 0;
       for (;;) {
         const int slot = seq % RING;
         if (tid == 0) S.flag = spin_until(&a.ctl->seq, seq + 1, a) ? 1 : 0;
         __syncthreads();
         if (!S.flag) { ok = false; break; }
         const PassRec* rec = a.recs + slot;
-        const uint64_t* snap = a.snaps + (size_t)slot * m;
+        const uint32_t* snap = a.snaps + (size_t)slot * m;
         // the record and the first multipliers are loaded together
-        uint64_t pre[GROUP];
+        uint32_t pre[GROUP];
 #pragma unroll
         for (int q = 0; q < GROUP; ++q) {
           const int r = q * BS + tid;
-          pre[q] = r < m ? ld_dev64(&snap[r]) : 0;
+          pre[q] = r < m ? ld_dev(&snap[r]) : 0;
         }
         if (tid == 0) {
           S.k = ld_dev32(&rec->k);
           S.last = ld_dev32(&rec->last);
-          S.pivmask = ld_dev64(&rec->pivmask);
+          S.pivmask = ld_dev(&rec->pivmask);
         }
-        if (tid < 64) {
+        if (tid < SW) {
           S.rows[tid] = ld_dev32(&rec->rows[tid]);
           S.bits[tid] = ld_dev32(&rec->bits[tid]);
-          S.L[tid] = ld_dev64(&rec->L[tid]);
+          S.L[tid] = ld_dev(&rec->L[tid]);
         }
         __syncthreads();
         const int k = S.k, last = S.last;
         const bool fused = own_next && last && k > 0;
-        if (tid == 0 && own_next && last) prof_mark(a, s, 4);
-        if (fused) {
-          const uint32_t nseq = seq + 1;
-          if (tid == 0) {
-            const uint32_t need = (nseq / RING) * (uint32_t)(G - 1);
-            S.flag = spin_until(&a.ctl->ack[nseq % RING], need, a) ? 1 : 0;
-          }
-          __syncthreads();
-          if (!S.flag) { ok = false; break; }
-        }
+        if (tid == 0 && own_next && last) prof_mark(a, t, 4);
+        if (fused && !wait_slot(seq + 1, G, a, S)) { ok = false; break; }
         if (k > 0) {
-          // owned columns with index > s
+          rank += k;  // every workgroup tracks the rank (the loops end together)
+          // owned word columns after wc
           uint64_t* list[MAX_CW];
           int nc = 0, fuse = -1;
-          for (int j = (s - g) >= 0 ? (s - g) / G + 1 : 0; j < nown; ++j) {
-            if (fused && g + j * G == s + 1) fuse = nc;
+          for (int j = (wc - g) >= 0 ? (wc - g) / G + 1 : 0; j < nown; ++j) {
+            if (fused && g + j * G == ((t + 1) >> 1)) fuse = nc;
             list[nc++] = cols + (size_t)j * m;
           }
-          rank += k;  // every workgroup tracks the rank (the loops end together)
           if (nc > 0) {
             mark_newpiv(newpiv, S);
             make_tables(list, nc, S);
-            uint64_t* snap_out = a.snaps + (size_t)((seq + 1) % RING) * m;
-            const uint32_t flags = apply_record(list, nc, snap, nullptr, m, pivflag, newpiv, fuse,
-                                                snap_out, pre, S);
+            const uint32_t flags = apply_record(list, nc, snap, nullptr, 0, m, pivflag, newpiv, fuse, 0,
+                                                a.snaps + (size_t)((seq + 1) % RING) * m, pre, S);
             if (fused) {
               compact_candidates(flags, nsl, S);
               prepared = true;
@@ -577,7 +617,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         __syncthreads();
         if (tid == 0) {
           __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (own_next && last) prof_mark(a, s, 5);
+          if (own_next && last) prof_mark(a, t, 5);
         }
         ++seq;
         if (last) break;
@@ -665,7 +705,7 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
     zx_set_error("no HIP device");
     return ZX_EDEVICE;
   }
-  // columns per workgroup: the smallest count whose grid is co-resident
+  // word columns per workgroup: the smallest count whose grid is co-resident
   int cw = 1, G = 0;
   size_t lds = 0;
   for (cw = 1; cw <= MAX_CW; ++cw) {
@@ -688,13 +728,14 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
   a.n_cols = n_cols;
   a.nw = nw;
   a.cw = cw;
+  a.nstrips = (n_cols + SW - 1) / SW;
   a.ld = ld_words;
   a.rank_dev = rank_dev;
   a.piv_dev = pivot_cols_dev;
   a.status = (int32_t*)base;
   a.ctl = (Ctl*)(base + W.ctl);
   a.recs = (PassRec*)(base + W.recs);
-  a.snaps = (uint64_t*)(base + W.snaps);
+  a.snaps = (uint32_t*)(base + W.snaps);
   a.piv_row = (int32_t*)(base + W.piv_row);
   a.piv_col = (int32_t*)(base + W.piv_col);
   a.spin_ticks = 100000000ull * 5;  // 5 s at the 100 MHz real-time counter
