@@ -28,11 +28,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per rref_kernel launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB, already scaled by the copy-kernel calibration), valid only for the
+# gf2.hip source they were measured on (sha256 prefix); see profiles/.
+RREF_TRAFFIC = {
+    "72cdca17f0fd03eb": {"fetch_kib": 83480.2, "write_kib": 36632.0},
+}
 METRIC = "GF(2) elim GB/s (% HBM peak); diagrams simplified/sec batched vs plain, bit-exact"
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def gf2_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2604_01059_amd", "csrc", "gf2.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def rref_traffic_bytes():
+    t = RREF_TRAFFIC.get(gf2_source_hash())
+    if t is None:
+        return None
+    return int(1024 * (t["fetch_kib"] + t["write_kib"]))
+
+
+def strip_timeline(zx, ws, m):
+    """Median per-strip phases from the kernel's timestamps (us)."""
+    P = zx.gf2_profile(ws, m).astype(np.int64)
+    used = np.nonzero(P[:, 0])[0]
+    if len(used) < 3:
+        return None
+    S = used[-1] + 1
+    us = lambda x: float(np.median(x)) * 0.01
+    s = np.arange(1, S - 1)
+    return {"strips": int(S),
+            "factor_us": us(P[s, 6] - P[s, 1]), "publish_us": us(P[s, 2] - P[s, 6]),
+            "owner_apply_us": us(P[s, 3] - P[s, 2]),
+            "handoff_us": us((P[s, 4] - P[s, 2])[P[s, 4] > 0]) if (P[s, 4] > 0).any() else None,
+            "next_apply_us": us((P[s, 5] - P[s, 4])[P[s, 4] > 0]) if (P[s, 4] > 0).any() else None,
+            "strip_period_us": us(np.diff(P[:S, 0])),
+            "span_us": float(P[S - 1, 3] - P[0, 0]) * 0.01}
 
 
 def rref_algorithmic_bytes(m: int, nw: int, last_strip: int) -> int:
@@ -74,8 +112,9 @@ def bench_rref(zx, args):
     last_strip = int(pv[r - 1]) // 64 if r > 0 else 0
     nbytes = rref_algorithmic_bytes(m, nw, last_strip)
     Rh = zx.to_host_words(R)
+    timeline = strip_timeline(zx, ws, m) if args.rref_strips else None
     return dict(A=A, R=Rh, rank=r, piv=pv, ms=ms, wall_ms=1e3 * wall / args.steps, bytes=nbytes,
-                last_strip=last_strip, m=m, n=n)
+                last_strip=last_strip, m=m, n=n, timeline=timeline)
 
 
 def cpu_baseline_rref(res, budget_s):
@@ -224,7 +263,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "copy"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
+    ap.add_argument("--rref-strips", action="store_true",
+                    help="record per-strip timestamps in the elimination kernel and report them")
     args = ap.parse_args()
+    if args.rref_strips:
+        os.environ["ZX_RREF_PROFILE"] = "1"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the GF(2) "
               "elimination would shard rows across GPUs with a per-strip pivot broadcast; "
@@ -265,12 +308,19 @@ def main():
                          "strips_with_pivots": res["last_strip"] + 1,
                          "algorithmic_bytes_per_step": res["bytes"]}
         out["pct_hbm_peak"] = round(100 * gbs / HBM_PEAK_GBS, 2)
+        traffic = rref_traffic_bytes()
         out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                           "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
+                                           "copy-calibrated) for gf2.hip " + gf2_source_hash()
+                                           + ("" if traffic else " (not measured for this source)"),
                            "kernel": "rref_kernel (+ rref_init)", "avg_launch_ms": round(res["ms"], 4),
                            "wall_ms_per_step": round(res["wall_ms"], 4)}
         log("rref: %.4f ms/step, %.1f GB/s algorithmic (%.1f%% of 8 TB/s), rank %d" %
             (res["ms"], gbs, 100 * gbs / HBM_PEAK_GBS, res["rank"]))
+        if res["timeline"]:
+            out["rref_strip_timeline"] = res["timeline"]
+            log("rref strips: %s" % res["timeline"])
         cb, exact = cpu_baseline_rref(res, args.cpu_budget)
         cb["threads"] = 1
         out["cpu_baseline"] = cb

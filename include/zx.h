@@ -209,6 +209,15 @@ zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_
                            void* ws, size_t ws_bytes, hipStream_t s);
 /* Sticky status of the last elimination that used this workspace (syncs). */
 zx_status zx_gf2_status(const void* ws, hipStream_t s);
+/* Per-strip timestamps (100 MHz real-time counter) of the last elimination in
+ * this workspace, recorded only when the environment variable
+ * ZX_RREF_PROFILE=1 was set when the library first launched the kernel.
+ * ticks: n x 8 int64 (n = min(max_strips, strips recorded)); per strip t:
+ * [0] owner starts, [1] candidates ready, [6] reduction done, [2] pass
+ * published, [3] owner applied it, [4] next owner saw the strip's last pass,
+ * [5] next owner applied it.  Unrecorded slots are 0.  Synchronises s. */
+zx_status zx_gf2_profile_read(const void* ws, int32_t m, int64_t* ticks, int32_t max_strips,
+                              hipStream_t s);
 
 /* ======================================================================
  * Symplectic commutation table of Pauli strings

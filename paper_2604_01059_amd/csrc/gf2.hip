@@ -142,10 +142,12 @@ __device__ bool spin_until(const uint32_t* p, uint32_t target, const Args& a) {
   }
 }
 
-__global__ void rref_init(Ctl* ctl, int32_t* status) {
+__global__ void rref_init(Ctl* ctl, int32_t* status, uint64_t* prof) {
   const int t = threadIdx.x;
   uint32_t* c = (uint32_t*)ctl;
   for (int i = t; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
+  if (prof)
+    for (int i = t; i < MAX_STRIPS * PROF_SLOTS; i += blockDim.x) prof[i] = 0;
   if (t == 0) *status = 0;
 }
 
@@ -675,6 +677,17 @@ extern "C" zx_status zx_gf2_status(const void* ws, hipStream_t s) {
   return st;
 }
 
+extern "C" zx_status zx_gf2_profile_read(const void* ws, int32_t m, int64_t* ticks, int32_t max_strips,
+                                         hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(ws && ticks && m > 0 && max_strips >= 0, "bad argument");
+  const int n = max_strips < MAX_STRIPS ? max_strips : MAX_STRIPS;
+  ZX_HIP(hipStreamSynchronize(s));
+  const WsLayout W = ws_layout(m);
+  ZX_HIP(hipMemcpy(ticks, (const uint8_t*)ws + W.prof, (size_t)n * PROF_SLOTS * 8, hipMemcpyDeviceToHost));
+  return ZX_OK;
+}
+
 extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
                                       int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
                                       void* ws, size_t ws_bytes, hipStream_t s) {
@@ -741,7 +754,7 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
   a.spin_ticks = 100000000ull * 5;  // 5 s at the 100 MHz real-time counter
   static const bool prof_on = getenv("ZX_RREF_PROFILE") && getenv("ZX_RREF_PROFILE")[0] == '1';
   a.prof = prof_on ? (uint64_t*)(base + W.prof) : nullptr;
-  hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.status);
+  hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.status, a.prof);
   ZX_HIP(hipGetLastError());
   void* args[] = {&a};
   ZX_HIP(hipLaunchCooperativeKernel((const void*)rref_kernel, dim3(G), dim3(BS), args, (unsigned)lds, s));

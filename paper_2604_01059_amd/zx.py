@@ -79,6 +79,7 @@ def load():
         "zx_gf2_workspace_bytes": ([i32, i32], sz),
         "zx_gf2_eliminate": ([P, P, i32, i32, i64, P, P, P, sz, P], i32),
         "zx_gf2_status": ([P, P], i32),
+        "zx_gf2_profile_read": ([P, i32, P, i32, P], i32),
         "zx_pauli_commute": ([P, P, i64, i32, i64, P, i64, u32, P], i32),
     }
     for name, (args, res) in sigs.items():
@@ -96,7 +97,7 @@ def exported_symbols():
             "zx_local_comp", "zx_pivot", "zx_simplify_variants", "zx_simplify_variant_name",
             "zx_simplify_workspace_bytes", "zx_simplify", "zx_batch_prepare", "zx_batch_simplify",
             "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
-            "zx_gf2_eliminate", "zx_gf2_status", "zx_pauli_commute"]
+            "zx_gf2_eliminate", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute"]
 
 
 def _check(rc):
@@ -296,6 +297,13 @@ def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, strea
 
 def gf2_status(ws, stream=None):
     return load().zx_gf2_status(_ptr(ws), _stream(stream))
+
+
+def gf2_profile(ws, m, max_strips=8192, stream=None):
+    """Per-strip timestamps (n x 8, 100 MHz ticks) if ZX_RREF_PROFILE=1 was set."""
+    out = np.zeros((max_strips, 8), np.int64)
+    _check(load().zx_gf2_profile_read(_ptr(ws), m, _np(out), max_strips, _stream(stream)))
+    return out
 
 
 # ------------------------------------------------------------------ Pauli --
