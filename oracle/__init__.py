@@ -50,6 +50,8 @@ def lib():
         _lib.or_pivot.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, C.c_int, C.POINTER(Scalar)]
         _lib.or_simplify.argtypes = [C.c_int, C.c_int, P, P, P, P, C.POINTER(Scalar), P, C.c_int,
                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        _lib.or_simplify_rounds.argtypes = [C.c_int, C.c_int, P, P, P, P, C.POINTER(Scalar), P, C.c_int,
+                                            C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
         _lib.or_gf2_rref.argtypes = [C.c_int, C.c_int, i64, P, P, C.POINTER(i32), C.POINTER(i64), P, i64]
         _lib.or_frontier.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, P, C.POINTER(i32), C.POINTER(i64)]
         _lib.or_pauli_commute.argtypes = [i64, C.c_int, P, P, i64, i64, i64, P, i64]
@@ -130,12 +132,16 @@ class Graph:
         return lib().or_pivot(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive),
                               _p(self.bnd), int(u), int(v), int(graph_only), C.byref(self.scalar))
 
-    def simplify(self) -> int:
+    def simplify(self, max_rounds: int = 0) -> int:
+        """Canonical greedy schedule to the fixed point, or for max_rounds
+        (> 0) rounds; the trace and round count of this call replace the
+        previous ones."""
         cap = 2 * self.n + 2
         tr = np.zeros((cap, 4), np.int32)
         nt, nr = C.c_int(0), C.c_int(0)
-        rc = lib().or_simplify(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive), _p(self.bnd),
-                               C.byref(self.scalar), _p(tr), cap, C.byref(nt), C.byref(nr))
+        rc = lib().or_simplify_rounds(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive), _p(self.bnd),
+                                      C.byref(self.scalar), _p(tr), cap, C.byref(nt), C.byref(nr),
+                                      int(max_rounds))
         self.trace = tr[: nt.value].copy()
         self.rounds = nr.value
         return rc

@@ -1,0 +1,147 @@
+"""Reference of the learned proposal's candidate handling and of the checks
+on schedules other than the canonical one.
+
+TEST INFRASTRUCTURE ONLY (imported by ``tests/``).
+
+The paper names the two rules and their fixed point (appendix "Rewrite
+rules", equations local_comp and pivoting; appendix "Stabilizer
+decompositions", first paragraph) but no order of application.  Any order
+reaches a fixed point by sound rewrites, so a schedule that is not the
+canonical one is checked by replaying its trace with the rule
+implementations of the C oracle, which verify each precondition.
+
+Everything here is written with plain Python loops over an oracle ``Graph``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import OK, Graph
+
+
+def lc_candidates(g: Graph):
+    """Interior present spiders with phase pi/2 or 3pi/2, ascending."""
+    return [u for u in range(g.n) if g.is_alive(u) and not g.has_boundary(u) and g.k[u] % 4 == 2]
+
+
+def pauli_candidates(g: Graph):
+    return [u for u in range(g.n) if g.is_alive(u) and not g.has_boundary(u) and g.k[u] % 4 == 0]
+
+
+def list_cap(n: int) -> int:
+    c = 64
+    while c < n:
+        c *= 2
+    return c
+
+
+def candidate_list(g: Graph):
+    """(pivot?, entries) as listed by a round: LC candidates if any, else the
+    pivot edges u < v between Pauli candidates in lexicographic order, at most
+    list_cap(n) of them."""
+    lc = lc_candidates(g)
+    if lc:
+        return False, [(u, -1) for u in lc]
+    P = set(pauli_candidates(g))
+    edges = []
+    for u in sorted(P):
+        for v in range(u + 1, g.n):
+            if v in P and g.edge(u, v):
+                edges.append((u, v))
+    return True, edges[: list_cap(g.n)]
+
+
+def neighbours(g: Graph, x):
+    return [y for y in range(g.n) if g.edge(x, y)]
+
+
+def endpoint_features(g: Graph, x, N):
+    """Seven numbers (fp32 quotients): degree/N, phase class one-hot
+    {k = 0 mod 4, k = 2 mod 4, k odd}, boundary-attached neighbours/N,
+    spiders at distance exactly two/N, neighbours with k = 0 mod 4 / N."""
+    nb = neighbours(g, x)
+    two = set()
+    for y in nb:
+        for z in neighbours(g, y):
+            if z != x and not g.edge(x, z):
+                two.add(z)
+    bnd = sum(1 for y in nb if g.has_boundary(y))
+    pauli = sum(1 for y in nb if g.k[y] % 4 == 0)
+    k = int(g.k[x])
+    f32 = np.float32
+    Nf = f32(N)
+    return [f32(len(nb)) / Nf, f32(k % 4 == 0), f32(k % 4 == 2), f32(k % 2 == 1),
+            f32(bnd) / Nf, f32(len(two)) / Nf, f32(pauli) / Nf]
+
+
+def features(g: Graph, entry, pivot: bool) -> np.ndarray:
+    """The 16 features of a candidate as bf16 bit patterns (uint16)."""
+    from .mlp import bf16_round
+    N = max(1, len(g.alive_list()))
+    u, v = entry
+    f = endpoint_features(g, u, N)
+    f += endpoint_features(g, v, N) if pivot else [np.float32(0)] * 7
+    f += [np.float32(1.0 if pivot else 0.0), np.float32(1.0)]
+    r = bf16_round(np.array(f, dtype=np.float32))
+    return (r.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def gate2q(g: Graph) -> int:
+    """Hadamard edges left plus the row additions of the output frontier."""
+    if len(g.outputs):
+        _, _, _, ops = g.frontier()
+    else:
+        ops = 0
+    return g.n_edges() + ops
+
+
+def rollout(state: Graph, entry, pivot: bool):
+    """Apply the candidate, then the canonical schedule to the fixed point:
+    (cost, fill-in added)."""
+    g = state.copy()
+    f0 = g.scalar.fill_in
+    u, v = entry
+    rc = g.pivot(u, v) if pivot else g.local_comp(u)
+    assert rc == OK, "candidate precondition failed"
+    rc = g.simplify()
+    assert rc == OK
+    return gate2q(g), g.scalar.fill_in - f0
+
+
+def replay(g: Graph, trace) -> Graph:
+    """Re-apply a trace (round, rule, u, v) in order with precondition checks;
+    returns the final state.  Raises AssertionError on an invalid step or if
+    a candidate remains at the end."""
+    g = g.copy()
+    for rnd, rule, u, v in np.asarray(trace).reshape(-1, 4):
+        rc = g.local_comp(int(u)) if rule == 0 else g.pivot(int(u), int(v))
+        assert rc == OK, "step (%d, %d, %d, %d) not applicable" % (rnd, rule, u, v)
+    assert not lc_candidates(g), "LC candidate left"
+    P = pauli_candidates(g)
+    for i, u in enumerate(P):
+        for w in P[i + 1:]:
+            assert not g.edge(u, w), "pivot candidate left"
+    return g
+
+
+def round_is_valid(before: Graph, entries, pivot: bool) -> bool:
+    """One round of a schedule: LC spiders pairwise non-adjacent and maximal
+    among the candidates; pivot pairs disjoint, mutually non-adjacent."""
+    if not pivot:
+        sel = [u for u, _ in entries]
+        for i, a in enumerate(sel):
+            for b in sel[i + 1:]:
+                if before.edge(a, b):
+                    return False
+        s = set(sel)
+        for c in lc_candidates(before):
+            if c not in s and not any(before.edge(c, x) for x in sel):
+                return False
+        return True
+    ends = []
+    for u, v in entries:
+        for w in ends:
+            if w in (u, v) or before.edge(u, w) or before.edge(v, w):
+                return False
+        ends += [u, v]
+    return True

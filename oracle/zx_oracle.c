@@ -207,13 +207,16 @@ static int pauli_candidate(const uint64_t* alive, const uint64_t* bnd, const int
   return is_interior(alive, bnd, v) && (k[v] == 0 || k[v] == 4);
 }
 
-int or_simplify(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
-                const uint64_t* bnd, or_scalar* sc, or_trace* trace, int trace_cap,
-                int* n_trace, int* n_rounds) {
+/* The same schedule stopped once max_rounds rounds (> 0) have been applied;
+ * used to reach the intermediate states of a greedy run. */
+int or_simplify_rounds(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
+                       const uint64_t* bnd, or_scalar* sc, or_trace* trace, int trace_cap,
+                       int* n_trace, int* n_rounds, int max_rounds) {
   int* sel = (int*)malloc(sizeof(int) * (size_t)(2 * n + 2));
   int nt = 0, round = 0;
   /* LC rounds */
   for (;;) {
+    if (max_rounds > 0 && round >= max_rounds) break;
     int ns = 0;
     for (int u = 0; u < n; ++u) {
       if (!lc_candidate(alive, bnd, k, u)) continue;
@@ -233,6 +236,7 @@ int or_simplify(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
   }
   /* pivot rounds */
   for (;;) {
+    if (max_rounds > 0 && round >= max_rounds) break;
     int np = 0; /* pairs stored as sel[2i], sel[2i+1] */
     for (int u = 0; u < n; ++u) {
       if (!pauli_candidate(alive, bnd, k, u)) continue;
@@ -259,6 +263,12 @@ int or_simplify(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
   *n_trace = nt;
   *n_rounds = round;
   return OR_OK;
+}
+
+int or_simplify(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
+                const uint64_t* bnd, or_scalar* sc, or_trace* trace, int trace_cap,
+                int* n_trace, int* n_rounds) {
+  return or_simplify_rounds(n, W, adj, k, alive, bnd, sc, trace, trace_cap, n_trace, n_rounds, 0);
 }
 
 /* ----------------------------------------------------- GF(2) elimination -- */

@@ -36,6 +36,8 @@ P_PHASES = 2
 P_MATRIX = 3
 P_PAULI = 4
 P_ARRIVAL = 5
+P_WEIGHTS = 6
+P_SERVE = 7
 
 
 @dataclass
@@ -192,3 +194,32 @@ def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
     u = unit(draw(s, np.arange(count, dtype=np.uint64)))
     gaps = -np.log1p(-u) / rate
     return np.cumsum(gaps)
+
+
+def network_init(seed: int, n_in: int = 16, n_hid: int = 256) -> np.ndarray:
+    """fp32 parameter vector W1[n_in][n_hid] | b1 | w2 | b2: weights uniform
+    in +-sqrt(6 / (fan_in + fan_out)), biases zero."""
+    s = stream_seed(seed, 0, P_WEIGHTS)
+    n1, n2 = n_in * n_hid, n_hid
+    u = unit(draw(s, np.arange(n1 + n2, dtype=np.uint64))) * 2.0 - 1.0
+    p = np.zeros(n1 + 2 * n_hid + 1, np.float32)
+    p[:n1] = u[:n1] * np.sqrt(6.0 / (n_in + n_hid))
+    p[n1 + n_hid:n1 + 2 * n_hid] = u[n1:] * np.sqrt(6.0 / (n_hid + 1))
+    return p
+
+
+def serve_params(seed: int, item: int, q_lo: int = 8, q_hi: int = 512, m_lo: int = 4, m_hi: int = 16,
+                 p_lo: float = 0.05, p_hi: float = 0.3):
+    """(q, N, p) of request ``item`` of a serving stream: q = round(exp(U[ln
+    q_lo, ln q_hi])), N = q * U{m_lo..m_hi}, p ~ U[p_lo, p_hi]."""
+    s = stream_seed(seed, item, P_SERVE)
+    h = draw(s, np.arange(3, dtype=np.uint64))
+    q = int(round(float(np.exp(np.log(q_lo) + (np.log(q_hi) - np.log(q_lo)) * float(unit(h[0]))))))
+    mult = int(randint(h[1], m_lo, m_hi))
+    p = p_lo + (p_hi - p_lo) * float(unit(h[2]))
+    return q, q * mult, p
+
+
+def serve_diagram(seed: int, item: int, **kw) -> Diagram:
+    q, n, p = serve_params(seed, item, **kw)
+    return make_diagram(seed, item, q, n, p)
