@@ -1,5 +1,6 @@
-"""Reference of the learned proposal's candidate handling and of the checks
-on schedules other than the canonical one.
+"""Reference of the learned proposal's candidate handling (local
+complementation rounds) and of the checks on schedules other than the
+canonical one.
 
 TEST INFRASTRUCTURE ONLY (imported by ``tests/``).
 
@@ -28,27 +29,10 @@ def pauli_candidates(g: Graph):
     return [u for u in range(g.n) if g.is_alive(u) and not g.has_boundary(u) and g.k[u] % 4 == 0]
 
 
-def list_cap(n: int) -> int:
-    c = 64
-    while c < n:
-        c *= 2
-    return c
-
-
 def candidate_list(g: Graph):
-    """(pivot?, entries) as listed by a round: LC candidates if any, else the
-    pivot edges u < v between Pauli candidates in lexicographic order, at most
-    list_cap(n) of them."""
-    lc = lc_candidates(g)
-    if lc:
-        return False, [(u, -1) for u in lc]
-    P = set(pauli_candidates(g))
-    edges = []
-    for u in sorted(P):
-        for v in range(u + 1, g.n):
-            if v in P and g.edge(u, v):
-                edges.append((u, v))
-    return True, edges[: list_cap(g.n)]
+    """The candidates of an LC round as the learned policy lists them:
+    (u, -1) for the LC candidates, ascending (empty past the LC phase)."""
+    return [(u, -1) for u in lc_candidates(g)]
 
 
 def neighbours(g: Graph, x):
@@ -74,14 +58,12 @@ def endpoint_features(g: Graph, x, N):
             f32(bnd) / Nf, f32(len(two)) / Nf, f32(pauli) / Nf]
 
 
-def features(g: Graph, entry, pivot: bool) -> np.ndarray:
-    """The 16 features of a candidate as bf16 bit patterns (uint16)."""
+def features(g: Graph, u) -> np.ndarray:
+    """The 16 features of LC candidate u as bf16 bit patterns (uint16):
+    its seven endpoint features, seven zeros, rule bit 0, constant 1."""
     from .mlp import bf16_round
     N = max(1, len(g.alive_list()))
-    u, v = entry
-    f = endpoint_features(g, u, N)
-    f += endpoint_features(g, v, N) if pivot else [np.float32(0)] * 7
-    f += [np.float32(1.0 if pivot else 0.0), np.float32(1.0)]
+    f = endpoint_features(g, u, N) + [np.float32(0)] * 7 + [np.float32(0.0), np.float32(1.0)]
     r = bf16_round(np.array(f, dtype=np.float32))
     return (r.view(np.uint32) >> 16).astype(np.uint16)
 
@@ -95,13 +77,12 @@ def gate2q(g: Graph) -> int:
     return g.n_edges() + ops
 
 
-def rollout(state: Graph, entry, pivot: bool):
-    """Apply the candidate, then the canonical schedule to the fixed point:
+def rollout(state: Graph, u):
+    """Apply LC at u, then the canonical schedule to the fixed point:
     (cost, fill-in added)."""
     g = state.copy()
     f0 = g.scalar.fill_in
-    u, v = entry
-    rc = g.pivot(u, v) if pivot else g.local_comp(u)
+    rc = g.local_comp(u)
     assert rc == OK, "candidate precondition failed"
     rc = g.simplify()
     assert rc == OK

@@ -133,20 +133,14 @@ def test_features_against_matrix_powers(seed):
         assert f[1] + f[2] == (1 - g.k[x] % 2) and f[3] == (g.k[x] % 2)
 
 
-def test_pivot_candidate_list_is_lexicographic_and_capped():
-    n = 20  # 16 interior Pauli spiders, complete among themselves: 120 edges > cap 64
-    W = 1
-    adj = np.zeros((n, W), np.uint64)
-    for i in range(2, 18):
-        for j in range(2, 18):
-            if i != j:
-                adj[i, 0] |= np.uint64(1) << np.uint64(j)
-    ph = np.zeros(n, np.int8)
-    g = oracle.Graph(n, adj, ph, inputs=[0, 1], outputs=[18, 19])
-    pivot, ent = policy.candidate_list(g)
-    assert pivot and len(ent) == 64 == policy.list_cap(n)
-    allp = [(u, v) for u in range(2, 18) for v in range(u + 1, 18)]
-    assert ent == allp[:64]
+def test_candidate_list_is_the_lc_candidates():
+    g, _ = small_graph(40, 0.2, 11)
+    ent = policy.candidate_list(g)
+    expect = [u for u in range(g.n) if g.k[u] % 4 == 2 and u not in (0, 1, g.n - 2, g.n - 1)]
+    assert [u for u, _ in ent] == expect and all(v == -1 for _, v in ent)
+    f = policy.features(g, expect[0])
+    assert f.dtype == np.uint16 and f.shape == (16,)
+    assert np.all(f[7:15] == 0) and f[15] == 0x3F80  # bf16(1.0)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -192,14 +186,14 @@ def test_rollout_is_sound_on_a_tiny_diagram():
     # a small diagram whose tensor the exact evaluator can afford
     for seed in range(40):
         g, _ = small_graph(9, 0.45, 100 + seed)
-        pivot, ent = policy.candidate_list(g)
+        ent = policy.candidate_list(g)
         if ent:
             break
     amp0 = evaluate_graph(g)
-    for e in ent[:4]:
+    for u, _ in ent[:4]:
         h = g.copy()
-        assert (h.pivot(*e) if pivot else h.local_comp(e[0])) == oracle.OK
+        assert h.local_comp(u) == oracle.OK
         h.simplify()
         assert evaluate_graph(h).equals(amp0)
-        cost, _ = policy.rollout(g, e, pivot)
+        cost, _ = policy.rollout(g, u)
         assert cost == policy.gate2q(h)
