@@ -12,7 +12,12 @@ headline's timed region):
   batched  4096 diagrams (q in 4..64, N = q * 4..16, p in [0.05, 0.3]):
            one persistent launch replayed from a HIP graph vs one launch per
            diagram (same kernel, host-synchronised); bit-exact vs the oracle
+  learned  training-set generation (rollouts), training and evaluation of
+           the learned proposal vs the greedy schedule on 1024 diagrams
+  serve    Poisson request stream into the continuous-batching server:
+           p50 / p99 latency (arrival to result on the host), throughput
   cpu_baseline  the plain C oracle on the same matrix, on this host's cores
+                (per leg: the oracle on that leg's workload)
 """
 from __future__ import annotations
 
@@ -236,7 +241,18 @@ def bench_batched(zx, args, pool):
         if (np.array_equal(a[0], rb[0][0]) and np.array_equal(a[1], rb[0][1]) and
                 np.array_equal(g.frontier()[0], rb[2][0])):
             same += 1
-    # oracle check of every diagram
+    cb = cpu_baseline_batched(pool, ds, res_b)
+    return dict(
+        workload="4096 diagrams: q~U{4..64}, N=q*U{4..16}, p~U[0.05,0.3], seed 3; simplify + frontier RREF",
+        variant=variant, batched_ms=round(batched_s * 1e3, 3), plain_ms=round(plain_s * 1e3, 2),
+        batched_diagrams_per_s=round(4096 / batched_s, 1), plain_diagrams_per_s=round(4096 / plain_s, 1),
+        speedup=round(plain_s / batched_s, 2), bit_exact_vs_oracle=cb.pop("bit_exact"),
+        batched_equals_plain="%d/4096" % same, cpu_baseline=cb)
+
+
+def cpu_baseline_batched(pool, ds, res_b):
+    """The oracle (plain C, one diagram per worker process) on the same 4096
+    diagrams: its throughput, and whether every GPU result equals it."""
     t0 = time.perf_counter()
     outs = list(pool.map(_oracle_diag, ds, chunksize=16))
     oracle_s = time.perf_counter() - t0
@@ -247,13 +263,106 @@ def bench_batched(zx, args, pool):
               and info.pow_sqrt2 == o[3] and info.phase8 == o[4] and np.array_equal(tr, o[5])
               and np.array_equal(fr[0], o[6]) and info.rank == o[7] and info.rowops == o[8])
         exact += ok
-    return dict(
-        workload="4096 diagrams: q~U{4..64}, N=q*U{4..16}, p~U[0.05,0.3], seed 3; simplify + frontier RREF",
-        variant=variant, batched_ms=round(batched_s * 1e3, 3), plain_ms=round(plain_s * 1e3, 2),
-        batched_diagrams_per_s=round(4096 / batched_s, 1), plain_diagrams_per_s=round(4096 / plain_s, 1),
-        speedup=round(plain_s / batched_s, 2), bit_exact_vs_oracle="%d/4096" % exact,
-        batched_equals_plain="%d/4096" % same,
-        oracle_all_cores_s=round(oracle_s, 2))
+    return {"value": round(len(ds) / oracle_s, 1), "unit": "diagrams/s", "cores": pool._processes,
+            "kind": "oracle", "sample": "all %d diagrams, one per worker process" % len(ds),
+            "bit_exact": "%d/%d" % (exact, len(ds))}
+
+
+def _oracle_eval(d):
+    import oracle
+    g = oracle.Graph.from_diagram(d)
+    g.simplify()
+    ops = g.frontier()[3] if len(g.outputs) else 0
+    return g.n_edges() + ops
+
+
+def bench_learned(zx, args, pool):
+    """Learned proposal: dataset from greedy runs (rollout labels), training
+    with the network kernels, evaluation on held-out diagrams vs greedy."""
+    import torch
+    from paper_2604_01059_amd import learned
+    from workloads import batch_diagram
+    t0 = time.perf_counter()
+    mlp = learned.new_network()
+    feats, costs = learned.make_dataset(args.learned_states, per_state=16, log=log)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    rollouts = int((costs >= 0).sum())
+    t0 = time.perf_counter()
+    curve = learned.train(mlp, feats, costs, per_state=16, epochs=args.learned_epochs, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    ev = learned.evaluate(mlp, n=1024)
+    out = dict(workload="train: %d greedy-run states of the batched generator (seed %d), 16 rollouts each; "
+                        "eval: 1024 diagrams q~U{32..128}, N=q*U{4..16}, seed %d"
+                        % (args.learned_states, learned.TRAIN_SEED, learned.EVAL_SEED),
+               dataset_s=round(data_s, 2), rollouts=rollouts, train_s=round(train_s, 2),
+               loss_first=curve[0][1] if curve else None, loss_last=curve[-1][1] if curve else None,
+               loss_curve=curve[:: max(1, len(curve) // 12)], **ev)
+    if pool is not None:
+        ds = [batch_diagram(learned.EVAL_SEED, i, q_lo=32, q_hi=128) for i in range(1024)]
+        t0 = time.perf_counter()
+        costs_cpu = list(pool.map(_oracle_eval, ds, chunksize=8))
+        out["cpu_baseline"] = {"value": round(1024 / (time.perf_counter() - t0), 1), "unit": "diagrams/s",
+                               "cores": pool._processes, "kind": "oracle",
+                               "sample": "the 1024 evaluation diagrams, greedy schedule",
+                               "gate2q": int(sum(costs_cpu)),
+                               "equals_gpu_greedy": int(sum(costs_cpu)) == ev["gate2q_greedy"]}
+    return out
+
+
+def _gen_serve(i):
+    from workloads import serve_diagram
+    return serve_diagram(5, i)
+
+
+def bench_serve(zx, args, pool):
+    """Serving: Poisson arrivals into a continuous-batching server."""
+    from workloads import poisson_arrivals
+    n_unique = args.serve_unique
+    t0 = time.perf_counter()
+    ds = list(pool.map(_gen_serve, range(n_unique), chunksize=8)) if pool is not None else \
+        [_gen_serve(i) for i in range(n_unique)]
+    log("serve: generated %d request diagrams in %.1f s (median N %d, max N %d)" %
+        (n_unique, time.perf_counter() - t0, int(np.median([d.n for d in ds])), max(d.n for d in ds)))
+    rate, warm, dur = args.serve_rate, args.serve_warmup, args.serve_seconds
+    count = int(rate * (warm + dur) * 1.05) + 16
+    arr = poisson_arrivals(5, rate, count)
+    arr = arr[arr < warm + dur]
+    sv = zx.Server(args.serve_pool_gib << 30, max_batch=2048, trusted=True)
+    start = time.perf_counter() + 0.05
+    backlog = []
+    lat, refused, nxt, done = [], 0, 0, 0
+    max_backlog = 0
+    while done < len(arr):
+        now = time.perf_counter() - start
+        while nxt < len(arr) and arr[nxt] <= now:
+            backlog.append(nxt)
+            nxt += 1
+        while backlog:
+            i = backlog[0]
+            if sv.submit(ds[i % n_unique], tag=i) is None:
+                refused += 1
+                break
+            backlog.pop(0)
+        max_backlog = max(max_backlog, len(backlog))
+        for r in sv.poll():
+            done += 1
+            if arr[r.tag] >= warm:
+                lat.append(r.t_done - (start + arr[r.tag]))
+    wall = time.perf_counter() - start
+    st = sv.stats()
+    sv.close()
+    lat = np.array(lat)
+    measured = int((arr >= warm).sum())
+    return dict(workload="Poisson %g req/s (seed 5), q=round(exp(U[ln 8, ln 512])), N=q*U{4..16}, "
+                         "p~U[0.05,0.3]; %d unique diagrams cycled; %g s warm-up + %g s measured"
+                         % (rate, n_unique, warm, dur),
+                requests=len(arr), measured=measured, throughput_req_s=round(measured / max(1e-9, wall - warm), 1),
+                p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3), max_ms=round(float(lat.max()) * 1e3, 3),
+                refused=refused, max_backlog=max_backlog, batches=int(st.batches),
+                pool_gib=args.serve_pool_gib, pool_peak_gib=round(st.pool_peak / 2 ** 30, 3))
 
 
 def main():
@@ -261,7 +370,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "copy"])
+    ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy"])
+    ap.add_argument("--learned-states", type=int, default=20000)
+    ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-unique", type=int, default=2048)
+    ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--rref-strips", action="store_true",
                     help="record per-strip timestamps in the elimination kernel and report them")
@@ -274,7 +390,7 @@ def main():
               "see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     pool = None
-    if args.only in ("all", "batched"):
+    if args.only in ("all", "batched", "learned", "serve"):
         # worker processes (generation, oracle checks) are forked before any
         # GPU call, so they never inherit an initialised device
         import multiprocessing as mp
@@ -329,11 +445,18 @@ def main():
     if args.only in ("all", "pauli"):
         out["pauli"] = bench_pauli(zx, max(3, args.steps // 4))
         log("pauli: %s" % out["pauli"])
-    if pool is not None:
+    if args.only in ("all", "batched"):
         out["batched"] = bench_batched(zx, args, pool)
+        log("batched: %s" % out["batched"])
+    if args.only in ("all", "learned"):
+        out["learned"] = bench_learned(zx, args, pool)
+        log("learned: %s" % out["learned"])
+    if args.only in ("all", "serve"):
+        out["serve"] = bench_serve(zx, args, pool)
+        log("serve: %s" % out["serve"])
+    if pool is not None:
         pool.close()
         pool.join()
-        log("batched: %s" % out["batched"])
     if "value" not in out:
         out.update(value=None, unit="GB/s", ms_per_step=None, config={"workload": args.only})
     print(json.dumps(out))

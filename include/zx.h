@@ -157,12 +157,25 @@ zx_status zx_pivot(zx_graph* g, int32_t u, int32_t v, uint32_t flags, hipStream_
  * already taken.  All rewrites of a round are applied together.
  * ==================================================================== */
 #define ZX_POLICY_GREEDY 0
+/* Learned priority (policy ZX_POLICY_LEARNED): each local-complementation
+ * round lists its candidate spiders (ascending), scores each with the
+ * network in opts.mlp on the features described at zx_rollout, and takes
+ * them in descending score order (ties: ascending id) unless adjacent to one
+ * already taken.  Pivot rounds keep the canonical order.  Results are exact
+ * ZX rewrites whatever the scores; only the schedule differs. */
+#define ZX_POLICY_LEARNED 1
+#define ZX_RESUME 0x2u   /* continue from the CURRENT diagram, trace and round count */
+
+typedef struct zx_mlp zx_mlp;
 
 typedef struct {
-  int32_t policy;     /* ZX_POLICY_GREEDY */
-  int32_t extract;    /* 1 = also reduce the output frontier */
-  int32_t tune_id;    /* kernel variant, -1 = autotuned / default */
-  uint32_t flags;     /* ZX_SYNC */
+  int32_t policy;       /* ZX_POLICY_GREEDY or ZX_POLICY_LEARNED */
+  int32_t extract;      /* 1 = also reduce the output frontier */
+  int32_t tune_id;      /* kernel variant, -1 = autotuned / default */
+  uint32_t flags;       /* ZX_SYNC, ZX_RESUME */
+  int32_t max_rounds;   /* stop after this many rounds in total, 0 = fixed point */
+  int32_t pad;
+  const zx_mlp* mlp;    /* ZX_POLICY_LEARNED: the scoring network */
 } zx_simplify_opts;
 
 /* Number of kernel variants and a short description of variant id. */
@@ -231,6 +244,131 @@ zx_status zx_gf2_profile_read(const void* ws, int32_t m, int64_t* ticks, int32_t
 zx_status zx_pauli_commute(const uint64_t* X, const uint64_t* Z, int64_t n_paulis,
                            int32_t n_qubits, int64_t ld_q, uint64_t* C, int64_t ld_c,
                            uint32_t flags, hipStream_t s);
+
+/* ======================================================================
+ * Learned rewrite proposal: scoring network, training kernels, rollouts
+ *
+ * The paper fixes no proposal policy; this one ranks the candidates of a
+ * round.  Network: score = w2 . relu(W1^T x + b1) + b2, x of ZX_MLP_IN
+ * features, ZX_MLP_HID hidden units.  x, W1 and w2 enter every product
+ * rounded to bf16 (round to nearest even); sums are fp32.  The parameters
+ * live in caller memory (device):
+ *   param  fp32 master, ZX_MLP_NPARAM floats: W1[ZX_MLP_IN][ZX_MLP_HID]
+ *          (input major) | b1[ZX_MLP_HID] | w2[ZX_MLP_HID] | b2
+ *   wbf16  bf16 copies used by the kernels, ZX_MLP_NBF16 halves: W1
+ *          transposed (hidden unit major) | w2.  zx_mlp_sync refreshes it.
+ * ==================================================================== */
+#define ZX_MLP_IN 16
+#define ZX_MLP_HID 256
+#define ZX_MLP_NPARAM (ZX_MLP_IN * ZX_MLP_HID + 2 * ZX_MLP_HID + 1)
+#define ZX_MLP_NBF16 (ZX_MLP_IN * ZX_MLP_HID + ZX_MLP_HID)
+
+struct zx_mlp {
+  float* param;
+  uint16_t* wbf16;
+};
+
+/* wbf16 <- bf16(param). */
+zx_status zx_mlp_sync(const zx_mlp* w, hipStream_t s);
+/* score[r] for rows r of x (rows x ZX_MLP_IN bf16, row major). */
+zx_status zx_mlp_forward(const zx_mlp* w, const uint16_t* x, int64_t rows, float* score,
+                         hipStream_t s);
+/* Softmax cross-entropy per segment: rows seg_off[i] .. seg_off[i+1]-1 are
+ * the candidates of state i; rows with cost < 0 are absent.  Target = the
+ * present row of least cost (first on ties).  loss[i] = logsumexp - score of
+ * the target (0 for a segment with no present row); dscore = (softmax -
+ * onehot) / n_seg on present rows, 0 elsewhere. */
+zx_status zx_mlp_loss(const float* score, const int64_t* cost, const int32_t* seg_off,
+                      int32_t n_seg, float* dscore, float* loss, hipStream_t s);
+/* grad (ZX_MLP_NPARAM floats, overwritten) = d(sum_r dscore[r] score[r]) /
+ * d(param), treating the bf16 rounding of W1 and w2 as the identity.  The
+ * sums over rows are reduced in a fixed order (deterministic). */
+size_t zx_mlp_workspace_bytes(int64_t rows);
+zx_status zx_mlp_backward(const zx_mlp* w, const uint16_t* x, const float* dscore, int64_t rows,
+                          float* grad, void* ws, size_t ws_bytes, hipStream_t s);
+/* Adam on the fp32 master (m, v: ZX_MLP_NPARAM floats each), then wbf16
+ * refresh.  step counts from 1; bias corrections 1 - beta^step. */
+zx_status zx_mlp_adam(const zx_mlp* w, const float* grad, float* m, float* v, float lr,
+                      float beta1, float beta2, float eps, int32_t step, hipStream_t s);
+
+/* Rollouts for training labels.  Item i = (state i / per_state, slot
+ * k = i % per_state) on states[i / per_state] (CURRENT diagrams, read only;
+ * at most 1024 spiders).  The kernel lists the state's local-complementation
+ * candidates (ascending), takes candidate c = k (all of them when there are
+ * at most per_state, else c = floor(k * count / per_state)), writes its
+ * features, applies it, runs the greedy schedule to the fixed point and
+ * reduces the output frontier:
+ *   cost[i]   = Hadamard edges left + frontier row additions (-1: no such
+ *               candidate, also for a state past its LC phase; -3: the
+ *               state is too large; -4: the round bound was exceeded)
+ *   fill[i]   = edges toggled on from the state to the end
+ *   move[i]   = {0 (LC), u, -1}, or {-1, -1, -1} without a candidate
+ *   feats[i]  = ZX_MLP_IN bf16 features of the candidate: degree / N,
+ *     phase class one-hot {k = 0 mod 4, k = 2 mod 4, k odd},
+ *     boundary-attached neighbours / N, two-hop count / N (spiders at
+ *     distance exactly 2), Pauli neighbours / N (k = 0 mod 4); seven zeros
+ *     (second endpoint, unused by LC); rule bit 0; constant 1.  N = present
+ *     spiders; quotients in fp32, then bf16.
+ * Synchronous (uploads the state table into ws). */
+size_t zx_rollout_workspace_bytes(zx_graph* const* states, int32_t n_states);
+zx_status zx_rollout(zx_graph* const* states, int32_t n_states, int32_t per_state, int64_t* cost,
+                     int64_t* fill, int32_t* move, uint16_t* feats, void* ws, size_t ws_bytes,
+                     hipStream_t s);
+
+/* ======================================================================
+ * Serving: continuous batching of simplification requests
+ *
+ * The paper's compile-once / sample-many use (section "Complexity",
+ * paragraph "Compilation") makes simplification a per-circuit service.  A
+ * server owns a caller-provided device pool; every request gets a slice of
+ * it (its arena) from submit until its result is harvested.  zx_server_poll
+ * drives the device: when no batch is running it launches one persistent
+ * simplify kernel over up to max_batch admitted requests (oldest first),
+ * and when that batch has finished it returns the results and frees the
+ * slices.  One batch runs at a time.  Calls on one server must not overlap
+ * (one thread at a time); different servers are independent.
+ * ==================================================================== */
+typedef struct zx_server zx_server;
+
+typedef struct {
+  int32_t n, n_in, n_out, pad;  /* spiders, input and output wires */
+  const uint64_t* adj;          /* host, n x ceil(n/64) words, symmetric */
+  const int8_t* phase;          /* host, n entries in 0..7 (units of pi/4) */
+  const int32_t* inputs;        /* host, spider of input wire i */
+  const int32_t* outputs;       /* host, spider of output wire j */
+  const uint8_t* bnd_is_h;      /* host or NULL */
+  int64_t tag;                  /* returned unchanged */
+} zx_request;
+
+typedef struct {
+  int64_t ticket, tag;
+  int32_t status;               /* sticky status of the request's diagram */
+  int32_t n_alive, rounds, n_trace, rank, phase8;
+  int64_t n_edges, rowops, pow_sqrt2, fill_in;
+  double t_submit, t_launch, t_done;  /* host steady clock, seconds */
+} zx_result;
+
+typedef struct {
+  int64_t submitted, refused, completed, batches, pending, running;
+  size_t pool_bytes, pool_used, pool_peak;
+} zx_server_stats;
+
+#define ZX_SERVE_TRUSTED 0x1u  /* submit skips the O(n^2) symmetry test */
+
+/* pool: device memory owned by the caller (256-byte aligned) that the server
+ * uses for its control data and the request arenas.  o: policy and extract
+ * (tune_id and max_rounds are ignored); NULL = greedy with extraction. */
+zx_status zx_server_create(zx_server** sv, void* pool, size_t pool_bytes, int32_t max_batch,
+                           const zx_simplify_opts* o, uint32_t flags);
+/* Validate and upload a request (synchronous for the host arrays).
+ * ZX_EBUSY: the pool has no room now (admission refused; retry after
+ * polling).  ZX_ECAPACITY: the request can never be served. */
+zx_status zx_server_submit(zx_server* sv, const zx_request* r, int64_t* ticket);
+/* Make progress and return up to max finished results. */
+zx_status zx_server_poll(zx_server* sv, zx_result* out, int32_t max, int32_t* n_out);
+zx_status zx_server_stats_read(const zx_server* sv, zx_server_stats* st);
+/* Waits for the running batch, then frees the server (not the pool). */
+void zx_server_destroy(zx_server* sv);
 
 #ifdef __cplusplus
 }

@@ -24,8 +24,11 @@
 //     row_w ^= XOR over x in S with w ~ x of contrib(x),
 // with contrib(u) = row_u for local complementation (the diagonal bit is
 // cleared afterwards) and contrib(u) = row_v minus u, contrib(v) = row_u
-// minus v for a pivot pair (u, v).  Rows are processed by "teams" of
-// T = min(64, pow2(W)) lanes, lane t owning words t, t + T, ...
+// minus v for a pivot pair (u, v).  No contribution row holds a bit of a
+// selected spider (they are pairwise non-adjacent), so the bits of a row at
+// selected positions cannot change during the round: every (row, word)
+// pair is updated by its own thread, which reads the row's selected bits
+// straight from the row, and the selected columns are cleared afterwards.
 #include <stdio.h>
 #include <string.h>
 
@@ -35,6 +38,7 @@
 #include <vector>
 
 #include "zx_internal.h"
+#include "mlp_dev.h"
 
 namespace {
 
@@ -46,7 +50,7 @@ __host__ __device__ inline int ldw_lds(int W) { return W | 1; }  // odd LDS row 
 __host__ __device__ inline int64_t aux_bytes(int n, int W) {
   int64_t k = (n + 7) & ~7;
   int64_t part = (2 * (int64_t)n + 7) & ~7;
-  return k + k + part + 8 * 8 * (int64_t)W;
+  return k + k + part + part + 8 * 8 * (int64_t)W;
 }
 __host__ __device__ inline int64_t lds_adj_bytes(int n, int W) { return (int64_t)n * ldw_lds(W) * 8; }
 
@@ -65,33 +69,51 @@ struct Shared {
   int32_t idx;
   int32_t status;
   int32_t rank;
+  int32_t nsw;         // words of the selected set (list in Ctx::blocked)
+  int32_t ns;          // selected spiders (list in Ctx::slist)
   int64_t rowops;
 };
 
+// LDS pointers are typed as such so that the compiler emits ds_* accesses.
+#define LDSP __attribute__((address_space(3)))
+template <bool LA> struct AdjPtr { using type = uint64_t*; };
+template <> struct AdjPtr<true> { using type = LDSP uint64_t*; };
+
+template <bool LA>  // LA: the working adjacency is in LDS (else in the arena)
 struct Ctx {
   ZxHeader* h;
   uint8_t* base;
   int n, W, ldw, q_in, q_out;
-  uint64_t* adj;     // work adjacency (LDS or global)
-  int8_t* k;         // phases (LDS)
-  int8_t* kc;        // per-selected contribution to neighbour phases (LDS)
-  int16_t* partner;  // pivot partner (LDS)
-  uint64_t* alive;
-  uint64_t* bnd;
-  uint64_t* cand;
-  uint64_t* sel;
-  uint64_t* inm;
-  uint64_t* outm;
-  uint64_t* blocked;
-  uint64_t* omask;   // output-attached spiders
-  int32_t* trace;    // global, 4 int32 per entry
+  typename AdjPtr<LA>::type adj;  // working adjacency
+  LDSP int8_t* k;          // phases
+  LDSP int8_t* kc;         // per-selected contribution to neighbour phases
+  LDSP int16_t* partner;   // pivot partner
+  LDSP int16_t* slist;     // selected spiders of the round, ascending
+  LDSP uint64_t* alive;
+  LDSP uint64_t* bnd;
+  LDSP uint64_t* cand;
+  LDSP uint64_t* sel;
+  LDSP uint64_t* inm;
+  LDSP uint64_t* outm;
+  LDSP uint64_t* blocked;
+  LDSP uint64_t* omask;    // output-attached spiders
+  int32_t* trace;          // global, 4 int32 per entry
   int T, nteams, team, tl;
 };
 
-__device__ __forceinline__ bool bit_of(const uint64_t* m, int v) { return (m[v >> 6] >> (v & 63)) & 1; }
+template <class P>
+__device__ __forceinline__ bool bit_of(P m, int v) { return (m[v >> 6] >> (v & 63)) & 1; }
 
 __device__ __forceinline__ uint64_t wave_shfl64(uint64_t v, int src, int width) {
   return __shfl(v, src, width);
+}
+
+// Lane l's 64-bit value, to every lane.  The builtin returns a signed int:
+// each half is taken as uint32 so that the low word is not sign-extended.
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ int team_size(int W) {
@@ -104,8 +126,8 @@ template <int BS>
 __device__ void block_sync() { __syncthreads(); }
 
 // --------------------------------------------------------------- setup --
-template <int BS>
-__device__ void setup_ctx(Ctx& c, uint8_t* arena, uint8_t* lds, bool lds_adj) {
+template <int BS, bool LA>
+__device__ void setup_ctx(Ctx<LA>& c, uint8_t* arena, uint8_t* lds) {
   c.h = (ZxHeader*)arena;
   c.base = arena;
   c.n = c.h->n;
@@ -114,8 +136,8 @@ __device__ void setup_ctx(Ctx& c, uint8_t* arena, uint8_t* lds, bool lds_adj) {
   c.q_out = c.h->n_out;
   const int n = c.n, W = c.W;
   uint8_t* p = lds;
-  if (lds_adj) {
-    c.adj = (uint64_t*)p;
+  if constexpr (LA) {
+    c.adj = (LDSP uint64_t*)p;
     c.ldw = ldw_lds(W);
     p += lds_adj_bytes(n, W);
   } else {
@@ -123,17 +145,18 @@ __device__ void setup_ctx(Ctx& c, uint8_t* arena, uint8_t* lds, bool lds_adj) {
     c.ldw = W;
   }
   const int64_t kb = (n + 7) & ~7;
-  c.k = (int8_t*)p; p += kb;
-  c.kc = (int8_t*)p; p += kb;
-  c.partner = (int16_t*)p; p += (2 * (int64_t)n + 7) & ~7;
-  c.alive = (uint64_t*)p; p += 8 * W;
-  c.bnd = (uint64_t*)p; p += 8 * W;
-  c.cand = (uint64_t*)p; p += 8 * W;
-  c.sel = (uint64_t*)p; p += 8 * W;
-  c.inm = (uint64_t*)p; p += 8 * W;
-  c.outm = (uint64_t*)p; p += 8 * W;
-  c.blocked = (uint64_t*)p; p += 8 * W;
-  c.omask = (uint64_t*)p; p += 8 * W;
+  c.k = (LDSP int8_t*)p; p += kb;
+  c.kc = (LDSP int8_t*)p; p += kb;
+  c.partner = (LDSP int16_t*)p; p += (2 * (int64_t)n + 7) & ~7;
+  c.slist = (LDSP int16_t*)p; p += (2 * (int64_t)n + 7) & ~7;
+  c.alive = (LDSP uint64_t*)p; p += 8 * W;
+  c.bnd = (LDSP uint64_t*)p; p += 8 * W;
+  c.cand = (LDSP uint64_t*)p; p += 8 * W;
+  c.sel = (LDSP uint64_t*)p; p += 8 * W;
+  c.inm = (LDSP uint64_t*)p; p += 8 * W;
+  c.outm = (LDSP uint64_t*)p; p += 8 * W;
+  c.blocked = (LDSP uint64_t*)p; p += 8 * W;
+  c.omask = (LDSP uint64_t*)p; p += 8 * W;
   c.trace = (int32_t*)(arena + c.h->off_trace);
   c.T = team_size(W);
   c.nteams = BS / c.T;
@@ -141,7 +164,10 @@ __device__ void setup_ctx(Ctx& c, uint8_t* arena, uint8_t* lds, bool lds_adj) {
   c.tl = threadIdx.x % c.T;
 }
 
-__device__ __forceinline__ uint64_t* row_ptr(const Ctx& c, int r) { return c.adj + (size_t)r * c.ldw; }
+template <bool LA>
+__device__ __forceinline__ typename AdjPtr<LA>::type row_ptr(const Ctx<LA>& c, int r) {
+  return c.adj + (size_t)r * c.ldw;
+}
 
 // Sum over threads of v into an LDS 64-bit accumulator.
 __device__ __forceinline__ void block_add(int64_t* acc, int64_t v) {
@@ -149,8 +175,8 @@ __device__ __forceinline__ void block_add(int64_t* acc, int64_t v) {
 }
 
 // Edge count of the work adjacency (rows are already masked to present spiders).
-template <int BS>
-__device__ int64_t count_edges(Ctx& c, Shared& sh) {
+template <int BS, bool LA>
+__device__ int64_t count_edges(Ctx<LA>& c, Shared& sh) {
   if (threadIdx.x == 0) sh.acc64[3] = 0;
   __syncthreads();
   int64_t pc = 0;
@@ -167,12 +193,12 @@ __device__ int64_t count_edges(Ctx& c, Shared& sh) {
 }
 
 // Load a diagram's state.  from_source: SOURCE section, else CURRENT.
-template <int BS>
-__device__ void load_state(Ctx& c, Shared& sh, bool lds_adj, bool from_source) {
+template <int BS, bool LA>
+__device__ void load_state(Ctx<LA>& c, Shared& sh, bool from_source) {
   const int n = c.n, W = c.W, tid = threadIdx.x;
   const uint64_t* src = (const uint64_t*)(c.base + (from_source ? c.h->off_src_adj : c.h->off_adj));
   const int8_t* srcph = (const int8_t*)(c.base + (from_source ? c.h->off_src_phase : c.h->off_phase));
-  if (lds_adj || from_source) {
+  if (LA || from_source) {
     for (int64_t i = tid; i < (int64_t)n * W; i += BS) {
       const int r = (int)(i / W), j = (int)(i % W);
       row_ptr(c, r)[j] = src[i];
@@ -212,17 +238,17 @@ __device__ void load_state(Ctx& c, Shared& sh, bool lds_adj, bool from_source) {
     sh.status = 0;
   }
   __syncthreads();
-  const int64_t e = count_edges<BS>(c, sh);
+  const int64_t e = count_edges<BS, LA>(c, sh);
   if (tid == 0) sh.E = e;
   __syncthreads();
 }
 
 // Write the work state back to the CURRENT section and the header.
-template <int BS>
-__device__ void store_state(Ctx& c, Shared& sh, bool lds_adj) {
+template <int BS, bool LA>
+__device__ void store_state(Ctx<LA>& c, Shared& sh) {
   const int n = c.n, W = c.W, tid = threadIdx.x;
   uint64_t* dst = (uint64_t*)(c.base + c.h->off_adj);
-  if (lds_adj) {
+  if (LA) {
     for (int64_t i = tid; i < (int64_t)n * W; i += BS) {
       const int r = (int)(i / W), j = (int)(i % W);
       dst[i] = row_ptr(c, r)[j];
@@ -253,8 +279,8 @@ __device__ void store_state(Ctx& c, Shared& sh, bool lds_adj) {
 // ------------------------------------------------------- candidate masks --
 // kind 0: local-complementation candidates (interior, k in {2, 6});
 // kind 1: Pauli candidates (interior, k in {0, 4}).  Returns non-empty.
-template <int BS>
-__device__ bool build_candidates(Ctx& c, Shared& sh, int kind) {
+template <int BS, bool LA>
+__device__ bool build_candidates(Ctx<LA>& c, Shared& sh, int kind) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) sh.any = 0;
   __syncthreads();
@@ -275,48 +301,51 @@ __device__ bool build_candidates(Ctx& c, Shared& sh, int kind) {
   return sh.any != 0;
 }
 
-// Lexicographically-first maximal independent set of the candidates (in
-// ascending spider id): a candidate joins when no lower candidate neighbour
-// joined, is excluded when one did.  Sweeps until every candidate is decided.
-template <int BS>
-__device__ void lfmis(Ctx& c, Shared& sh) {
-  const int tid = threadIdx.x, W = c.W;
-  for (int j = tid; j < W; j += BS) {
-    c.inm[j] = 0;
-    c.outm[j] = 0;
-  }
+// Lexicographically-first maximal independent set of the candidates (scan
+// in ascending spider id, take a candidate unless adjacent to one taken).
+// One wavefront, one 64-spider block at a time: lane l checks candidate
+// 64b + l against the spiders taken in earlier blocks (its row AND the taken
+// mask), then the survivors of the block are resolved in ascending order
+// with scalar bit operations on their rows' word b.
+template <int BS, bool LA>
+__device__ void lfmis(Ctx<LA>& c, Shared& sh) {
+  const int W = c.W;
+  for (int j = threadIdx.x; j < W; j += BS) c.sel[j] = 0;
   __syncthreads();
-  for (;;) {
-    if (tid == 0) sh.any = 0;
-    __syncthreads();
-    for (int v = tid; v < c.n; v += BS) {
-      if (!bit_of(c.cand, v) || bit_of(c.inm, v) || bit_of(c.outm, v)) continue;
-      const uint64_t* row = row_ptr(c, v);
-      const int vw = v >> 6;
-      bool out = false, pending = false;
-      for (int j = 0; j <= vw; ++j) {
-        uint64_t low = row[j] & c.cand[j];
-        if (j == vw) low &= (1ull << (v & 63)) - 1;
-        if (low & c.inm[j]) { out = true; break; }
-        if (low & ~c.outm[j]) pending = true;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int b = 0; b < W; ++b) {
+      const uint64_t cw = c.cand[b];
+      if (!cw) continue;
+      const int u = 64 * b + lane;
+      const bool isc = (cw >> lane) & 1;
+      bool free_ = isc;
+      uint64_t inblk = 0;
+      if (isc) {
+        const auto ru = row_ptr(c, u);
+        for (int jj = 0; jj < b; ++jj)
+          if (ru[jj] & c.sel[jj]) { free_ = false; break; }
+        inblk = ru[b];
       }
-      if (out) atomicOr((unsigned long long*)&c.outm[vw], 1ull << (v & 63));
-      else if (!pending) atomicOr((unsigned long long*)&c.inm[vw], 1ull << (v & 63));
-      else sh.any = 1;
+      uint64_t R = __ballot(free_);  // survivors, to resolve in order
+      uint64_t taken = 0;
+      while (R) {
+        const int l = __builtin_ctzll(R);
+        taken |= 1ull << l;
+        R &= ~(readlane64(inblk, l) | (1ull << l));
+      }
+      if (lane == 0) c.sel[b] = taken;
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    if (!sh.any) break;
-    __syncthreads();
   }
-  for (int j = tid; j < W; j += BS) c.sel[j] = c.inm[j];
   __syncthreads();
 }
 
 // Wave 0: lexicographic pivot-pair selection among the Pauli candidates.
 // Writes partner[], sel (both ends), blocked, the trace entries; returns
 // the number of pairs through sh.cnt.
-template <int BS>
-__device__ void select_pivots(Ctx& c, Shared& sh) {
+template <int BS, bool LA>
+__device__ void select_pivots(Ctx<LA>& c, Shared& sh) {
   const int tid = threadIdx.x, W = c.W;
   for (int j = tid; j < W; j += BS) {
     c.sel[j] = 0;
@@ -343,7 +372,7 @@ __device__ void select_pivots(Ctx& c, Shared& sh) {
         // blocked bit of u (owned by lane wi % 64, slot wi / 64)
         uint64_t bw = wave_shfl64(wi < 64 ? blk[0] : blk[1], wi & 63, 64);
         if ((bw >> b) & 1) continue;
-        const uint64_t* ru = row_ptr(c, u);
+        const auto ru = row_ptr(c, u);
         uint64_t t[MAXS];
 #pragma unroll
         for (int s = 0; s < MAXS; ++s) {
@@ -369,7 +398,7 @@ __device__ void select_pivots(Ctx& c, Shared& sh) {
           const uint64_t x = wave_shfl64(t[1], src, 64);
           v = 64 * (64 + src) + __ffsll((long long)x) - 1;
         }
-        const uint64_t* rv = row_ptr(c, v);
+        const auto rv = row_ptr(c, v);
 #pragma unroll
         for (int s = 0; s < MAXS; ++s) {
           const int j = lane + 64 * s;
@@ -383,11 +412,13 @@ __device__ void select_pivots(Ctx& c, Shared& sh) {
         if (lane == 0) {
           c.partner[u] = (int16_t)v;
           c.partner[v] = (int16_t)u;
-          int32_t* e = c.trace + 4 * (int64_t)nt;
-          e[0] = round;
-          e[1] = 1;
-          e[2] = u;
-          e[3] = v;
+          if (c.trace) {
+            int32_t* e = c.trace + 4 * (int64_t)nt;
+            e[0] = round;
+            e[1] = 1;
+            e[2] = u;
+            e[3] = v;
+          }
           c.sel[u >> 6] |= 1ull << (u & 63);
           c.sel[v >> 6] |= 1ull << (v & 63);
         }
@@ -407,16 +438,16 @@ __device__ void select_pivots(Ctx& c, Shared& sh) {
 // LC: acc64[0] = sum deg, acc64[1] = sum deg(deg-1)/2, acc64[2] = phase sum.
 // Pivot: acc64[0] = sum (deg u + deg v - 1), acc64[1] = sum T_p, acc64[2] = phase.
 // Also fills kc[] and, for pivots, swaps each pair's rows into contributions.
-template <int BS>
-__device__ void prepare_round(Ctx& c, Shared& sh, bool pivot, bool graph_only) {
+template <int BS, bool LA>
+__device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_only) {
   const int W = c.W;
-  if (threadIdx.x == 0) sh.acc64[0] = sh.acc64[1] = sh.acc64[2] = 0;
+  if (threadIdx.x == 0) sh.acc64[0] = sh.acc64[1] = sh.acc64[2] = sh.acc64[3] = 0;
   __syncthreads();
   for (int x = c.team; x < c.n; x += c.nteams) {
     if (!bit_of(c.sel, x)) continue;
     const int p = pivot ? c.partner[x] : -1;
     if (pivot && p < x) continue;  // one team per pair, at its lower end
-    uint64_t* rx = row_ptr(c, x);
+    auto rx = row_ptr(c, x);
     int dx = 0, dp = 0, common = 0;
     for (int j = c.tl; j < W; j += c.T) {
       const uint64_t a = rx[j];
@@ -450,7 +481,7 @@ __device__ void prepare_round(Ctx& c, Shared& sh, bool pivot, bool graph_only) {
     }
     if (pivot) {
       // contrib(x) = row_p minus x, contrib(p) = row_x minus p: swap rows
-      uint64_t* rp = row_ptr(c, p);
+      auto rp = row_ptr(c, p);
       for (int j = c.tl; j < W; j += c.T) {
         uint64_t a = rx[j], b = rp[j];
         if (j == (x >> 6)) b &= ~(1ull << (x & 63));
@@ -464,75 +495,168 @@ __device__ void prepare_round(Ctx& c, Shared& sh, bool pivot, bool graph_only) {
   (void)graph_only;
 }
 
-// The rank-|S| update of every present row outside S.
-template <int BS>
-__device__ void apply_round(Ctx& c, Shared& sh, bool pivot, bool graph_only) {
-  const int W = c.W, T = c.T, tl = c.tl;
-  for (int w = c.team; w < c.n; w += c.nteams) {
-    if (!bit_of(c.alive, w) || bit_of(c.sel, w)) continue;
-    uint64_t* row = row_ptr(c, w);
-    uint64_t mw[MAXS], acc[MAXS];
+// List the words of the selected set (sh.nsw entries in c.blocked) and the
+// selected spiders in ascending order (sh.ns entries in c.slist).
+template <int BS, bool LA>
+__device__ void collect_swords(Ctx<LA>& c, Shared& sh) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    LDSP int32_t* sw = (LDSP int32_t*)c.blocked;
+    int cnt = 0, ns = 0;
+    for (int j0 = 0; j0 < c.W; j0 += 64) {
+      const int j = j0 + lane;
+      const uint64_t wd = j < c.W ? c.sel[j] : 0;
+      const bool nz = wd != 0;
+      const uint64_t b = __ballot(nz);
+      if (nz) sw[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] = j;
+      cnt += __popcll(b);
+      // ascending spider list: exclusive prefix of the per-word popcounts
+      const int pc = __popcll(wd);
+      int ex = 0, tot = 0;
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      const int j = tl + s * T;
-      mw[s] = j < W ? row[j] & c.sel[j] : 0;
-      acc[s] = 0;
+      for (int bit = 0; bit < 7; ++bit) {
+        const uint64_t bb = __ballot((pc >> bit) & 1);
+        ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0)) << bit;
+        tot += __popcll(bb) << bit;
+      }
+      uint64_t m = wd;
+      int pos = ns + ex;
+      while (m) {
+        const int bit = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        c.slist[pos++] = (int16_t)(64 * j + bit);
+      }
+      ns += tot;
     }
-    int dk = 0;
-    bool any = false;
+    if (lane == 0) {
+      sh.nsw = cnt;
+      sh.ns = ns;
+    }
+  }
+  __syncthreads();
+}
+
+// The rank-|S| update of every present row outside S, by (row, word)
+// threads.  Also sums into sh.acc64[3] the popcounts of every present
+// non-selected row with the selected columns masked out (twice the edge
+// count after the round); selected columns are cleared by delete_selected.
+//
+// Few selected spiders (the common case): spider-major.  A thread keeps the
+// words of up to MAXI rows in registers for the whole round; for each
+// selected x it tests "w ~ x" as bit x of row w (the adjacency is symmetric,
+// so this is also "x ~ w") and XORs in x's contribution word.  Rows are
+// only written at the end, and all loads are independent.
+// Many selected spiders: row-major, walking the selected bits of each row.
+constexpr int MAXI = 4;
+constexpr int SPIDER_MAJOR_MAX = 64;
+
+template <int BS, bool LA>
+__device__ void apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+  const int W = c.W, n = c.n, nsw = sh.nsw, ns = sh.ns;
+  const int rows_per = BS / W;
+  const int tw = threadIdx.x / W, j = threadIdx.x - tw * W;
+  int64_t pc = 0;
+  if (tw < rows_per && ns <= SPIDER_MAJOR_MAX) {
+    for (int w0 = tw; w0 < n; w0 += rows_per * MAXI) {
+      uint64_t v[MAXI];
+      int dk[MAXI];
+      uint32_t act = 0;
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      if (s * T >= W) break;
-      for (int l = 0; l < T; ++l) {
-        const int i = s * T + l;
-        if (i >= W) break;
-        uint64_t mi = wave_shfl64(mw[s], l, T);
-        while (mi) {
-          const int b = __ffsll((long long)mi) - 1;
-          mi &= mi - 1;
-          const int x = 64 * i + b;
-          const uint64_t* rx = row_ptr(c, x);
+      for (int i = 0; i < MAXI; ++i) {
+        const int w = w0 + i * rows_per;
+        const bool a = w < n && bit_of(c.alive, w) && !bit_of(c.sel, w);
+        act |= (a ? 1u : 0u) << i;
+        v[i] = a ? row_ptr(c, w)[j] : 0;
+        dk[i] = 0;
+      }
+      if (act) {
+        for (int sidx = 0; sidx < ns; ++sidx) {
+          const int x = c.slist[sidx];
+          const uint64_t val = row_ptr(c, x)[j];
+          const int kx = c.kc[x];
+          const int px = pivot ? c.partner[x] : 0;
 #pragma unroll
-          for (int s2 = 0; s2 < MAXS; ++s2) {
-            const int j = tl + s2 * T;
-            if (j < W) acc[s2] ^= rx[j];
+          for (int i = 0; i < MAXI; ++i) {
+            if (!((act >> i) & 1)) continue;
+            const auto rw = row_ptr(c, w0 + i * rows_per);
+            if ((rw[x >> 6] >> (x & 63)) & 1) {
+              v[i] ^= val;
+              if (j == 0) {
+                dk[i] += kx;
+                if (pivot && ((rw[px >> 6] >> (px & 63)) & 1)) dk[i] += 2;  // adjacent to both ends
+              }
+            }
           }
-          if (!graph_only) {
+        }
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+          if (!((act >> i) & 1)) continue;
+          const int w = w0 + i * rows_per;
+          auto rw = row_ptr(c, w);
+          uint64_t x = v[i];
+          if (j == (w >> 6)) x &= ~(1ull << (w & 63));
+          if (x != rw[j]) rw[j] = x;
+          pc += __popcll(x & ~c.sel[j]);
+          if (j == 0 && dk[i]) c.k[w] = (int8_t)((c.k[w] + dk[i]) & 7);
+        }
+      }
+    }
+  } else if (tw < rows_per) {
+    const LDSP int32_t* sw = (const LDSP int32_t*)c.blocked;
+    for (int w = tw; w < n; w += rows_per) {
+      if (!bit_of(c.alive, w) || bit_of(c.sel, w)) continue;
+      auto row = row_ptr(c, w);
+      uint64_t acc = 0;
+      int dk = 0;
+      for (int q = 0; q < nsw; ++q) {
+        const int kw = sw[q];
+        uint64_t msk = row[kw] & c.sel[kw];
+        while (msk) {
+          const int b = __ffsll((long long)msk) - 1;
+          msk &= msk - 1;
+          const int x = 64 * kw + b;
+          acc ^= row_ptr(c, x)[j];
+          if (j == 0) {
             dk += c.kc[x];
             if (pivot) {
               const int p = c.partner[x];
               if ((row[p >> 6] >> (p & 63)) & 1) dk += 2;  // adjacent to both ends
             }
           }
-          any = true;
         }
       }
+      const uint64_t old = row[j];
+      uint64_t v = old ^ acc;
+      if (j == (w >> 6)) v &= ~(1ull << (w & 63));
+      if (v != old) row[j] = v;
+      pc += __popcll(v & ~c.sel[j]);
+      if (j == 0 && dk) c.k[w] = (int8_t)((c.k[w] + dk) & 7);
     }
-    if (!any) continue;
-    // every lane of the team has read `row` above (mw, partner tests)
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      const int j = tl + s * T;
-      if (j < W) {
-        uint64_t v = row[j] ^ acc[s];
-        if (!graph_only) v &= ~c.sel[j];
-        if (j == (w >> 6)) v &= ~(1ull << (w & 63));
-        row[j] = v;
-      }
-    }
-    if (!graph_only && tl == 0) c.k[w] = (int8_t)((c.k[w] + dk) & 7);
   }
+  __syncthreads();  // the spider-major path reads rows it does not own until here
+  block_add(&sh.acc64[3], pc);
   __syncthreads();
 }
 
-// Delete the selected spiders (rows zeroed, alive cleared, phase 0).
-template <int BS>
-__device__ void delete_selected(Ctx& c) {
-  const int W = c.W;
-  for (int x = c.team; x < c.n; x += c.nteams) {
+// Delete the selected spiders: clear their columns in every other row, zero
+// their rows, clear alive, phase 0.
+template <int BS, bool LA>
+__device__ void delete_selected(Ctx<LA>& c, Shared& sh) {
+  const int W = c.W, n = c.n, nsw = sh.nsw;
+  const LDSP int32_t* sw = (const LDSP int32_t*)c.blocked;
+  if (nsw > 0) {
+    for (int it = threadIdx.x; it < n * nsw; it += BS) {
+      const int w = it / nsw, q = it - w * nsw;
+      const int kw = sw[q];
+      auto row = row_ptr(c, w);
+      if (bit_of(c.sel, w)) continue;
+      const uint64_t v = row[kw];
+      if (v & c.sel[kw]) row[kw] = v & ~c.sel[kw];
+    }
+  }
+  for (int x = c.team; x < n; x += c.nteams) {
     if (!bit_of(c.sel, x)) continue;
-    uint64_t* rx = row_ptr(c, x);
+    auto rx = row_ptr(c, x);
     for (int j = c.tl; j < W; j += c.T) rx[j] = 0;
     if (c.tl == 0) c.k[x] = 0;
   }
@@ -541,12 +665,13 @@ __device__ void delete_selected(Ctx& c) {
   __syncthreads();
 }
 
-// Scalar and counters after a ZX round (not graph-only).
-template <int BS>
-__device__ void finish_round(Ctx& c, Shared& sh, bool pivot, int removed) {
-  const int64_t e_before = sh.E;
-  const int64_t e_after = count_edges<BS>(c, sh);
+// Scalar and counters after a ZX round; the edge count after the round comes
+// from apply_round (sh.acc64[3] = twice the count).
+template <int BS, bool LA>
+__device__ void finish_round(Ctx<LA>& c, Shared& sh, int removed) {
   if (threadIdx.x == 0) {
+    const int64_t e_before = sh.E;
+    const int64_t e_after = sh.acc64[3] / 2;
     sh.pow_sqrt2 += (e_after - e_before) + removed;
     sh.phase8 = (int32_t)((sh.phase8 + sh.acc64[2]) & 7);
     // edges toggled on = (pairs toggled + change among the other spiders) / 2
@@ -555,13 +680,12 @@ __device__ void finish_round(Ctx& c, Shared& sh, bool pivot, int removed) {
     sh.E = e_after;
   }
   __syncthreads();
-  (void)pivot;
 }
 
 // Trace entries of a local-complementation round (ascending spider id).
-template <int BS>
-__device__ void trace_lc_round(Ctx& c, Shared& sh) {
-  if (threadIdx.x < 64) {
+template <int BS, bool LA>
+__device__ void trace_lc_round(Ctx<LA>& c, Shared& sh) {
+  if (c.trace && threadIdx.x < 64) {
     const int lane = threadIdx.x;
     int base = sh.n_trace;
     for (int j0 = 0; j0 < c.W; j0 += 64) {
@@ -592,13 +716,35 @@ __device__ void trace_lc_round(Ctx& c, Shared& sh) {
   __syncthreads();
 }
 
+#include "policy_dev.h"
+
 // ----------------------------------------------------------- simplify --
-template <int BS>
-__device__ void simplify_rounds(Ctx& c, Shared& sh) {
+// Rounds until the fixed point, or until sh.round reaches max_rounds (> 0).
+// LEARN: candidates taken in the network's priority order (pol), else the
+// canonical order.
+template <int BS, bool LA, bool LEARN>
+__device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds) {
+  // every round deletes at least one spider: more than n + 1 rounds from
+  // here would be a defect, reported instead of looping on
+  const int round_cap = sh.round + c.n + 1;
   // local-complementation rounds
   for (;;) {
-    if (!build_candidates<BS>(c, sh, 0)) break;
-    lfmis<BS>(c, sh);
+    if (max_rounds > 0 && sh.round >= max_rounds) return;
+    if (sh.round > round_cap) {
+      sh.status = ZX_EDEVICE;
+      return;
+    }
+    if (!build_candidates<BS, LA>(c, sh, 0)) break;
+    if constexpr (LEARN) {
+      const int C = list_lc<BS, LA>(c, sh, *pol);
+      const float invN = pauli_mask_and_scale<BS, LA>(c, sh);
+      policy_score<BS, LA>(c, *pol, C, invN);
+      __syncthreads();
+      sort_keys_desc<BS>(*pol, C);
+      select_lc_priority<BS, LA>(c, sh, *pol, C);
+    } else {
+      lfmis<BS, LA>(c, sh);
+    }
     if (threadIdx.x == 0) sh.cnt = 0;
     __syncthreads();
     int cnt = 0;
@@ -606,24 +752,31 @@ __device__ void simplify_rounds(Ctx& c, Shared& sh) {
     if (cnt) atomicAdd(&sh.cnt, cnt);
     __syncthreads();
     const int removed = sh.cnt;
-    trace_lc_round<BS>(c, sh);
-    prepare_round<BS>(c, sh, false, false);
-    apply_round<BS>(c, sh, false, false);
-    delete_selected<BS>(c);
-    finish_round<BS>(c, sh, false, removed);
+    trace_lc_round<BS, LA>(c, sh);
+    prepare_round<BS, LA>(c, sh, false, false);
+    collect_swords<BS, LA>(c, sh);
+    apply_round<BS, LA>(c, sh, false);
+    delete_selected<BS, LA>(c, sh);
+    finish_round<BS, LA>(c, sh, removed);
     if (threadIdx.x == 0) sh.round++;
     __syncthreads();
   }
   // pivot rounds
   for (;;) {
-    if (!build_candidates<BS>(c, sh, 1)) break;
-    select_pivots<BS>(c, sh);
+    if (max_rounds > 0 && sh.round >= max_rounds) return;
+    if (sh.round > round_cap) {
+      sh.status = ZX_EDEVICE;
+      return;
+    }
+    if (!build_candidates<BS, LA>(c, sh, 1)) break;
+    select_pivots<BS, LA>(c, sh);
     const int npairs = sh.cnt;
     if (npairs == 0) break;
-    prepare_round<BS>(c, sh, true, false);
-    apply_round<BS>(c, sh, true, false);
-    delete_selected<BS>(c);
-    finish_round<BS>(c, sh, true, 2 * npairs);
+    prepare_round<BS, LA>(c, sh, true, false);
+    collect_swords<BS, LA>(c, sh);
+    apply_round<BS, LA>(c, sh, true);
+    delete_selected<BS, LA>(c, sh);
+    finish_round<BS, LA>(c, sh, 2 * npairs);
     for (int v = threadIdx.x; v < c.n; v += BS)
       if (bit_of(c.sel, v)) c.partner[v] = -1;
     if (threadIdx.x == 0) sh.round++;
@@ -631,113 +784,154 @@ __device__ void simplify_rounds(Ctx& c, Shared& sh) {
   }
 }
 
+// Minimum over the wavefront of non-negative 31-bit values, by bisection on
+// ballots (no cross-lane data movement).
+__device__ __forceinline__ int wave_min31(int v) {
+  uint64_t active = __ballot(true);
+  int res = 0;
+  for (int b = 30; b >= 0; --b) {
+    const uint64_t zeros = __ballot(((v >> b) & 1) == 0) & active;
+    if (zeros) active = zeros;
+    else res |= 1 << b;
+  }
+  return res;
+}
+
+// Sum over the wavefront of values in [0, 15].
+__device__ __forceinline__ int wave_sum4(int v) {
+  int tot = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) tot += __popcll(__ballot((v >> b) & 1)) << b;
+  return tot;
+}
+
 // Output frontier: rows = spiders of outputs 0..q-1, columns = spider ids,
 // bit c = edge to a present spider c not attached to an output; then
-// Gauss-Jordan with the lowest-index pivot row, counting row additions.
-// M: q x W words (LDS or global).
-template <int BS>
-__device__ void frontier(Ctx& c, Shared& sh, uint64_t* M) {
+// Gauss-Jordan with the lowest-index pivot row (swapped into place),
+// counting row additions.  M: q x W words (LDS or global).  The elimination
+// runs in one wavefront: lane l owns rows l, l + 64, ...; the next pivot is
+// the minimum (column, row) key, found by ballot bisection.
+// from_work: rows come from the working adjacency (else from the arena's
+// CURRENT section, written back by store_state); write_out: store the
+// pivots, the reduced frontier and the header fields (else only sh.rank and
+// sh.rowops are set).
+template <int BS, bool LA>
+__device__ void frontier(Ctx<LA>& c, Shared& sh, uint64_t* M, bool from_work, bool write_out) {
   const int q = c.q_out, W = c.W, tid = threadIdx.x;
   const int32_t* outs = (const int32_t*)(c.base + c.h->off_out);
+  const uint64_t* adj = (const uint64_t*)(c.base + c.h->off_adj);
   for (int64_t i = tid; i < (int64_t)q * W; i += BS) {
     const int r = (int)(i / W), j = (int)(i % W);
-    M[i] = row_ptr(c, outs[r])[j] & c.alive[j] & ~c.omask[j];
-  }
-  if (tid == 0) {
-    sh.rank = 0;
-    sh.rowops = 0;
+    const uint64_t x = from_work ? row_ptr(c, outs[r])[j] : adj[(size_t)outs[r] * W + j];
+    M[i] = x & c.alive[j] & ~c.omask[j];
   }
   __syncthreads();
   int32_t* fpiv = (int32_t*)(c.base + c.h->off_fpiv);
-  int cur = 0, cmin = 0;
-  while (cur < q) {
-    if (tid == 0) sh.key = 0x7fffffff;
-    __syncthreads();
-    // lowest (column, row) over rows >= cur
-    for (int r = cur + tid; r < q; r += BS) {
-      const uint64_t* mr = M + (size_t)r * W;
-      for (int j = cmin >> 6; j < W; ++j) {
-        if (mr[j]) {
-          const int col = 64 * j + __ffsll((long long)mr[j]) - 1;
-          atomicMin(&sh.key, (col << 15) | r);
-          break;
+  if (tid < 64) {
+    const int lane = tid;
+    int cur = 0, cmin = 0;
+    int64_t ops = 0;
+    constexpr int NOKEY = 0x7fffffff;
+    while (cur < q) {
+      int best = NOKEY;
+      for (int p = lane; p < q; p += 64) {
+        if (p < cur) continue;
+        const uint64_t* mr = M + (size_t)p * W;
+        for (int j = cmin >> 6; j < W; ++j) {
+          const uint64_t x = mr[j];
+          if (x) {
+            const int key = ((64 * j + __ffsll((long long)x) - 1) << 15) | p;
+            best = key < best ? key : best;
+            break;
+          }
         }
       }
-    }
-    __syncthreads();
-    const int key = sh.key;
-    if (key == 0x7fffffff) break;
-    const int col = key >> 15, r = key & 0x7fff;
-    if (r != cur) {
-      for (int j = tid; j < W; j += BS) {
-        const uint64_t a = M[(size_t)r * W + j];
-        M[(size_t)r * W + j] = M[(size_t)cur * W + j];
-        M[(size_t)cur * W + j] = a;
+      const int mn = wave_min31(best);
+      if (mn == NOKEY) break;
+      const int col = mn >> 15, r = mn & 0x7fff;
+      if (r != cur) {
+        for (int j = lane; j < W; j += 64) {
+          const uint64_t a = M[(size_t)r * W + j];
+          M[(size_t)r * W + j] = M[(size_t)cur * W + j];
+          M[(size_t)cur * W + j] = a;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
       }
-    }
-    __syncthreads();
-    int ops = 0;
-    const uint64_t* pr = M + (size_t)cur * W;
-    for (int i = tid; i < q; i += BS) {
-      if (i == cur) continue;
-      uint64_t* mi = M + (size_t)i * W;
-      if ((mi[col >> 6] >> (col & 63)) & 1) {
-        for (int j = 0; j < W; ++j) mi[j] ^= pr[j];
-        ++ops;
+      const uint64_t* pr = M + (size_t)cur * W;
+      int cnt = 0;
+      for (int p = lane; p < q; p += 64) {
+        if (p == cur) continue;
+        uint64_t* mr = M + (size_t)p * W;
+        if ((mr[col >> 6] >> (col & 63)) & 1) {
+          for (int j = 0; j < W; ++j) mr[j] ^= pr[j];
+          ++cnt;
+        }
       }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      ops += wave_sum4(cnt);
+      if (lane == 0 && write_out) fpiv[cur] = col;
+      ++cur;
+      cmin = col + 1;
     }
-    if (ops) atomicAdd((unsigned long long*)&sh.rowops, (unsigned long long)ops);
-    if (tid == 0) fpiv[cur] = col;
-    ++cur;
-    cmin = col + 1;
-    __syncthreads();
+    if (write_out)
+      for (int j = cur + lane; j < q; j += 64) fpiv[j] = -1;
+    if (lane == 0) {
+      sh.rank = cur;
+      sh.rowops = ops;
+    }
   }
+  __syncthreads();
+  if (!write_out) return;
   uint64_t* front = (uint64_t*)(c.base + c.h->off_front);
   if (M != front)
     for (int64_t i = tid; i < (int64_t)q * W; i += BS) front[i] = M[i];
-  for (int j = cur + tid; j < q; j += BS) fpiv[j] = -1;
   if (tid == 0) {
-    c.h->rank = cur;
+    c.h->rank = sh.rank;
     c.h->rowops = sh.rowops;
   }
   __syncthreads();
 }
 
-// One diagram, start to finish.
-template <int BS>
-__device__ void process_diagram(uint8_t* arena, uint8_t* lds, int64_t lds_cap, int extract,
-                                Shared& sh) {
+struct SimpArgs {
+  int64_t lds_cap;
+  int32_t extract;
+  int32_t max_rounds;  // 0: to the fixed point
+  int32_t resume;      // continue from the CURRENT diagram
+  int32_t pad;
+  const uint16_t* wbf;  // learned policy: network (bf16 copy)
+  const float* param;   // learned policy: network (fp32 master)
+};
+
+// One diagram, start to finish, with the adjacency in LDS (LA) or the arena.
+template <int BS, bool LA, bool LEARN>
+__device__ void run_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Shared& sh) {
   ZxHeader* h = (ZxHeader*)arena;
-  const int n = h->n, W = h->W;
-  const int64_t aux = aux_bytes(n, W);
-  if (h->magic != ZX_MAGIC || W > MAXW || n > 32767 || aux > lds_cap) {
-    if (threadIdx.x == 0) zx_dev_fail(&h->status, ZX_ECAPACITY);
-    __syncthreads();
-    return;
+  Ctx<LA> c;
+  setup_ctx<BS, LA>(c, arena, lds);
+  load_state<BS, LA>(c, sh, !a.resume);
+  if (a.resume && threadIdx.x == 0) {
+    sh.n_trace = h->n_trace;
+    sh.round = h->rounds;
   }
-  const bool lds_adj = lds_adj_bytes(n, W) + aux <= lds_cap;
-  Ctx c;
-  setup_ctx<BS>(c, arena, lds, lds_adj);
-  load_state<BS>(c, sh, lds_adj, true);
-  simplify_rounds<BS>(c, sh);
-  store_state<BS>(c, sh, lds_adj);
+  __syncthreads();
+  Pol pol;
+  if constexpr (LEARN)
+    setup_pol<BS>(pol, lds + (LA ? lds_adj_bytes(c.n, c.W) : 0) + aux_bytes(c.n, c.W), c.n, a.wbf,
+                  a.param);
+  simplify_rounds<BS, LA, LEARN>(c, sh, &pol, a.max_rounds);
+  store_state<BS, LA>(c, sh);
   if (threadIdx.x == 0) {
     h->n_trace = sh.n_trace;
     h->rounds = sh.round;
+    if (sh.status) zx_dev_fail(&h->status, sh.status);
   }
-  if (extract && c.q_out > 0) {
+  if (a.extract && c.q_out > 0) {
     // LDS mode: the adjacency region is free once written back
-    uint64_t* M = lds_adj ? (uint64_t*)lds : (uint64_t*)(arena + h->off_front);
-    if (lds_adj) {
-      // frontier rows must be built from the adjacency: copy them out first
-      __syncthreads();
-    }
-    if (lds_adj) {
-      // rebuild rows from the global copy just written
-      c.adj = (uint64_t*)(arena + h->off_adj);
-      c.ldw = W;
-    }
-    frontier<BS>(c, sh, M);
+    uint64_t* M = LA ? (uint64_t*)lds : (uint64_t*)(arena + h->off_front);
+    __syncthreads();
+    frontier<BS, LA>(c, sh, M, false, true);
   } else if (threadIdx.x == 0) {
     h->rank = -1;
     h->rowops = 0;
@@ -745,14 +939,28 @@ __device__ void process_diagram(uint8_t* arena, uint8_t* lds, int64_t lds_cap, i
   __syncthreads();
 }
 
+template <int BS, bool LEARN>
+__device__ void process_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Shared& sh) {
+  ZxHeader* h = (ZxHeader*)arena;
+  const int n = h->n, W = h->W;
+  const int64_t aux = aux_bytes(n, W) + (LEARN ? pol_bytes(n, BS) : 0);
+  if (h->magic != ZX_MAGIC || n < 1 || W != (n + 63) / 64 || W > MAXW || n > 32767 || aux > a.lds_cap) {
+    if (threadIdx.x == 0) zx_dev_fail(&h->status, ZX_ECAPACITY);
+    __syncthreads();
+    return;
+  }
+  if (lds_adj_bytes(n, W) + aux <= a.lds_cap) run_diagram<BS, true, LEARN>(arena, lds, a, sh);
+  else run_diagram<BS, false, LEARN>(arena, lds, a, sh);
+}
+
 struct Queue {
   uint32_t next;
   uint32_t pad[63];
 };
 
-template <int BS>
+template <int BS, bool LEARN>
 __global__ __launch_bounds__(BS) void simplify_kernel(uint8_t* const* table, int32_t n_graphs,
-                                                      Queue* q, int64_t lds_cap, int extract) {
+                                                      Queue* q, SimpArgs a) {
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
   for (;;) {
@@ -761,7 +969,123 @@ __global__ __launch_bounds__(BS) void simplify_kernel(uint8_t* const* table, int
     const int idx = sh.idx;
     __syncthreads();
     if (idx >= n_graphs) break;
-    process_diagram<BS>(table[idx], smem_dyn, lds_cap, extract, sh);
+    process_diagram<BS, LEARN>(table[idx], smem_dyn, a, sh);
+  }
+}
+
+// Rollouts: item i = (state i / per_state, candidate slot i % per_state).
+// The state (CURRENT section of its arena) is only read; the work copy is in
+// LDS, the frontier matrix in this block's slice of mbuf.
+struct RollArgs {
+  uint8_t* const* states;
+  int32_t n_items;
+  int32_t per_state;
+  int64_t lds_cap;
+  uint64_t* mbuf;
+  int64_t mbuf_words;  // per block
+  int64_t* cost;
+  int64_t* fill;
+  int32_t* move;
+  uint16_t* feats;
+};
+
+// adjacency + auxiliary arrays + candidate list + one wavefront's features
+__host__ __device__ inline int64_t roll_lds_bytes(int n, int W) {
+  return lds_adj_bytes(n, W) + aux_bytes(n, W) + 16 + (int64_t)pol_cap(n) * 4 + 32 * zxmlp::IN * 2;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
+  extern __shared__ __align__(16) uint8_t smem_dyn[];
+  __shared__ Shared sh;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sh.idx = (int32_t)atomicAdd(&q->next, 1u);
+    __syncthreads();
+    const int idx = sh.idx;
+    __syncthreads();
+    if (idx >= a.n_items) break;
+    const int si = idx / a.per_state, k = idx - si * a.per_state;
+    uint8_t* arena = a.states[si];
+    const ZxHeader* h = (const ZxHeader*)arena;
+    const int n = h->n, W = h->W;
+    const bool fits = h->magic == ZX_MAGIC && n >= 1 && W == (n + 63) / 64 && W <= MAXW && n <= 32767 &&
+                      roll_lds_bytes(n, W) <= a.lds_cap &&
+                      (int64_t)h->n_out * W <= a.mbuf_words;
+    if (!fits) {
+      if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = 0;
+      if (tid == 0) {
+        a.cost[idx] = -3;
+        a.fill[idx] = 0;
+        a.move[3 * (int64_t)idx] = -1;
+        a.move[3 * (int64_t)idx + 1] = -1;
+        a.move[3 * (int64_t)idx + 2] = -1;
+      }
+      continue;
+    }
+    Ctx<true> c;
+    setup_ctx<BS, true>(c, arena, smem_dyn);
+    c.trace = nullptr;
+    Pol pol;
+    pol.wbf = nullptr;
+    pol.param = nullptr;
+    pol.cap = pol_cap(n);
+    pol.key = nullptr;
+    uint8_t* pa = align16(smem_dyn + lds_adj_bytes(n, W) + aux_bytes(n, W));
+    pol.list = (LDSP uint32_t*)pa;
+    pol.fbuf = (LDSP uint16_t*)(pa + (int64_t)pol.cap * 4);
+    load_state<BS, true>(c, sh, false);
+    // candidates of an LC round; a state past its LC phase has none here
+    int C = 0;
+    if (build_candidates<BS, true>(c, sh, 0)) C = list_lc<BS, true>(c, sh, pol);
+    if (k >= C) {
+      if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = 0;
+      if (tid == 0) {
+        a.cost[idx] = -1;
+        a.fill[idx] = 0;
+        a.move[3 * (int64_t)idx] = -1;
+        a.move[3 * (int64_t)idx + 1] = -1;
+        a.move[3 * (int64_t)idx + 2] = -1;
+      }
+      continue;
+    }
+    const int ci = C <= a.per_state ? k : (int)((int64_t)k * C / a.per_state);
+    const int u = (int)pol.list[ci];
+    const float invN = pauli_mask_and_scale<BS, true>(c, sh);
+    if (tid < 64) {
+      candidate_features(c, u, invN, pol.fbuf);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = pol.fbuf[tid];
+    }
+    for (int j = tid; j < W; j += BS) c.sel[j] = 0;
+    __syncthreads();
+    const int64_t fill0 = sh.fill_in;
+    if (tid == 0) {
+      a.move[3 * (int64_t)idx] = 0;
+      a.move[3 * (int64_t)idx + 1] = u;
+      a.move[3 * (int64_t)idx + 2] = -1;
+      c.sel[u >> 6] |= 1ull << (u & 63);
+    }
+    __syncthreads();
+    // the candidate as a one-rewrite round, then the greedy schedule
+    prepare_round<BS, true>(c, sh, false, false);
+    collect_swords<BS, true>(c, sh);
+    apply_round<BS, true>(c, sh, false);
+    delete_selected<BS, true>(c, sh);
+    finish_round<BS, true>(c, sh, 1);
+    simplify_rounds<BS, true, false>(c, sh, nullptr, 0);
+    if (c.q_out > 0) {
+      frontier<BS, true>(c, sh, a.mbuf + (int64_t)blockIdx.x * a.mbuf_words, true, false);
+    } else if (tid == 0) {
+      sh.rowops = 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      a.cost[idx] = sh.status ? -4 : sh.E + sh.rowops;
+      a.fill[idx] = sh.fill_in - fill0;
+    }
+    __syncthreads();
   }
 }
 
@@ -776,9 +1100,10 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
   ZxHeader* h = (ZxHeader*)arena;
-  Ctx c;
-  setup_ctx<BS>(c, arena, smem_dyn, false);
-  load_state<BS>(c, sh, false, false);
+  constexpr bool LA = false;
+  Ctx<LA> c;
+  setup_ctx<BS, LA>(c, arena, smem_dyn);
+  load_state<BS, LA>(c, sh, false);
   // precondition
   if (threadIdx.x == 0) {
     bool ok = u >= 0 && u < c.n && bit_of(c.alive, u);
@@ -817,7 +1142,7 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
       __syncthreads();
       for (int w = c.team; w < c.n; w += c.nteams) {
         if (w == u || w == v || !bit_of(c.alive, w)) continue;
-        uint64_t* row = row_ptr(c, w);
+        auto row = row_ptr(c, w);
         const bool nu = (row[u >> 6] >> (u & 63)) & 1, nv = (row[v >> 6] >> (v & 63)) & 1;
         if (!nu && !nv) continue;
         __builtin_amdgcn_wave_barrier();
@@ -836,7 +1161,7 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
       __syncthreads();
       for (int w = c.team; w < c.n; w += c.nteams) {
         if (!bit_of(c.inm, w)) continue;
-        uint64_t* row = row_ptr(c, w);
+        auto row = row_ptr(c, w);
         for (int j = c.tl; j < c.W; j += c.T) {
           uint64_t x = row[j] ^ c.inm[j];
           if (j == (w >> 6)) x &= ~(1ull << (w & 63));
@@ -845,16 +1170,17 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
       }
       __syncthreads();
     }
-    const int64_t e = count_edges<BS>(c, sh);
+    const int64_t e = count_edges<BS, LA>(c, sh);
     if (threadIdx.x == 0) sh.E = e;
     __syncthreads();
   } else {
-    prepare_round<BS>(c, sh, pivot != 0, false);
-    apply_round<BS>(c, sh, pivot != 0, false);
-    delete_selected<BS>(c);
-    finish_round<BS>(c, sh, pivot != 0, pivot ? 2 : 1);
+    prepare_round<BS, LA>(c, sh, pivot != 0, false);
+    collect_swords<BS, LA>(c, sh);
+    apply_round<BS, LA>(c, sh, pivot != 0);
+    delete_selected<BS, LA>(c, sh);
+    finish_round<BS, LA>(c, sh, pivot ? 2 : 1);
   }
-  store_state<BS>(c, sh, false);
+  store_state<BS, LA>(c, sh);
 }
 
 __global__ void reset_kernel(uint8_t* arena) {
@@ -915,16 +1241,15 @@ const Variant kVariants[] = {
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 1;
 
-template <int BS>
-zx_status launch_simplify_bs(uint8_t* const* table, int32_t n, Queue* q, int64_t lds_cap,
-                             int extract, hipStream_t s) {
+template <int BS, bool LEARN>
+zx_status launch_simplify_bs(uint8_t* const* table, int32_t n, Queue* q, const SimpArgs& a,
+                             hipStream_t s) {
   const ZxDevice* d = zx_device();
   if (!d) return ZX_EDEVICE;
-  ZX_HIP(hipFuncSetAttribute((const void*)simplify_kernel<BS>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap));
+  const void* fn = (const void*)simplify_kernel<BS, LEARN>;
+  ZX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_cap));
   int per_cu = 0;
-  ZX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)simplify_kernel<BS>, BS,
-                                                      (size_t)lds_cap));
+  ZX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BS, (size_t)a.lds_cap));
   if (per_cu < 1) {
     zx_set_error("simplify variant does not fit a CU");
     return ZX_ECAPACITY;
@@ -932,17 +1257,21 @@ zx_status launch_simplify_bs(uint8_t* const* table, int32_t n, Queue* q, int64_t
   int grid = per_cu * d->n_cu;
   if (grid > n) grid = n;
   hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, s, q);
-  hipLaunchKernelGGL(simplify_kernel<BS>, dim3(grid), dim3(BS), (size_t)lds_cap, s, table, n, q,
-                     lds_cap, extract);
+  hipLaunchKernelGGL((simplify_kernel<BS, LEARN>), dim3(grid), dim3(BS), (size_t)a.lds_cap, s, table, n,
+                     q, a);
   ZX_HIP(hipGetLastError());
   return ZX_OK;
 }
 
-zx_status launch_simplify(int variant, uint8_t* const* table, int32_t n, Queue* q, int extract,
-                          hipStream_t s) {
+zx_status launch_simplify(int variant, uint8_t* const* table, int32_t n, Queue* q, SimpArgs a,
+                          bool learned, hipStream_t s) {
   const Variant& v = kVariants[variant];
-  if (v.bs == 256) return launch_simplify_bs<256>(table, n, q, v.lds_cap, extract, s);
-  return launch_simplify_bs<512>(table, n, q, v.lds_cap, extract, s);
+  a.lds_cap = v.lds_cap;
+  if (v.bs == 256)
+    return learned ? launch_simplify_bs<256, true>(table, n, q, a, s)
+                   : launch_simplify_bs<256, false>(table, n, q, a, s);
+  return learned ? launch_simplify_bs<512, true>(table, n, q, a, s)
+                 : launch_simplify_bs<512, false>(table, n, q, a, s);
 }
 
 // autotuner cache: (device name, size class) -> variant
@@ -1036,32 +1365,89 @@ static std::string size_class(const zx_batch* b) {
   return buf;
 }
 
-static bool variant_fits(const zx_batch* b, int v) {
+static bool variant_fits_n(int max_n, int v, bool learned) {
   const ZxDevice* d = zx_device();
   if (!d || kVariants[v].lds_cap > (int64_t)d->lds_per_block) return false;
-  const int W = (b->max_n + 63) / 64;
-  return aux_bytes(b->max_n, W) <= kVariants[v].lds_cap;
+  if (max_n > 32767 || (max_n + 63) / 64 > MAXW) return false;
+  const int W = (max_n + 63) / 64;
+  const int64_t need = aux_bytes(max_n, W) + (learned ? pol_bytes(max_n, kVariants[v].bs) : 0);
+  return need <= kVariants[v].lds_cap;
+}
+static bool variant_fits(const zx_batch* b, int v, bool learned) { return variant_fits_n(b->max_n, v, learned); }
+
+static int pick_variant(const zx_batch* b, int tune_id, bool learned) {
+  if (tune_id >= 0 && tune_id < kNumVariants) return tune_id;
+  if (!learned) {
+    if (b->tuned >= 0) return b->tuned;
+    auto it = tune_cache().find(size_class(b));
+    if (it != tune_cache().end()) return it->second;
+  }
+  if (variant_fits(b, kDefaultVariant, learned)) return kDefaultVariant;
+  for (int v = 0; v < kNumVariants; ++v)
+    if (variant_fits(b, v, learned)) return v;
+  return kDefaultVariant;
 }
 
-static int pick_variant(const zx_batch* b, int tune_id) {
-  if (tune_id >= 0 && tune_id < kNumVariants) return tune_id;
-  if (b->tuned >= 0) return b->tuned;
-  auto it = tune_cache().find(size_class(b));
-  if (it != tune_cache().end()) return it->second;
-  if (variant_fits(b, kDefaultVariant)) return kDefaultVariant;
-  for (int v = 0; v < kNumVariants; ++v)
-    if (variant_fits(b, v)) return v;
-  return kDefaultVariant;
+static SimpArgs simp_args(const zx_simplify_opts* o) {
+  SimpArgs a;
+  a.lds_cap = 0;
+  a.extract = o->extract;
+  a.max_rounds = o->max_rounds > 0 ? o->max_rounds : 0;
+  a.resume = (o->flags & ZX_RESUME) ? 1 : 0;
+  a.pad = 0;
+  a.wbf = o->mlp ? o->mlp->wbf16 : nullptr;
+  a.param = o->mlp ? o->mlp->param : nullptr;
+  return a;
+}
+
+static_assert(sizeof(Queue) == ZX_QUEUE_BYTES, "queue size");
+
+int32_t zx_max_spiders(int32_t policy) {
+  int32_t best = 0;
+  for (int v = 0; v < kNumVariants; ++v) {
+    int lo = 1, hi = 32767;
+    if (!variant_fits_n(lo, v, policy == ZX_POLICY_LEARNED)) continue;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo + 1) / 2;
+      if (variant_fits_n(mid, v, policy == ZX_POLICY_LEARNED)) lo = mid;
+      else hi = mid - 1;
+    }
+    best = std::max(best, lo);
+  }
+  return best;
+}
+
+zx_status zx_launch_batch(uint8_t* const* table_dev, int32_t n, void* queue, int32_t max_n,
+                          const zx_simplify_opts* o, hipStream_t s) {
+  const bool learned = o->policy == ZX_POLICY_LEARNED;
+  int v = -1;
+  if (variant_fits_n(max_n, kDefaultVariant, learned)) v = kDefaultVariant;
+  for (int i = 0; i < kNumVariants && v < 0; ++i)
+    if (variant_fits_n(max_n, i, learned)) v = i;
+  if (v < 0) {
+    zx_set_error("diagram of %d spiders too large for the simplify kernels", max_n);
+    return ZX_ECAPACITY;
+  }
+  return launch_simplify(v, table_dev, n, (Queue*)queue, simp_args(o), learned, s);
 }
 
 extern "C" zx_status zx_batch_simplify(zx_batch* b, const zx_simplify_opts* o, hipStream_t s) {
   zx_clear_error();
   ZX_CHECK_ARG(b, "null batch");
-  zx_simplify_opts def = {ZX_POLICY_GREEDY, 1, -1, 0};
+  zx_simplify_opts def = {ZX_POLICY_GREEDY, 1, -1, 0, 0, 0, nullptr};
   if (!o) o = &def;
-  ZX_CHECK_ARG(o->policy == ZX_POLICY_GREEDY, "unknown policy %d", o->policy);
-  const int v = pick_variant(b, o->tune_id);
-  zx_status st = launch_simplify(v, b->table_dev, b->n, b->queue, o->extract, s);
+  ZX_CHECK_ARG(o->policy == ZX_POLICY_GREEDY || o->policy == ZX_POLICY_LEARNED, "unknown policy %d",
+               o->policy);
+  const bool learned = o->policy == ZX_POLICY_LEARNED;
+  if (learned)
+    ZX_CHECK_ARG(o->mlp && o->mlp->param && o->mlp->wbf16, "learned policy needs a network");
+  ZX_CHECK_ARG(o->max_rounds >= 0, "negative max_rounds");
+  const int v = pick_variant(b, o->tune_id, learned);
+  if (!variant_fits(b, v, learned)) {
+    zx_set_error("diagrams too large for simplify variant %d", v);
+    return ZX_ECAPACITY;
+  }
+  zx_status st = launch_simplify(v, b->table_dev, b->n, b->queue, simp_args(o), learned, s);
   if (st != ZX_OK) return st;
   if (o->flags & ZX_SYNC) ZX_HIP(hipStreamSynchronize(s));
   return ZX_OK;
@@ -1089,11 +1475,13 @@ extern "C" zx_status zx_batch_autotune(zx_batch* b, int32_t extract, int32_t rep
   ZX_HIP(hipEventCreate(&e1));
   int best = -1;
   float bt = 1e30f;
+  zx_simplify_opts o = {ZX_POLICY_GREEDY, extract, -1, 0, 0, 0, nullptr};
+  const SimpArgs a = simp_args(&o);
   for (int v = 0; v < kNumVariants; ++v) {
-    if (!variant_fits(b, v)) continue;
-    if (launch_simplify(v, b->table_dev, b->n, b->queue, extract, s) != ZX_OK) continue;
+    if (!variant_fits(b, v, false)) continue;
+    if (launch_simplify(v, b->table_dev, b->n, b->queue, a, false, s) != ZX_OK) continue;
     ZX_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) launch_simplify(v, b->table_dev, b->n, b->queue, extract, s);
+    for (int r = 0; r < reps; ++r) launch_simplify(v, b->table_dev, b->n, b->queue, a, false, s);
     ZX_HIP(hipEventRecord(e1, s));
     ZX_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -1104,8 +1492,8 @@ extern "C" zx_status zx_batch_autotune(zx_batch* b, int32_t extract, int32_t rep
       best = v;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (best < 0) {
     zx_set_error("no simplify variant could run");
     return ZX_ECAPACITY;
@@ -1159,5 +1547,83 @@ extern "C" zx_status zx_graph_reset(zx_graph* g, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(32), dim3(256), 0, s, g->arena);
   hipLaunchKernelGGL(reset_edges_kernel, dim3(1), dim3(256), 0, s, g->arena);
   ZX_HIP(hipGetLastError());
+  return ZX_OK;
+}
+
+// ------------------------------------------------------------ rollouts --
+namespace {
+constexpr int kRollBS = 512;
+constexpr int64_t kRollLds = 152 * 1024;
+constexpr int kRollBlocksPerCU = 2;  // bound used to size the workspace
+
+int64_t roll_mbuf_words(zx_graph* const* states, int32_t n_states) {
+  int64_t mw = 1;
+  for (int i = 0; i < n_states; ++i)
+    if (states[i]) mw = std::max(mw, (int64_t)states[i]->n_out * states[i]->W);
+  return (mw + 31) & ~int64_t(31);
+}
+int roll_grid_max() {
+  const ZxDevice* d = zx_device();
+  return (d ? d->n_cu : 256) * kRollBlocksPerCU;
+}
+}  // namespace
+
+extern "C" size_t zx_rollout_workspace_bytes(zx_graph* const* states, int32_t n_states) {
+  if (!states || n_states <= 0) return 0;
+  const size_t table = ((size_t)n_states * 8 + 255) & ~size_t(255);
+  return 256 + sizeof(Queue) + table + (size_t)roll_grid_max() * roll_mbuf_words(states, n_states) * 8;
+}
+
+extern "C" zx_status zx_rollout(zx_graph* const* states, int32_t n_states, int32_t per_state,
+                                int64_t* cost, int64_t* fill, int32_t* move, uint16_t* feats, void* ws,
+                                size_t ws_bytes, hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(states && n_states > 0 && per_state > 0, "bad argument");
+  ZX_CHECK_ARG(cost && fill && move && feats && ws, "null buffer");
+  ZX_CHECK_ARG(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
+  ZX_CHECK_ARG((int64_t)n_states * per_state <= INT32_MAX, "too many items");
+  if (ws_bytes < zx_rollout_workspace_bytes(states, n_states)) {
+    zx_set_error("workspace too small");
+    return ZX_ECAPACITY;
+  }
+  std::vector<uint8_t*> tab((size_t)n_states);
+  for (int i = 0; i < n_states; ++i) {
+    ZX_CHECK_ARG(states[i], "null state %d", i);
+    tab[i] = states[i]->arena;
+  }
+  const ZxDevice* d = zx_device();
+  if (!d) return ZX_EDEVICE;
+  const int64_t lds = std::min<int64_t>(kRollLds, (int64_t)d->lds_per_block);
+  Queue* q = (Queue*)((uint8_t*)ws + 256);
+  uint8_t** table = (uint8_t**)((uint8_t*)ws + 256 + sizeof(Queue));
+  uint64_t* mbuf = (uint64_t*)((uint8_t*)table + (((size_t)n_states * 8 + 255) & ~size_t(255)));
+  ZX_HIP(hipMemcpyAsync(table, tab.data(), (size_t)n_states * 8, hipMemcpyHostToDevice, s));
+  const void* fn = (const void*)rollout_kernel<kRollBS>;
+  ZX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  ZX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kRollBS, (size_t)lds));
+  if (per_cu < 1) {
+    zx_set_error("rollout kernel does not fit a CU");
+    return ZX_ECAPACITY;
+  }
+  const int32_t items = n_states * per_state;
+  int grid = std::min(per_cu, kRollBlocksPerCU) * d->n_cu;
+  grid = std::min(grid, roll_grid_max());
+  if (grid > items) grid = items;
+  RollArgs a;
+  a.states = table;
+  a.n_items = items;
+  a.per_state = per_state;
+  a.lds_cap = lds;
+  a.mbuf = mbuf;
+  a.mbuf_words = roll_mbuf_words(states, n_states);
+  a.cost = cost;
+  a.fill = fill;
+  a.move = move;
+  a.feats = feats;
+  hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, s, q);
+  hipLaunchKernelGGL(rollout_kernel<kRollBS>, dim3(grid), dim3(kRollBS), (size_t)lds, s, q, a);
+  ZX_HIP(hipGetLastError());
+  ZX_HIP(hipStreamSynchronize(s));
   return ZX_OK;
 }

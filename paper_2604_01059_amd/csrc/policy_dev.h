@@ -1,0 +1,281 @@
+// Learned selection priority for the local-complementation rounds: candidate
+// list, candidate features, network scores, priority order and the
+// selection of the round's rewrites in that order.  Pivot rounds keep the
+// canonical order.  Included by graph.hip inside its namespace, after the
+// round primitives.
+
+// Policy work areas in LDS (after the auxiliary arrays).
+struct Pol {
+  const uint16_t* wbf;    // network, bf16 copy (global)
+  const float* param;     // network, fp32 master (global; b1, b2 read)
+  int cap;                // list capacity, power of two >= n (>= 64)
+  LDSP uint32_t* list;    // candidate spiders of an LC round
+  LDSP uint64_t* key;     // sort keys, descending = priority order
+  LDSP uint16_t* fbuf;    // per wavefront 32 x ZX_MLP_IN bf16 features
+};
+
+__host__ __device__ inline int pol_cap(int n) {
+  int c = 64;
+  while (c < n) c <<= 1;
+  return c;
+}
+__host__ __device__ inline int64_t pol_bytes(int n, int bs) {
+  const int cap = pol_cap(n);
+  return 16 + (int64_t)cap * 4 + (int64_t)cap * 8 + (int64_t)(bs / 64) * 32 * zxmlp::IN * 2;
+}
+
+// The feature rows are read 16 bytes at a time: start the area on 16 bytes.
+__device__ inline uint8_t* align16(uint8_t* p) { return (uint8_t*)(((uintptr_t)p + 15) & ~uintptr_t(15)); }
+
+template <int BS>
+__device__ void setup_pol(Pol& p, uint8_t* at, int n, const uint16_t* wbf, const float* param) {
+  p.wbf = wbf;
+  p.param = param;
+  p.cap = pol_cap(n);
+  at = align16(at);
+  p.key = (LDSP uint64_t*)at;
+  at += (int64_t)p.cap * 8;
+  p.list = (LDSP uint32_t*)at;
+  at += (int64_t)p.cap * 4;
+  p.fbuf = (LDSP uint16_t*)at;
+}
+
+// Exclusive prefix over the wavefront of values in [0, 127], and the total.
+__device__ __forceinline__ int wave_excl_scan7(int v, int& total) {
+  int ex = 0, tot = 0;
+#pragma unroll
+  for (int bit = 0; bit < 7; ++bit) {
+    const uint64_t bb = __ballot((v >> bit) & 1);
+    ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0)) << bit;
+    tot += __popcll(bb) << bit;
+  }
+  total = tot;
+  return ex;
+}
+
+// Sum over the wavefront of values in [0, 255].
+__device__ __forceinline__ int wave_sum8(int v) {
+  int tot = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) tot += __popcll(__ballot((v >> b) & 1)) << b;
+  return tot;
+}
+
+// Candidate list of an LC round: the candidate spiders, ascending.
+template <int BS, bool LA>
+__device__ int list_lc(Ctx<LA>& c, Shared& sh, Pol& p) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int cnt = 0;
+    for (int j0 = 0; j0 < c.W; j0 += 64) {
+      const int j = j0 + lane;
+      uint64_t m = j < c.W ? c.cand[j] : 0;
+      int tot;
+      int pos = cnt + wave_excl_scan7(__popcll(m), tot);
+      while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        p.list[pos++] = (uint32_t)(64 * j + b);
+      }
+      cnt += tot;
+    }
+    if (lane == 0) sh.cnt = cnt;
+  }
+  __syncthreads();
+  const int cnt = sh.cnt;
+  __syncthreads();
+  return cnt;
+}
+
+// Present spiders with k = 0 mod 4 into c.inm (used by the features).
+template <int BS, bool LA>
+__device__ float pauli_mask_and_scale(Ctx<LA>& c, Shared& sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) sh.key = 0;
+  __syncthreads();
+  for (int j = wv; j < c.W; j += BS / 64) {
+    const int v = 64 * j + lane;
+    const bool ok = v < c.n && bit_of(c.alive, v) && (c.k[v] & 3) == 0;
+    const uint64_t w = __ballot(ok);
+    if (lane == 0) {
+      c.inm[j] = w;
+      atomicAdd(&sh.key, __popcll(c.alive[j]));
+    }
+  }
+  __syncthreads();
+  const int N = sh.key > 0 ? sh.key : 1;
+  __syncthreads();
+  return 1.0f / (float)N;
+}
+
+// The seven features of endpoint x into f[0..6] (one wavefront; lane 0
+// writes).  Two-hop set: OR of the neighbours' rows minus N[x].
+template <bool LA>
+__device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* f) {
+  const int lane = threadIdx.x & 63, W = c.W;
+  const auto rx = row_ptr(c, x);
+  uint64_t acc[MAXS], own[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) {
+    const int j = lane + 64 * s;
+    acc[s] = 0;
+    own[s] = j < W ? rx[j] : 0;
+  }
+  for (int kw = 0; kw < W; ++kw) {
+    uint64_t m = rx[kw];  // same address in every lane
+    while (m) {
+      const int b = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const auto rw = row_ptr(c, 64 * kw + b);
+#pragma unroll
+      for (int s = 0; s < MAXS; ++s) {
+        const int j = lane + 64 * s;
+        if (j < W) acc[s] |= rw[j];
+      }
+    }
+  }
+  int deg = 0, bn = 0, th = 0, pn = 0;
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) {
+    const int j = lane + 64 * s;
+    if (j < W) {
+      uint64_t two = acc[s] & ~own[s];
+      if (j == (x >> 6)) two &= ~(1ull << (x & 63));
+      deg += __popcll(own[s]);
+      bn += __popcll(own[s] & c.bnd[j]);
+      th += __popcll(two);
+      pn += __popcll(own[s] & c.inm[j]);
+    }
+  }
+  deg = wave_sum8(deg);
+  bn = wave_sum8(bn);
+  th = wave_sum8(th);
+  pn = wave_sum8(pn);
+  if (lane == 0) {
+    const int k = c.k[x];
+    f[0] = zxmlp::to_bf16((float)deg * invN);
+    f[1] = zxmlp::to_bf16((k & 3) == 0 ? 1.f : 0.f);
+    f[2] = zxmlp::to_bf16((k & 3) == 2 ? 1.f : 0.f);
+    f[3] = zxmlp::to_bf16((k & 1) ? 1.f : 0.f);
+    f[4] = zxmlp::to_bf16((float)bn * invN);
+    f[5] = zxmlp::to_bf16((float)th * invN);
+    f[6] = zxmlp::to_bf16((float)pn * invN);
+  }
+}
+
+// Features of LC candidate u into f[0..15] (one wavefront): its endpoint
+// features, zeros for the second endpoint, rule bit 0, constant 1.
+template <bool LA>
+__device__ void candidate_features(Ctx<LA>& c, int u, float invN, LDSP uint16_t* f) {
+  const int lane = threadIdx.x & 63;
+  endpoint_features(c, u, invN, f);
+  if (lane < 7) f[7 + lane] = 0;
+  if (lane == 0) {
+    f[14] = zxmlp::to_bf16(0.f);
+    f[15] = zxmlp::to_bf16(1.f);
+  }
+}
+
+// Order-preserving map of a float onto uint32.
+__device__ __forceinline__ uint32_t float_order(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Scores of list entries 0..C-1 into p.key as (order(score) << 32) |
+// ~index, so that descending keys give descending scores, ties by index.
+template <int BS, bool LA>
+__device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  LDSP uint16_t* fb = p.fbuf + wv * 32 * zxmlp::IN;
+  for (int base = wv * 32; base < C; base += (BS / 64) * 32) {
+    for (int r = 0; r < 32; ++r) {
+      LDSP uint16_t* f = fb + r * zxmlp::IN;
+      if (base + r < C) candidate_features(c, (int)p.list[base + r], invN, f);
+      else if (lane < zxmlp::IN) f[lane] = 0;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    float s[16];
+    zxmlp::score32(zxmlp::load_a(fb), p.wbf, p.param, s);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int idx = base + zxmlp::acc_row(i, lane);
+      if ((lane & 31) == i && idx < C)
+        p.key[idx] = ((uint64_t)float_order(s[i]) << 32) | (uint32_t)(0xffffffffu - (uint32_t)idx);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Bitonic sort of p.key[0..P) descending, P = next power of two >= C
+// (entries C..P-1 are set to 0 and sort last).
+template <int BS>
+__device__ void sort_keys_desc(Pol& p, int C) {
+  int P = 1;
+  while (P < C) P <<= 1;
+  for (int i = C + threadIdx.x; i < P; i += BS) p.key[i] = 0;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += BS) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = p.key[i], b = p.key[ixj];
+          const bool desc = (i & k) == 0;
+          if (desc ? (a < b) : (a > b)) {
+            p.key[i] = b;
+            p.key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint32_t key_index(uint64_t k) { return 0xffffffffu - (uint32_t)k; }
+
+// LC round in priority order: take each candidate unless adjacent to one
+// taken before it.  One wavefront, 64 candidates of the order at a time:
+// lane l tests its candidate against the spiders taken in earlier blocks,
+// builds its adjacency to the block's other candidates, and the block is
+// resolved in order with scalar bit operations.
+template <int BS, bool LA>
+__device__ void select_lc_priority(Ctx<LA>& c, Shared& sh, Pol& p, int C) {
+  const int W = c.W;
+  for (int j = threadIdx.x; j < W; j += BS) c.sel[j] = 0;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int b = 0; b < C; b += 64) {
+      const int e = b + lane;
+      const int u = e < C ? (int)p.list[key_index(p.key[e])] : -1;
+      const int cnt = C - b < 64 ? C - b : 64;
+      bool fr = u >= 0;
+      uint64_t nb = 0;
+      if (fr) {
+        const auto ru = row_ptr(c, u);
+        for (int j = 0; j < W; ++j)
+          if (ru[j] & c.sel[j]) {
+            fr = false;
+            break;
+          }
+      }
+      for (int m = 0; m < cnt; ++m) {
+        const int x = __builtin_amdgcn_readlane(u, m);
+        if (u >= 0) nb |= (uint64_t)((row_ptr(c, u)[x >> 6] >> (x & 63)) & 1) << m;
+      }
+      uint64_t R = __ballot(fr), taken = 0;
+      while (R) {
+        const int l = __builtin_ctzll(R);
+        taken |= 1ull << l;
+        R &= ~(readlane64(nb, l) | (1ull << l));
+      }
+      if ((taken >> lane) & 1) atomicOr((unsigned long long*)&c.sel[u >> 6], 1ull << (u & 63));
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+}

@@ -56,20 +56,19 @@ extern "C" size_t zx_graph_bytes(int32_t n, int32_t n_in, int32_t n_out) {
   return (size_t)zx_layout(n, n_in, n_out).bytes;
 }
 
-extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
-                                     const uint64_t* adj_host, const int8_t* phase_host,
-                                     const int32_t* in_spider, int32_t n_in,
-                                     const int32_t* out_spider, int32_t n_out,
-                                     const uint8_t* bnd_is_h, hipStream_t s) {
-  zx_clear_error();
-  ZX_CHECK_ARG(g && dev_arena && adj_host && phase_host, "null argument");
+// Validate a diagram on the host and assemble its arena image (header,
+// SOURCE and CURRENT sections, boundary tables, masks).  Bits at or beyond n,
+// self loops, phases outside 0..7 and bad boundary ids are always rejected:
+// the kernels index by spider id.  The O(n^2) symmetry test is optional.
+zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
+                         const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
+                         int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
+                         std::vector<uint8_t>& img) {
+  ZX_CHECK_ARG(adj_host && phase_host, "null argument");
   ZX_CHECK_ARG(n > 0 && n <= (1 << 20), "n out of range: %d", n);
   ZX_CHECK_ARG(n_in >= 0 && n_out >= 0 && n_in + n_out <= n, "bad boundary counts");
   ZX_CHECK_ARG((n_in == 0 || in_spider) && (n_out == 0 || out_spider), "null boundary list");
-  ZX_CHECK_ARG(((uintptr_t)dev_arena & 255) == 0, "arena must be 256-byte aligned");
   ZxLayout L = zx_layout(n, n_in, n_out);
-  ZX_CHECK_ARG(arena_bytes >= (size_t)L.bytes, "arena too small: %zu < %lld", arena_bytes,
-               (long long)L.bytes);
   const int W = (n + 63) / 64;
   // validate on the host: symmetric, zero diagonal, no bits >= n, phases
   for (int r = 0; r < n; ++r) {
@@ -78,12 +77,13 @@ extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena
     if (n % 64) ZX_CHECK_ARG((row[W - 1] >> (n % 64)) == 0, "bits beyond n in row %d", r);
     ZX_CHECK_ARG(phase_host[r] >= 0 && phase_host[r] < 8, "phase of spider %d not in 0..7", r);
   }
-  for (int r = 0; r < n; ++r)
-    for (int c = r + 1; c < n; ++c) {
-      int a = (adj_host[(size_t)r * W + c / 64] >> (c % 64)) & 1;
-      int b = (adj_host[(size_t)c * W + r / 64] >> (r % 64)) & 1;
-      ZX_CHECK_ARG(a == b, "adjacency not symmetric at (%d,%d)", r, c);
-    }
+  if (check_symmetry)
+    for (int r = 0; r < n; ++r)
+      for (int c = r + 1; c < n; ++c) {
+        int a = (adj_host[(size_t)r * W + c / 64] >> (c % 64)) & 1;
+        int b = (adj_host[(size_t)c * W + r / 64] >> (r % 64)) & 1;
+        ZX_CHECK_ARG(a == b, "adjacency not symmetric at (%d,%d)", r, c);
+      }
   std::vector<uint8_t> seen((size_t)n, 0);
   for (int i = 0; i < n_in + n_out; ++i) {
     int v = i < n_in ? in_spider[i] : out_spider[i - n_in];
@@ -92,7 +92,7 @@ extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena
     seen[v] = 1;
   }
   // assemble the whole arena image on the host, then one copy
-  std::vector<uint8_t> img((size_t)L.bytes, 0);
+  img.assign((size_t)L.bytes, 0);
   ZxHeader h;
   memset(&h, 0, sizeof(h));
   h.magic = ZX_MAGIC;
@@ -133,6 +133,28 @@ extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena
   for (int v = 0; v < n; ++v) al[v / 64] |= (uint64_t)1 << (v % 64);
   int32_t* fp = (int32_t*)(img.data() + L.off_fpiv);
   for (int j = 0; j < n_out; ++j) fp[j] = -1;
+  return ZX_OK;
+}
+
+extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
+                                     const uint64_t* adj_host, const int8_t* phase_host,
+                                     const int32_t* in_spider, int32_t n_in,
+                                     const int32_t* out_spider, int32_t n_out,
+                                     const uint8_t* bnd_is_h, hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(g && dev_arena && adj_host && phase_host, "null argument");
+  ZX_CHECK_ARG(n > 0 && n <= (1 << 20), "n out of range: %d", n);
+  ZX_CHECK_ARG(n_in >= 0 && n_out >= 0 && n_in + n_out <= n, "bad boundary counts");
+  ZX_CHECK_ARG((n_in == 0 || in_spider) && (n_out == 0 || out_spider), "null boundary list");
+  ZX_CHECK_ARG(((uintptr_t)dev_arena & 255) == 0, "arena must be 256-byte aligned");
+  ZxLayout L = zx_layout(n, n_in, n_out);
+  ZX_CHECK_ARG(arena_bytes >= (size_t)L.bytes, "arena too small: %zu < %lld", arena_bytes,
+               (long long)L.bytes);
+  std::vector<uint8_t> img;
+  zx_status st = zx_build_image(n, adj_host, phase_host, in_spider, n_in, out_spider, n_out, bnd_is_h,
+                                true, img);
+  if (st != ZX_OK) return st;
+  const int W = (n + 63) / 64;
   ZX_HIP(hipMemcpyAsync(dev_arena, img.data(), img.size(), hipMemcpyHostToDevice, s));
   ZX_HIP(hipStreamSynchronize(s));  // the staging image is freed on return
   zx_graph* G = (zx_graph*)calloc(1, sizeof(zx_graph));

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <vector>
 
 #include "../../include/zx.h"
 
@@ -75,6 +76,20 @@ struct zx_graph {
 
 // ------------------------------------------------------------ errors --
 void zx_set_error(const char* fmt, ...);
+
+// Host validation + arena image of a diagram (runtime.hip).
+zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
+                         const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
+                         int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
+                         std::vector<uint8_t>& img);
+
+// One persistent simplify launch over a device table of arenas (graph.hip);
+// queue: ZX_QUEUE_BYTES of device memory; max_n: largest diagram.
+constexpr size_t ZX_QUEUE_BYTES = 256;
+zx_status zx_launch_batch(uint8_t* const* table_dev, int32_t n, void* queue, int32_t max_n,
+                          const zx_simplify_opts* o, hipStream_t s);
+// Largest diagram the simplify kernels take with this policy.
+int32_t zx_max_spiders(int32_t policy);
 void zx_clear_error();
 
 #define ZX_CHECK_ARG(cond, ...)            \

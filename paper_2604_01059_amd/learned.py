@@ -1,0 +1,202 @@
+"""Learned rewrite proposal: training data from greedy runs, training with the
+library's network kernels, evaluation against the greedy schedule.
+
+The paper applies its two rules (appendix "Rewrite rules") greedily to the
+fixed point (appendix "Stabilizer decompositions") and says nothing on the
+order; a different order reaches a different, equally valid fixed point with
+a different cost.  This module learns an order.
+
+* State: a diagram at the start of a round of a greedy run.
+* Candidates: the local-complementation candidates of the round (pivot
+  rounds keep the canonical order).
+* Label of a candidate: its rollout cost -- apply it, finish greedily, count
+  Hadamard edges plus frontier row additions (``zx.rollout``).
+* Loss: softmax cross-entropy of the scores of a state's candidates toward
+  its cheapest candidate (``zx_mlp_loss``).
+* Use: ``policy=ZX_POLICY_LEARNED`` takes each LC round's candidates in
+  descending score order; ``simplify_with_fallback`` keeps, per diagram, the
+  cheaper of the learned and the greedy result.
+
+Every step runs in the HIP library; this module only moves tensors.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import zx
+
+TRAIN_SEED = 41
+EVAL_SEED = 42
+
+
+def gate2q(info) -> int:
+    """Hadamard edges left plus the row additions of the output frontier."""
+    return int(info.n_edges) + int(info.rowops)
+
+
+def new_network(seed: int = TRAIN_SEED) -> zx.MLP:
+    from workloads import network_init
+    return zx.MLP(torch.from_numpy(network_init(seed)))
+
+
+def greedy_states(diagrams, max_states=None):
+    """Snapshots of every round start of the greedy runs of ``diagrams``
+    (states at their fixed point are dropped)."""
+    graphs = [zx.Graph.from_diagram(d) for d in diagrams]
+    states = []
+    r = 0
+    active = graphs
+    while active:
+        snaps = [g.snapshot() for g in active]
+        zx.simplify(active, extract=False, max_rounds=r + 1, resume=True)
+        nxt = []
+        for g, s in zip(active, snaps):
+            if g.info().rounds > r:
+                states.append(s)
+                nxt.append(g)
+        active = nxt
+        r += 1
+        if max_states is not None and len(states) >= max_states:
+            break
+    return states[:max_states] if max_states is not None else states
+
+
+def make_dataset(n_states: int, per_state: int = 16, seed: int = TRAIN_SEED, chunk: int = 256,
+                 log=None):
+    """(features, costs) for n_states states of greedy runs on the batched
+    generator's diagrams: features (n_states * per_state, 16) int16 bf16 bits,
+    costs (n_states * per_state,) int64 (-1 = no candidate in that slot)."""
+    from workloads import batch_diagram
+    feats, costs = [], []
+    have, item = 0, 0
+    t0 = time.time()
+    while have < n_states:
+        ds = [batch_diagram(seed, item + i) for i in range(chunk)]
+        item += chunk
+        states = greedy_states(ds, max_states=n_states - have)
+        if not states:
+            continue
+        cost, _, _, f = zx.rollout(states, per_state)
+        # states past their LC phase have no candidate: drop them
+        keep = (cost.view(-1, per_state) >= 0).any(dim=1)
+        rows = keep.repeat_interleave(per_state)
+        feats.append(f[rows])
+        costs.append(cost[rows])
+        have += int(keep.sum())
+        del states
+        if log:
+            log("dataset: %d states, %d diagrams, %.1f s" % (have, item, time.time() - t0))
+    return torch.cat(feats), torch.cat(costs)
+
+
+def train(mlp: zx.MLP, feats, costs, per_state: int = 16, epochs: int = 4, batch_states: int = 512,
+          lr: float = 1e-3, seed: int = TRAIN_SEED, log=None):
+    """Adam on the per-state cross-entropy.  Returns the loss curve (mean
+    loss of every logged step)."""
+    S = costs.numel() // per_state
+    dev = feats.device
+    seg = torch.arange(0, batch_states * per_state + 1, per_state, dtype=torch.int32, device=dev)
+    ws = None
+    gen = torch.Generator().manual_seed(seed)
+    curve = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(S, generator=gen).to(dev)
+        for b in range(0, S - batch_states + 1, batch_states):
+            idx = perm[b:b + batch_states]
+            rows = (idx[:, None] * per_state + torch.arange(per_state, device=dev)[None]).reshape(-1)
+            x = feats[rows].contiguous()
+            c = costs[rows].contiguous()
+            score = mlp.forward(x)
+            ds, loss = zx.MLP.loss(score, c, seg)
+            if ws is None:
+                ws = torch.empty(zx.load().zx_mlp_workspace_bytes(x.shape[0]), dtype=torch.uint8, device=dev)
+            mlp.backward(x, ds, ws=ws)
+            mlp.adam(lr=lr)
+            step += 1
+            if step % 25 == 0:
+                curve.append((step, float(loss.mean())))
+        if log and curve:
+            log("epoch %d: loss %.4f" % (ep, curve[-1][1]))
+    return curve
+
+
+def evaluate(mlp: zx.MLP, n: int = 1024, seed: int = EVAL_SEED, q_lo: int = 32, q_hi: int = 128):
+    """Learned vs greedy on n held-out diagrams: gate2q, fill-in, wall time."""
+    from workloads import batch_diagram
+    ds = [batch_diagram(seed, i, q_lo=q_lo, q_hi=q_hi) for i in range(n)]
+    greedy = [zx.Graph.from_diagram(d) for d in ds]
+    learned = [zx.Graph.from_diagram(d) for d in ds]
+    bg, bl = zx.Batch(greedy), zx.Batch(learned)
+    times = {}
+    for name, run in (("greedy", lambda: bg.run()),
+                      ("learned", lambda: bl.run(policy=zx.ZX_POLICY_LEARNED, mlp=mlp))):
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1)
+    for b, name in ((bg, "greedy"), (bl, "learned")):
+        st = b.status()
+        if st != zx.ZX_OK:
+            raise zx.ZxError(st, "%s batch failed" % name)
+    gi = [g.info() for g in greedy]
+    li = [g.info() for g in learned]
+    cg = np.array([gate2q(i) for i in gi])
+    cl = np.array([gate2q(i) for i in li])
+    best = np.minimum(cg, cl)
+    return {
+        "diagrams": n,
+        "mean_spiders": float(np.mean([d.n for d in ds])),
+        "gate2q_greedy": int(cg.sum()),
+        "gate2q_learned": int(cl.sum()),
+        "gate2q_fallback": int(best.sum()),
+        "gain_learned": float(1 - cl.sum() / cg.sum()),
+        "gain_fallback": float(1 - best.sum() / cg.sum()),
+        "learned_better": int((cl < cg).sum()),
+        "learned_worse": int((cl > cg).sum()),
+        "fill_greedy": int(sum(i.fill_in for i in gi)),
+        "fill_learned": int(sum(i.fill_in for i in li)),
+        "ms_greedy": times["greedy"],
+        "ms_learned": times["learned"],
+    }
+
+
+def simplify_with_fallback(graphs, mlp: zx.MLP):
+    """Simplify each graph with the learned policy and with the greedy one;
+    keep the cheaper result (gate2q) in ``graphs``.  Returns, per graph,
+    True where the learned result was kept."""
+    twins = [g.snapshot() for g in graphs]
+    zx.simplify(graphs, extract=True, policy=zx.ZX_POLICY_LEARNED, mlp=mlp)
+    zx.simplify(twins, extract=True)
+    kept = []
+    for g, t in zip(graphs, twins):
+        if gate2q(t.info()) < gate2q(g.info()):
+            g.arena.copy_(t.arena)
+            kept.append(False)
+        else:
+            kept.append(True)
+    return kept
+
+
+def save(mlp: zx.MLP, path: str):
+    """Network and optimiser state as safetensors."""
+    from safetensors.torch import save_file
+    save_file({"param": mlp.param.cpu(), "wbf16": mlp.wbf16.cpu(), "adam_m": mlp.m.cpu(),
+               "adam_v": mlp.v.cpu(), "step": torch.tensor([mlp.step], dtype=torch.int64)}, path)
+
+
+def load(path: str) -> zx.MLP:
+    from safetensors.torch import load_file
+    t = load_file(path)
+    m = zx.MLP(t["param"])
+    m.m.copy_(t["adam_m"])
+    m.v.copy_(t["adam_v"])
+    m.step = int(t["step"][0])
+    return m

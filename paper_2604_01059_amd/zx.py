@@ -16,7 +16,12 @@ LIB_PATH = os.path.join(HERE, "libzx.so")
 
 ZX_OK, ZX_EINVAL, ZX_ENOMATCH, ZX_ECAPACITY, ZX_EDEVICE, ZX_EBUSY = 0, -1, -2, -3, -4, -5
 ZX_GRAPH_ONLY = 0x1
+ZX_RESUME = 0x2
 ZX_SYNC = 0x100
+ZX_POLICY_GREEDY, ZX_POLICY_LEARNED = 0, 1
+MLP_IN, MLP_HID = 16, 256
+MLP_NPARAM = MLP_IN * MLP_HID + 2 * MLP_HID + 1
+MLP_NBF16 = MLP_IN * MLP_HID + MLP_HID
 STATUS_NAMES = {0: "ZX_OK", -1: "ZX_EINVAL", -2: "ZX_ENOMATCH", -3: "ZX_ECAPACITY",
                 -4: "ZX_EDEVICE", -5: "ZX_EBUSY"}
 
@@ -34,10 +39,36 @@ class GraphInfo(C.Structure):
                 ("rank", C.c_int32), ("pad", C.c_int32), ("rowops", C.c_int64)]
 
 
+class MlpHandle(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("wbf16", C.c_void_p)]
+
+
 class SimplifyOpts(C.Structure):
     _fields_ = [("policy", C.c_int32), ("extract", C.c_int32), ("tune_id", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("max_rounds", C.c_int32), ("pad", C.c_int32),
+                ("mlp", C.POINTER(MlpHandle))]
 
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_in", C.c_int32), ("n_out", C.c_int32), ("pad", C.c_int32),
+                ("adj", C.c_void_p), ("phase", C.c_void_p), ("inputs", C.c_void_p), ("outputs", C.c_void_p),
+                ("bnd_is_h", C.c_void_p), ("tag", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("tag", C.c_int64), ("status", C.c_int32), ("n_alive", C.c_int32),
+                ("rounds", C.c_int32), ("n_trace", C.c_int32), ("rank", C.c_int32), ("phase8", C.c_int32),
+                ("n_edges", C.c_int64), ("rowops", C.c_int64), ("pow_sqrt2", C.c_int64), ("fill_in", C.c_int64),
+                ("t_submit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("refused", C.c_int64), ("completed", C.c_int64),
+                ("batches", C.c_int64), ("pending", C.c_int64), ("running", C.c_int64),
+                ("pool_bytes", C.c_size_t), ("pool_used", C.c_size_t), ("pool_peak", C.c_size_t)]
+
+
+ZX_SERVE_TRUSTED = 0x1
 
 _lib = None
 
@@ -81,6 +112,20 @@ def load():
         "zx_gf2_status": ([P, P], i32),
         "zx_gf2_profile_read": ([P, i32, P, i32, P], i32),
         "zx_pauli_commute": ([P, P, i64, i32, i64, P, i64, u32, P], i32),
+        "zx_mlp_sync": ([C.POINTER(MlpHandle), P], i32),
+        "zx_mlp_forward": ([C.POINTER(MlpHandle), P, i64, P, P], i32),
+        "zx_mlp_loss": ([P, P, P, i32, P, P, P], i32),
+        "zx_mlp_workspace_bytes": ([i64], sz),
+        "zx_mlp_backward": ([C.POINTER(MlpHandle), P, P, i64, P, P, sz, P], i32),
+        "zx_mlp_adam": ([C.POINTER(MlpHandle), P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, i32, P],
+                        i32),
+        "zx_rollout_workspace_bytes": ([P, i32], sz),
+        "zx_rollout": ([P, i32, i32, P, P, P, P, P, sz, P], i32),
+        "zx_server_create": ([C.POINTER(P), P, sz, i32, C.POINTER(SimplifyOpts), u32], i32),
+        "zx_server_submit": ([P, C.POINTER(Request), C.POINTER(i64)], i32),
+        "zx_server_poll": ([P, P, i32, C.POINTER(i32)], i32),
+        "zx_server_stats_read": ([P, C.POINTER(ServerStats)], i32),
+        "zx_server_destroy": ([P], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -97,7 +142,10 @@ def exported_symbols():
             "zx_local_comp", "zx_pivot", "zx_simplify_variants", "zx_simplify_variant_name",
             "zx_simplify_workspace_bytes", "zx_simplify", "zx_batch_prepare", "zx_batch_simplify",
             "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
-            "zx_gf2_eliminate", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute"]
+            "zx_gf2_eliminate", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
+            "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
+            "zx_mlp_adam", "zx_rollout_workspace_bytes", "zx_rollout", "zx_server_create",
+            "zx_server_submit", "zx_server_poll", "zx_server_stats_read", "zx_server_destroy"]
 
 
 def _check(rc):
@@ -173,6 +221,19 @@ class Graph:
     def from_diagram(cls, d, arena=None, stream=None):
         return cls.create(d.adj, d.phase, d.inputs, d.outputs, d.bnd_is_h, arena=arena, stream=stream)
 
+    @classmethod
+    def attach(cls, arena):
+        """Handle for an arena that already holds a diagram (synchronous)."""
+        h = C.c_void_p()
+        _check(load().zx_graph_attach(C.byref(h), _ptr(arena), arena.numel()))
+        import torch
+        hdr = arena[:16].cpu().numpy().view(np.int32)
+        return cls(h, arena, int(hdr[1]), int(hdr[2]), int(hdr[3]))
+
+    def snapshot(self):
+        """Independent copy of the arena (SOURCE, CURRENT, trace, header)."""
+        return Graph.attach(self.arena.clone())
+
     def read(self, stream=None):
         adj = np.zeros((self.n, self.W), np.uint64)
         ph = np.zeros(self.n, np.int8)
@@ -221,13 +282,21 @@ def _graph_array(graphs):
     return arr
 
 
-def simplify(graphs, extract=True, tune_id=-1, ws=None, stream=None):
+def _opts(extract, tune_id, policy, mlp, max_rounds, resume):
+    o = SimplifyOpts(policy, 1 if extract else 0, tune_id, ZX_RESUME if resume else 0, int(max_rounds), 0, None)
+    if mlp is not None:
+        o.mlp = C.pointer(mlp.handle)
+    return o
+
+
+def simplify(graphs, extract=True, tune_id=-1, ws=None, stream=None, policy=ZX_POLICY_GREEDY, mlp=None,
+             max_rounds=0, resume=False):
     import torch
     n = len(graphs)
     nb = simplify_workspace_bytes(n)
     if ws is None:
         ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    opts = SimplifyOpts(0, 1 if extract else 0, tune_id, 0)
+    opts = _opts(extract, tune_id, policy, mlp, max_rounds, resume)
     _check(load().zx_simplify(_graph_array(graphs), n, C.byref(opts), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
 
@@ -245,9 +314,10 @@ class Batch:
                                        self.ws.numel(), _stream(stream)))
         self.h = h
 
-    def run(self, extract=True, tune_id=-1, stream=None):
-        opts = SimplifyOpts(0, 1 if extract else 0, tune_id, 0)
-        _check(load().zx_batch_simplify(self.h, C.byref(opts), _stream(stream)))
+    def run(self, extract=True, tune_id=-1, stream=None, policy=ZX_POLICY_GREEDY, mlp=None, max_rounds=0,
+            resume=False):
+        self._opts = _opts(extract, tune_id, policy, mlp, max_rounds, resume)
+        _check(load().zx_batch_simplify(self.h, C.byref(self._opts), _stream(stream)))
 
     def status(self, stream=None):
         return load().zx_batch_status(self.h, _stream(stream))
@@ -263,6 +333,132 @@ class Batch:
         if getattr(self, "h", None) and _lib is not None:
             _lib.zx_batch_destroy(self.h)
             self.h = None
+
+
+# ------------------------------------------------------- learned proposal --
+
+class MLP:
+    """Scoring network in device memory: fp32 master ``param`` (W1 | b1 | w2 |
+    b2), bf16 copy ``wbf16`` (W1 transposed | w2), Adam moments ``m``, ``v``."""
+
+    def __init__(self, param):
+        import torch
+        assert param.numel() == MLP_NPARAM and param.dtype == torch.float32
+        self.param = param.contiguous().cuda()
+        self.wbf16 = torch.zeros(MLP_NBF16, dtype=torch.int16, device=self.param.device)
+        self.m = torch.zeros_like(self.param)
+        self.v = torch.zeros_like(self.param)
+        self.grad = torch.zeros_like(self.param)
+        self.step = 0
+        self.handle = MlpHandle(self.param.data_ptr(), self.wbf16.data_ptr())
+        self.sync()
+
+    def sync(self, stream=None):
+        _check(load().zx_mlp_sync(C.byref(self.handle), _stream(stream)))
+
+    def forward(self, x, score=None, stream=None):
+        import torch
+        rows = x.shape[0]
+        if score is None:
+            score = torch.empty(rows, dtype=torch.float32, device=x.device)
+        _check(load().zx_mlp_forward(C.byref(self.handle), _ptr(x), rows, _ptr(score), _stream(stream)))
+        return score
+
+    @staticmethod
+    def loss(score, cost, seg_off, stream=None):
+        import torch
+        n_seg = seg_off.numel() - 1
+        dscore = torch.empty_like(score)
+        loss = torch.empty(max(n_seg, 1), dtype=torch.float32, device=score.device)
+        _check(load().zx_mlp_loss(_ptr(score), _ptr(cost), _ptr(seg_off), n_seg, _ptr(dscore), _ptr(loss),
+                                  _stream(stream)))
+        return dscore, loss[:n_seg]
+
+    def backward(self, x, dscore, ws=None, stream=None):
+        import torch
+        rows = x.shape[0]
+        nb = load().zx_mlp_workspace_bytes(rows)
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        _check(load().zx_mlp_backward(C.byref(self.handle), _ptr(x), _ptr(dscore), rows, _ptr(self.grad),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+        return self.grad
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, grad=None, stream=None):
+        self.step += 1
+        g = self.grad if grad is None else grad
+        _check(load().zx_mlp_adam(C.byref(self.handle), _ptr(g), _ptr(self.m), _ptr(self.v), lr, beta1, beta2,
+                                  eps, self.step, _stream(stream)))
+
+
+class Server:
+    """Continuous-batching simplification service over a device pool."""
+
+    def __init__(self, pool_bytes, max_batch=1024, policy=ZX_POLICY_GREEDY, mlp=None, extract=True,
+                 trusted=False):
+        import torch
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+        self.mlp = mlp
+        self._opts = _opts(extract, -1, policy, mlp, 0, False)
+        h = C.c_void_p()
+        _check(load().zx_server_create(C.byref(h), _ptr(self.pool), pool_bytes, max_batch, C.byref(self._opts),
+                                       ZX_SERVE_TRUSTED if trusted else 0))
+        self.h = h
+        self._out = (Result * 4096)()
+
+    def submit(self, d, tag=0):
+        """Submit a workloads.Diagram; returns the ticket, or None when the
+        pool is full (ZX_EBUSY)."""
+        adj = np.ascontiguousarray(d.adj, dtype=np.uint64)
+        ph = np.ascontiguousarray(d.phase, dtype=np.int8)
+        ins = np.ascontiguousarray(d.inputs, dtype=np.int32)
+        outs = np.ascontiguousarray(d.outputs, dtype=np.int32)
+        bh = None if d.bnd_is_h is None else np.ascontiguousarray(d.bnd_is_h, dtype=np.uint8)
+        r = Request(int(d.n), len(ins), len(outs), 0, adj.ctypes.data, ph.ctypes.data,
+                    ins.ctypes.data if len(ins) else None, outs.ctypes.data if len(outs) else None,
+                    bh.ctypes.data if bh is not None else None, int(tag))
+        t = C.c_int64(-1)
+        rc = load().zx_server_submit(self.h, C.byref(r), C.byref(t))
+        if rc == ZX_EBUSY:
+            return None
+        _check(rc)
+        return t.value
+
+    def poll(self):
+        n = C.c_int32(0)
+        _check(load().zx_server_poll(self.h, C.cast(self._out, C.c_void_p), len(self._out), C.byref(n)))
+        return [Result.from_buffer_copy(self._out[i]) for i in range(n.value)]
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().zx_server_stats_read(self.h, C.byref(st)))
+        return st
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zx_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def rollout(states, per_state, stream=None):
+    """Candidate rollouts of CURRENT diagrams: (cost, fill, move, feats) device
+    tensors of n_states * per_state rows (synchronous)."""
+    import torch
+    n = len(states)
+    arr = _graph_array(states)
+    nb = load().zx_rollout_workspace_bytes(arr, n)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    items = n * per_state
+    cost = torch.empty(items, dtype=torch.int64, device="cuda")
+    fill = torch.empty(items, dtype=torch.int64, device="cuda")
+    move = torch.empty((items, 3), dtype=torch.int32, device="cuda")
+    feats = torch.empty((items, MLP_IN), dtype=torch.int16, device="cuda")
+    _check(load().zx_rollout(arr, n, per_state, _ptr(cost), _ptr(fill), _ptr(move), _ptr(feats), _ptr(ws),
+                             ws.numel(), _stream(stream)))
+    return cost, fill, move, feats
 
 
 def simplify_variants():
