@@ -108,6 +108,11 @@ __device__ __forceinline__ uint64_t wave_shfl64(uint64_t v, int src, int width) 
   return __shfl(v, src, width);
 }
 
+// A value that every lane holds alike (read from LDS after a barrier), made
+// visibly uniform to the compiler: branches and loop bounds on it then
+// compile to scalar control flow instead of exec-mask control flow.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Lane l's 64-bit value, to every lane.  The builtin returns a signed int:
 // each half is taken as uint32 so that the low word is not sign-extended.
 __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
@@ -130,10 +135,10 @@ template <int BS, bool LA>
 __device__ void setup_ctx(Ctx<LA>& c, uint8_t* arena, uint8_t* lds) {
   c.h = (ZxHeader*)arena;
   c.base = arena;
-  c.n = c.h->n;
-  c.W = c.h->W;
-  c.q_in = c.h->n_in;
-  c.q_out = c.h->n_out;
+  c.n = uni(c.h->n);
+  c.W = uni(c.h->W);
+  c.q_in = uni(c.h->n_in);
+  c.q_out = uni(c.h->n_out);
   const int n = c.n, W = c.W;
   uint8_t* p = lds;
   if constexpr (LA) {
@@ -298,7 +303,7 @@ __device__ bool build_candidates(Ctx<LA>& c, Shared& sh, int kind) {
     }
   }
   __syncthreads();
-  return sh.any != 0;
+  return uni(sh.any) != 0;
 }
 
 // Lexicographically-first maximal independent set of the candidates (scan
@@ -552,7 +557,7 @@ constexpr int SPIDER_MAJOR_MAX = 64;
 
 template <int BS, bool LA>
 __device__ void apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
-  const int W = c.W, n = c.n, nsw = sh.nsw, ns = sh.ns;
+  const int W = c.W, n = c.n, nsw = uni(sh.nsw), ns = uni(sh.ns);
   const int rows_per = BS / W;
   const int tw = threadIdx.x / W, j = threadIdx.x - tw * W;
   int64_t pc = 0;
@@ -642,7 +647,7 @@ __device__ void apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
 // their rows, clear alive, phase 0.
 template <int BS, bool LA>
 __device__ void delete_selected(Ctx<LA>& c, Shared& sh) {
-  const int W = c.W, n = c.n, nsw = sh.nsw;
+  const int W = c.W, n = c.n, nsw = uni(sh.nsw);
   const LDSP int32_t* sw = (const LDSP int32_t*)c.blocked;
   if (nsw > 0) {
     for (int it = threadIdx.x; it < n * nsw; it += BS) {
@@ -726,11 +731,11 @@ template <int BS, bool LA, bool LEARN>
 __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds) {
   // every round deletes at least one spider: more than n + 1 rounds from
   // here would be a defect, reported instead of looping on
-  const int round_cap = sh.round + c.n + 1;
+  const int round_cap = uni(sh.round) + c.n + 1;
   // local-complementation rounds
   for (;;) {
-    if (max_rounds > 0 && sh.round >= max_rounds) return;
-    if (sh.round > round_cap) {
+    if (max_rounds > 0 && uni(sh.round) >= max_rounds) return;
+    if (uni(sh.round) > round_cap) {
       sh.status = ZX_EDEVICE;
       return;
     }
@@ -751,7 +756,7 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     for (int j = threadIdx.x; j < c.W; j += BS) cnt += __popcll(c.sel[j]);
     if (cnt) atomicAdd(&sh.cnt, cnt);
     __syncthreads();
-    const int removed = sh.cnt;
+    const int removed = uni(sh.cnt);
     trace_lc_round<BS, LA>(c, sh);
     prepare_round<BS, LA>(c, sh, false, false);
     collect_swords<BS, LA>(c, sh);
@@ -763,14 +768,14 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
   }
   // pivot rounds
   for (;;) {
-    if (max_rounds > 0 && sh.round >= max_rounds) return;
-    if (sh.round > round_cap) {
+    if (max_rounds > 0 && uni(sh.round) >= max_rounds) return;
+    if (uni(sh.round) > round_cap) {
       sh.status = ZX_EDEVICE;
       return;
     }
     if (!build_candidates<BS, LA>(c, sh, 1)) break;
     select_pivots<BS, LA>(c, sh);
-    const int npairs = sh.cnt;
+    const int npairs = uni(sh.cnt);
     if (npairs == 0) break;
     prepare_round<BS, LA>(c, sh, true, false);
     collect_swords<BS, LA>(c, sh);
@@ -966,7 +971,7 @@ __global__ __launch_bounds__(BS) void simplify_kernel(uint8_t* const* table, int
   for (;;) {
     if (threadIdx.x == 0) sh.idx = (int32_t)atomicAdd(&q->next, 1u);
     __syncthreads();
-    const int idx = sh.idx;
+    const int idx = uni(sh.idx);
     __syncthreads();
     if (idx >= n_graphs) break;
     process_diagram<BS, LEARN>(table[idx], smem_dyn, a, sh);
@@ -1002,88 +1007,80 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
   for (;;) {
     if (tid == 0) sh.idx = (int32_t)atomicAdd(&q->next, 1u);
     __syncthreads();
-    const int idx = sh.idx;
+    const int idx = uni(sh.idx);
     __syncthreads();
     if (idx >= a.n_items) break;
     const int si = idx / a.per_state, k = idx - si * a.per_state;
     uint8_t* arena = a.states[si];
     const ZxHeader* h = (const ZxHeader*)arena;
-    const int n = h->n, W = h->W;
-    const bool fits = h->magic == ZX_MAGIC && n >= 1 && W == (n + 63) / 64 && W <= MAXW && n <= 32767 &&
-                      roll_lds_bytes(n, W) <= a.lds_cap &&
-                      (int64_t)h->n_out * W <= a.mbuf_words;
-    if (!fits) {
-      if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = 0;
-      if (tid == 0) {
-        a.cost[idx] = -3;
-        a.fill[idx] = 0;
-        a.move[3 * (int64_t)idx] = -1;
-        a.move[3 * (int64_t)idx + 1] = -1;
-        a.move[3 * (int64_t)idx + 2] = -1;
-      }
-      continue;
-    }
+    const int n = uni(h->n), W = uni(h->W), q_out = uni(h->n_out);
+    const bool fits = uni(h->magic) == ZX_MAGIC && n >= 1 && W == (n + 63) / 64 && W <= MAXW &&
+                      n <= 32767 && roll_lds_bytes(n, W) <= a.lds_cap && (int64_t)q_out * W <= a.mbuf_words;
+    // One structured branch per item, no early exit from the body: every
+    // wave of the block takes the same path through the same barriers.
     Ctx<true> c;
-    setup_ctx<BS, true>(c, arena, smem_dyn);
-    c.trace = nullptr;
     Pol pol;
-    pol.wbf = nullptr;
-    pol.param = nullptr;
-    pol.cap = pol_cap(n);
-    pol.key = nullptr;
-    uint8_t* pa = align16(smem_dyn + lds_adj_bytes(n, W) + aux_bytes(n, W));
-    pol.list = (LDSP uint32_t*)pa;
-    pol.fbuf = (LDSP uint16_t*)(pa + (int64_t)pol.cap * 4);
-    load_state<BS, true>(c, sh, false);
-    // candidates of an LC round; a state past its LC phase has none here
     int C = 0;
-    if (build_candidates<BS, true>(c, sh, 0)) C = list_lc<BS, true>(c, sh, pol);
-    if (k >= C) {
+    if (fits) {
+      setup_ctx<BS, true>(c, arena, smem_dyn);
+      c.trace = nullptr;
+      pol.wbf = nullptr;
+      pol.param = nullptr;
+      pol.cap = pol_cap(n);
+      pol.key = nullptr;
+      uint8_t* pa = align16(smem_dyn + lds_adj_bytes(n, W) + aux_bytes(n, W));
+      pol.list = (LDSP uint32_t*)pa;
+      pol.fbuf = (LDSP uint16_t*)(pa + (int64_t)pol.cap * 4);
+      load_state<BS, true>(c, sh, false);
+      // candidates of an LC round; a state past its LC phase has none here
+      if (build_candidates<BS, true>(c, sh, 0)) C = list_lc<BS, true>(c, sh, pol);
+    }
+    if (fits && k < C) {
+      const int ci = C <= a.per_state ? k : (int)((int64_t)k * C / a.per_state);
+      const int u = uni((int)pol.list[ci]);
+      const float invN = pauli_mask_and_scale<BS, true>(c, sh);
+      if (tid < 64) {
+        candidate_features(c, u, invN, pol.fbuf);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = pol.fbuf[tid];
+      }
+      for (int j = tid; j < W; j += BS) c.sel[j] = 0;
+      __syncthreads();
+      const int64_t fill0 = sh.fill_in;
+      if (tid == 0) {
+        a.move[3 * (int64_t)idx] = 0;
+        a.move[3 * (int64_t)idx + 1] = u;
+        a.move[3 * (int64_t)idx + 2] = -1;
+        c.sel[u >> 6] |= 1ull << (u & 63);
+      }
+      __syncthreads();
+      // the candidate as a one-rewrite round, then the greedy schedule
+      prepare_round<BS, true>(c, sh, false, false);
+      collect_swords<BS, true>(c, sh);
+      apply_round<BS, true>(c, sh, false);
+      delete_selected<BS, true>(c, sh);
+      finish_round<BS, true>(c, sh, 1);
+      simplify_rounds<BS, true, false>(c, sh, nullptr, 0);
+      if (c.q_out > 0) {
+        frontier<BS, true>(c, sh, a.mbuf + (int64_t)blockIdx.x * a.mbuf_words, true, false);
+      } else if (tid == 0) {
+        sh.rowops = 0;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        a.cost[idx] = sh.status ? -4 : sh.E + sh.rowops;
+        a.fill[idx] = sh.fill_in - fill0;
+      }
+    } else {
       if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = 0;
       if (tid == 0) {
-        a.cost[idx] = -1;
+        a.cost[idx] = fits ? -1 : -3;
         a.fill[idx] = 0;
         a.move[3 * (int64_t)idx] = -1;
         a.move[3 * (int64_t)idx + 1] = -1;
         a.move[3 * (int64_t)idx + 2] = -1;
       }
-      continue;
-    }
-    const int ci = C <= a.per_state ? k : (int)((int64_t)k * C / a.per_state);
-    const int u = (int)pol.list[ci];
-    const float invN = pauli_mask_and_scale<BS, true>(c, sh);
-    if (tid < 64) {
-      candidate_features(c, u, invN, pol.fbuf);
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = pol.fbuf[tid];
-    }
-    for (int j = tid; j < W; j += BS) c.sel[j] = 0;
-    __syncthreads();
-    const int64_t fill0 = sh.fill_in;
-    if (tid == 0) {
-      a.move[3 * (int64_t)idx] = 0;
-      a.move[3 * (int64_t)idx + 1] = u;
-      a.move[3 * (int64_t)idx + 2] = -1;
-      c.sel[u >> 6] |= 1ull << (u & 63);
-    }
-    __syncthreads();
-    // the candidate as a one-rewrite round, then the greedy schedule
-    prepare_round<BS, true>(c, sh, false, false);
-    collect_swords<BS, true>(c, sh);
-    apply_round<BS, true>(c, sh, false);
-    delete_selected<BS, true>(c, sh);
-    finish_round<BS, true>(c, sh, 1);
-    simplify_rounds<BS, true, false>(c, sh, nullptr, 0);
-    if (c.q_out > 0) {
-      frontier<BS, true>(c, sh, a.mbuf + (int64_t)blockIdx.x * a.mbuf_words, true, false);
-    } else if (tid == 0) {
-      sh.rowops = 0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      a.cost[idx] = sh.status ? -4 : sh.E + sh.rowops;
-      a.fill[idx] = sh.fill_in - fill0;
     }
     __syncthreads();
   }

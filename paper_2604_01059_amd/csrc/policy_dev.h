@@ -82,7 +82,7 @@ __device__ int list_lc(Ctx<LA>& c, Shared& sh, Pol& p) {
     if (lane == 0) sh.cnt = cnt;
   }
   __syncthreads();
-  const int cnt = sh.cnt;
+  const int cnt = uni(sh.cnt);
   __syncthreads();
   return cnt;
 }
@@ -103,7 +103,7 @@ __device__ float pauli_mask_and_scale(Ctx<LA>& c, Shared& sh) {
     }
   }
   __syncthreads();
-  const int N = sh.key > 0 ? sh.key : 1;
+  const int N = uni(sh.key) > 0 ? uni(sh.key) : 1;
   __syncthreads();
   return 1.0f / (float)N;
 }

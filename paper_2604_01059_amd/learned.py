@@ -64,7 +64,7 @@ def greedy_states(diagrams, max_states=None):
     return states[:max_states] if max_states is not None else states
 
 
-def make_dataset(n_states: int, per_state: int = 16, seed: int = TRAIN_SEED, chunk: int = 256,
+def make_dataset(n_states: int, per_state: int = 16, seed: int = TRAIN_SEED, chunk: int = 128,
                  log=None):
     """(features, costs) for n_states states of greedy runs on the batched
     generator's diagrams: features (n_states * per_state, 16) int16 bf16 bits,
@@ -79,6 +79,9 @@ def make_dataset(n_states: int, per_state: int = 16, seed: int = TRAIN_SEED, chu
         states = greedy_states(ds, max_states=n_states - have)
         if not states:
             continue
+        if log:
+            log("dataset: %d round-start states from diagrams %d..%d, %.1f s"
+                % (len(states), item - chunk, item - 1, time.time() - t0))
         cost, _, _, f = zx.rollout(states, per_state)
         # states past their LC phase have no candidate: drop them
         keep = (cost.view(-1, per_state) >= 0).any(dim=1)
