@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # (KiB, already scaled by the copy-kernel calibration), valid only for the
 # gf2.hip source they were measured on (sha256 prefix); see profiles/.
 RREF_TRAFFIC = {
-    "72cdca17f0fd03eb": {"fetch_kib": 83480.2, "write_kib": 36632.0},
+    "85f2bae1c654fb20": {"fetch_kib": 83476.6, "write_kib": 36857.3},
 }
 METRIC = "GF(2) elim GB/s (% HBM peak); diagrams simplified/sec batched vs plain, bit-exact"
 
@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy"])
     ap.add_argument("--learned-states", type=int, default=20000)
-    ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)

@@ -322,11 +322,13 @@ zx_status zx_rollout(zx_graph* const* states, int32_t n_states, int32_t per_stat
  * paragraph "Compilation") makes simplification a per-circuit service.  A
  * server owns a caller-provided device pool; every request gets a slice of
  * it (its arena) from submit until its result is harvested.  zx_server_poll
- * drives the device: when no batch is running it launches one persistent
- * simplify kernel over up to max_batch admitted requests (oldest first),
- * and when that batch has finished it returns the results and frees the
- * slices.  One batch runs at a time.  Calls on one server must not overlap
- * (one thread at a time); different servers are independent.
+ * drives the device: it harvests finished batches (results out, slices
+ * freed) and fills free batch slots.  Up to 4 batches run at once, each one
+ * persistent simplify launch on its own stream over up to max_batch
+ * admitted requests of one size class (oldest first): requests above 1024
+ * spiders batch apart from the others and hold at most 2 slots, so small
+ * requests never wait behind a large one.  Calls on one server must not
+ * overlap (one thread at a time); different servers are independent.
  * ==================================================================== */
 typedef struct zx_server zx_server;
 
@@ -356,7 +358,8 @@ typedef struct {
 #define ZX_SERVE_TRUSTED 0x1u  /* submit skips the O(n^2) symmetry test */
 
 /* pool: device memory owned by the caller (256-byte aligned) that the server
- * uses for its control data and the request arenas.  o: policy and extract
+ * uses for its control data (4 x (256 + 8 max_batch + 56 max_batch) bytes,
+ * each part rounded up to 256) and the request arenas.  o: policy and extract
  * (tune_id and max_rounds are ignored); NULL = greedy with extraction. */
 zx_status zx_server_create(zx_server** sv, void* pool, size_t pool_bytes, int32_t max_batch,
                            const zx_simplify_opts* o, uint32_t flags);

@@ -95,6 +95,24 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+constexpr int kSlots = 4;          // batches in flight at once
+constexpr int kLargeSlots = 2;     // of which at most this many hold large requests
+constexpr int32_t kLargeN = 1024;  // requests above this many spiders batch apart
+
+// One batch in flight: its control data (device, from the pool), staging
+// (pinned host), stream and completion event.
+struct Slot {
+  void* queue;
+  uint8_t** table_dev;
+  ResDev* res_dev;
+  uint8_t** table_host;
+  ResDev* res_host;
+  hipStream_t stream;
+  hipEvent_t done;
+  bool large;
+  std::vector<Req> running;
+};
+
 struct zx_server {
   uint8_t* pool;
   size_t pool_bytes;
@@ -102,22 +120,18 @@ struct zx_server {
   uint32_t flags;
   zx_simplify_opts opts;
   int32_t max_n;
-  // control data at the head of the pool
-  void* queue;
-  uint8_t** table_dev;
-  ResDev* res_dev;
   uint8_t* arenas;  // request slices start here
   PoolAlloc alloc;
-  // pinned host staging
-  uint8_t** table_host;
-  ResDev* res_host;
-  hipStream_t compute, upload;
-  hipEvent_t done;
+  Slot slot[kSlots];
+  hipStream_t upload;
   std::deque<Req> pending;
-  std::vector<Req> running;
   std::deque<zx_result> finished;
   int64_t next_ticket, submitted, refused, completed, batches;
 };
+
+static size_t slot_head_bytes(int32_t max_batch) {
+  return ZX_QUEUE_BYTES + align256((size_t)max_batch * 8) + align256((size_t)max_batch * sizeof(ResDev));
+}
 
 extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_bytes, int32_t max_batch,
                                       const zx_simplify_opts* o, uint32_t flags) {
@@ -130,7 +144,8 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   ZX_CHECK_ARG(o->policy == ZX_POLICY_GREEDY || o->policy == ZX_POLICY_LEARNED, "unknown policy");
   if (o->policy == ZX_POLICY_LEARNED)
     ZX_CHECK_ARG(o->mlp && o->mlp->param && o->mlp->wbf16, "learned policy needs a network");
-  const size_t head = ZX_QUEUE_BYTES + align256((size_t)max_batch * 8) + align256((size_t)max_batch * sizeof(ResDev));
+  const size_t per_slot = slot_head_bytes(max_batch);
+  const size_t head = kSlots * per_slot;
   if (pool_bytes < head + 4096) {
     zx_set_error("pool too small for max_batch %d", max_batch);
     return ZX_ECAPACITY;
@@ -145,21 +160,28 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   S->opts.max_rounds = 0;
   S->opts.flags = 0;
   S->max_n = zx_max_spiders(o->policy);
-  S->queue = S->pool;
-  S->table_dev = (uint8_t**)(S->pool + ZX_QUEUE_BYTES);
-  S->res_dev = (ResDev*)(S->pool + ZX_QUEUE_BYTES + align256((size_t)max_batch * 8));
   S->arenas = S->pool + head;
   S->alloc.init(pool_bytes - head);
-  S->table_host = nullptr;
-  S->res_host = nullptr;
-  S->compute = S->upload = nullptr;
-  S->done = nullptr;
+  S->upload = nullptr;
   S->next_ticket = S->submitted = S->refused = S->completed = S->batches = 0;
-  hipError_t e = hipHostMalloc((void**)&S->table_host, (size_t)max_batch * 8, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&S->res_host, (size_t)max_batch * sizeof(ResDev), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->compute, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->done, hipEventDisableTiming);
+  hipError_t e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
+  for (int i = 0; i < kSlots; ++i) {
+    Slot& L = S->slot[i];
+    uint8_t* base = S->pool + i * per_slot;
+    L.queue = base;
+    L.table_dev = (uint8_t**)(base + ZX_QUEUE_BYTES);
+    L.res_dev = (ResDev*)(base + ZX_QUEUE_BYTES + align256((size_t)max_batch * 8));
+    L.table_host = nullptr;
+    L.res_host = nullptr;
+    L.stream = nullptr;
+    L.done = nullptr;
+    L.large = false;
+    if (e == hipSuccess) e = hipHostMalloc((void**)&L.table_host, (size_t)max_batch * 8, hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&L.res_host, (size_t)max_batch * sizeof(ResDev), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     zx_set_error("server set-up failed: %s", hipGetErrorString(e));
     zx_server_destroy(S);
@@ -171,13 +193,18 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
 
 extern "C" void zx_server_destroy(zx_server* S) {
   if (!S) return;
-  if (S->compute) (void)hipStreamSynchronize(S->compute);
-  if (S->upload) (void)hipStreamSynchronize(S->upload);
-  if (S->done) (void)hipEventDestroy(S->done);
-  if (S->compute) (void)hipStreamDestroy(S->compute);
-  if (S->upload) (void)hipStreamDestroy(S->upload);
-  if (S->table_host) (void)hipHostFree(S->table_host);
-  if (S->res_host) (void)hipHostFree(S->res_host);
+  for (int i = 0; i < kSlots; ++i) {
+    Slot& L = S->slot[i];
+    if (L.stream) (void)hipStreamSynchronize(L.stream);
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+    if (L.table_host) (void)hipHostFree(L.table_host);
+    if (L.res_host) (void)hipHostFree(L.res_host);
+  }
+  if (S->upload) {
+    (void)hipStreamSynchronize(S->upload);
+    (void)hipStreamDestroy(S->upload);
+  }
   delete S;
 }
 
@@ -222,11 +249,11 @@ extern "C" zx_status zx_server_submit(zx_server* S, const zx_request* r, int64_t
   return ZX_OK;
 }
 
-static zx_status harvest(zx_server* S) {
+static void harvest(zx_server* S, Slot& L) {
   const double t = now_s();
-  for (size_t i = 0; i < S->running.size(); ++i) {
-    const Req& q = S->running[i];
-    const ResDev& d = S->res_host[i];
+  for (size_t i = 0; i < L.running.size(); ++i) {
+    const Req& q = L.running[i];
+    const ResDev& d = L.res_host[i];
     zx_result r;
     r.ticket = q.ticket;
     r.tag = q.tag;
@@ -247,31 +274,41 @@ static zx_status harvest(zx_server* S) {
     S->alloc.release(q.off, q.bytes);
     S->completed++;
   }
-  S->running.clear();
-  return ZX_OK;
+  L.running.clear();
 }
 
-static zx_status launch(zx_server* S) {
-  const size_t k = std::min(S->pending.size(), (size_t)S->max_batch);
-  S->running.assign(S->pending.begin(), S->pending.begin() + (long)k);
-  S->pending.erase(S->pending.begin(), S->pending.begin() + (long)k);
+// Launch the oldest pending request's size class (up to max_batch of them,
+// oldest first) into slot L.
+static zx_status launch(zx_server* S, Slot& L, bool large) {
+  L.running.clear();
+  for (auto it = S->pending.begin(); it != S->pending.end() && (int32_t)L.running.size() < S->max_batch;) {
+    if ((it->n > kLargeN) == large) {
+      L.running.push_back(*it);
+      it = S->pending.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  const size_t k = L.running.size();
+  if (k == 0) return ZX_OK;
+  L.large = large;
   // longest first inside the batch
-  std::stable_sort(S->running.begin(), S->running.end(), [](const Req& a, const Req& b) { return a.n > b.n; });
+  std::stable_sort(L.running.begin(), L.running.end(), [](const Req& a, const Req& b) { return a.n > b.n; });
   const double t = now_s();
   int32_t max_n = 0;
   for (size_t i = 0; i < k; ++i) {
-    S->running[i].t_launch = t;
-    S->table_host[i] = S->running[i].arena;
-    max_n = std::max(max_n, S->running[i].n);
+    L.running[i].t_launch = t;
+    L.table_host[i] = L.running[i].arena;
+    max_n = std::max(max_n, L.running[i].n);
   }
-  ZX_HIP(hipMemcpyAsync(S->table_dev, S->table_host, k * 8, hipMemcpyHostToDevice, S->compute));
-  zx_status st = zx_launch_batch(S->table_dev, (int32_t)k, S->queue, max_n, &S->opts, S->compute);
+  ZX_HIP(hipMemcpyAsync(L.table_dev, L.table_host, k * 8, hipMemcpyHostToDevice, L.stream));
+  zx_status st = zx_launch_batch(L.table_dev, (int32_t)k, L.queue, max_n, &S->opts, L.stream);
   if (st != ZX_OK) return st;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, S->compute, S->table_dev,
-                     (int32_t)k, S->res_dev);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, L.stream, L.table_dev,
+                     (int32_t)k, L.res_dev);
   ZX_HIP(hipGetLastError());
-  ZX_HIP(hipMemcpyAsync(S->res_host, S->res_dev, k * sizeof(ResDev), hipMemcpyDeviceToHost, S->compute));
-  ZX_HIP(hipEventRecord(S->done, S->compute));
+  ZX_HIP(hipMemcpyAsync(L.res_host, L.res_dev, k * sizeof(ResDev), hipMemcpyDeviceToHost, L.stream));
+  ZX_HIP(hipEventRecord(L.done, L.stream));
   S->batches++;
   return ZX_OK;
 }
@@ -279,19 +316,39 @@ static zx_status launch(zx_server* S) {
 extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, int32_t* n_out) {
   zx_clear_error();
   ZX_CHECK_ARG(S && max >= 0 && (max == 0 || out), "bad argument");
-  if (!S->running.empty()) {
-    const hipError_t q = hipEventQuery(S->done);
+  int busy_large = 0;
+  for (int i = 0; i < kSlots; ++i) {
+    Slot& L = S->slot[i];
+    if (L.running.empty()) continue;
+    const hipError_t q = hipEventQuery(L.done);
     if (q == hipSuccess) {
-      zx_status st = harvest(S);
-      if (st != ZX_OK) return st;
+      harvest(S, L);
     } else if (q != hipErrorNotReady) {
       zx_set_error("batch failed: %s", hipGetErrorString(q));
       return ZX_EDEVICE;
+    } else if (L.large) {
+      busy_large++;
     }
   }
-  if (S->running.empty() && !S->pending.empty()) {
-    zx_status st = launch(S);
+  // fill free slots: the class of the oldest pending request first; large
+  // requests never take more than kLargeSlots slots
+  for (int i = 0; i < kSlots && !S->pending.empty(); ++i) {
+    Slot& L = S->slot[i];
+    if (!L.running.empty()) continue;
+    bool want_large = S->pending.front().n > kLargeN;
+    if (want_large && busy_large >= kLargeSlots) {
+      want_large = false;
+      bool any_small = false;
+      for (const Req& q : S->pending)
+        if (q.n <= kLargeN) {
+          any_small = true;
+          break;
+        }
+      if (!any_small) break;
+    }
+    zx_status st = launch(S, L, want_large);
     if (st != ZX_OK) return st;
+    if (want_large) busy_large++;
   }
   int32_t m = 0;
   while (m < max && !S->finished.empty()) {
@@ -305,12 +362,14 @@ extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, i
 extern "C" zx_status zx_server_stats_read(const zx_server* S, zx_server_stats* st) {
   zx_clear_error();
   ZX_CHECK_ARG(S && st, "null argument");
+  int64_t running = 0;
+  for (int i = 0; i < kSlots; ++i) running += (int64_t)S->slot[i].running.size();
   st->submitted = S->submitted;
   st->refused = S->refused;
   st->completed = S->completed;
   st->batches = S->batches;
   st->pending = (int64_t)S->pending.size();
-  st->running = (int64_t)S->running.size();
+  st->running = running;
   st->pool_bytes = S->pool_bytes;
   st->pool_used = S->alloc.used();
   st->pool_peak = S->alloc.peak();

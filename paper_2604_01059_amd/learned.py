@@ -95,7 +95,7 @@ def make_dataset(n_states: int, per_state: int = 16, seed: int = TRAIN_SEED, chu
     return torch.cat(feats), torch.cat(costs)
 
 
-def train(mlp: zx.MLP, feats, costs, per_state: int = 16, epochs: int = 4, batch_states: int = 512,
+def train(mlp: zx.MLP, feats, costs, per_state: int = 16, epochs: int = 4, batch_states: int = 128,
           lr: float = 1e-3, seed: int = TRAIN_SEED, log=None):
     """Adam on the per-state cross-entropy.  Returns the loss curve (mean
     loss of every logged step)."""
@@ -120,7 +120,7 @@ def train(mlp: zx.MLP, feats, costs, per_state: int = 16, epochs: int = 4, batch
             mlp.backward(x, ds, ws=ws)
             mlp.adam(lr=lr)
             step += 1
-            if step % 25 == 0:
+            if step % 20 == 0:
                 curve.append((step, float(loss.mean())))
         if log and curve:
             log("epoch %d: loss %.4f" % (ep, curve[-1][1]))

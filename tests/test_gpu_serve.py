@@ -42,6 +42,10 @@ def check(r, d):
 
 def test_serve_matches_oracle(zx):
     ds = [serve_diagram(5, i, q_hi=64) for i in range(120)]
+    # a few above 1024 spiders: they are batched apart from the rest
+    big = [d for d in (serve_diagram(5, 500 + i, q_lo=100, q_hi=128) for i in range(12)) if d.n > 1024][:3]
+    assert big
+    ds = ds[:60] + big + ds[60:]
     sv = zx.Server(256 << 20, max_batch=48)
     res = []
     print("serve", len(ds), "requests", flush=True)
@@ -63,7 +67,7 @@ def test_serve_matches_oracle(zx):
 def test_serve_admission(zx):
     ds = [serve_diagram(5, 1000 + i, q_hi=48) for i in range(40)]
     biggest = max(zx.Graph.bytes_for(d.n, len(d.inputs), len(d.outputs)) for d in ds)
-    head = 256 + 256 + 256  # queue, table, results for max_batch = 4
+    head = 4 * (256 + 256 + 256)  # per batch slot: queue, table, results for max_batch = 4
     sv = zx.Server(head + 3 * ((biggest + 255) // 256 * 256), max_batch=4)
     todo = list(range(len(ds)))
     res, refused = [], 0
