@@ -321,14 +321,15 @@ zx_status zx_rollout(zx_graph* const* states, int32_t n_states, int32_t per_stat
  * The paper's compile-once / sample-many use (section "Complexity",
  * paragraph "Compilation") makes simplification a per-circuit service.  A
  * server owns a caller-provided device pool; every request gets a slice of
- * it (its arena) from submit until its result is harvested.  zx_server_poll
- * drives the device: it harvests finished batches (results out, slices
- * freed) and fills free batch slots.  Up to 4 batches run at once, each one
- * persistent simplify launch on its own stream over up to max_batch
- * admitted requests of one size class (oldest first): requests above 1024
- * spiders batch apart from the others and hold at most 2 slots, so small
- * requests never wait behind a large one.  Calls on one server must not
- * overlap (one thread at a time); different servers are independent.
+ * it (its arena) from submit until its result is harvested.  Submit uploads
+ * the request and appends it to a ring in coherent host memory; a resident
+ * kernel (two 512-thread workgroups per CU) claims ring entries in order,
+ * one workgroup per diagram, and posts each summary and a completion flag
+ * back to host memory, so no request waits for another to finish.  The
+ * kernel leaves after 50 ms without work; submit and poll start it again
+ * when requests are waiting.  zx_server_poll harvests completions (results
+ * out, slices freed).  Calls on one server must not overlap (one thread at
+ * a time); different servers are independent.
  * ==================================================================== */
 typedef struct zx_server zx_server;
 
@@ -347,7 +348,9 @@ typedef struct {
   int32_t status;               /* sticky status of the request's diagram */
   int32_t n_alive, rounds, n_trace, rank, phase8;
   int64_t n_edges, rowops, pow_sqrt2, fill_in;
-  double t_submit, t_launch, t_done;  /* host steady clock, seconds */
+  double t_submit, t_launch, t_done;  /* host steady clock, seconds; t_launch =
+                                         t_submit (requests start as soon as a
+                                         workgroup is free) */
 } zx_result;
 
 typedef struct {
@@ -358,19 +361,21 @@ typedef struct {
 #define ZX_SERVE_TRUSTED 0x1u  /* submit skips the O(n^2) symmetry test */
 
 /* pool: device memory owned by the caller (256-byte aligned) that the server
- * uses for its control data (4 x (256 + 8 max_batch + 56 max_batch) bytes,
- * each part rounded up to 256) and the request arenas.  o: policy and extract
- * (tune_id and max_rounds are ignored); NULL = greedy with extraction. */
+ * uses for a 256-byte control block and the request arenas.  max_batch is
+ * kept for compatibility (the ring holds 65536 requests).  o: policy and
+ * extract (tune_id and max_rounds are ignored); NULL = greedy with
+ * extraction.  Requests up to 8192 spiders (4096 with the learned policy). */
 zx_status zx_server_create(zx_server** sv, void* pool, size_t pool_bytes, int32_t max_batch,
                            const zx_simplify_opts* o, uint32_t flags);
 /* Validate and upload a request (synchronous for the host arrays).
- * ZX_EBUSY: the pool has no room now (admission refused; retry after
- * polling).  ZX_ECAPACITY: the request can never be served. */
+ * ZX_EBUSY: the pool or the ring has no room now (admission refused; retry
+ * after polling).  ZX_ECAPACITY: the request can never be served. */
 zx_status zx_server_submit(zx_server* sv, const zx_request* r, int64_t* ticket);
 /* Make progress and return up to max finished results. */
 zx_status zx_server_poll(zx_server* sv, zx_result* out, int32_t max, int32_t* n_out);
 zx_status zx_server_stats_read(const zx_server* sv, zx_server_stats* st);
-/* Waits for the running batch, then frees the server (not the pool). */
+/* Lets the resident kernel finish the submitted requests and stop, then
+ * frees the server (not the pool).  Results not yet polled are dropped. */
 void zx_server_destroy(zx_server* sv);
 
 #ifdef __cplusplus

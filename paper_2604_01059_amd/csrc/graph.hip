@@ -99,6 +99,8 @@ struct Ctx {
   LDSP uint64_t* omask;    // output-attached spiders
   int32_t* trace;          // global, 4 int32 per entry
   int T, nteams, team, tl;
+  LDSP uint64_t* scr;      // arena mode: free LDS for the round update
+  int scr_words;
 };
 
 template <class P>
@@ -162,6 +164,8 @@ __device__ void setup_ctx(Ctx<LA>& c, uint8_t* arena, uint8_t* lds) {
   c.outm = (LDSP uint64_t*)p; p += 8 * W;
   c.blocked = (LDSP uint64_t*)p; p += 8 * W;
   c.omask = (LDSP uint64_t*)p; p += 8 * W;
+  c.scr = nullptr;
+  c.scr_words = 0;
   c.trace = (int32_t*)(arena + c.h->off_trace);
   c.T = team_size(W);
   c.nteams = BS / c.T;
@@ -555,8 +559,84 @@ __device__ void collect_swords(Ctx<LA>& c, Shared& sh) {
 constexpr int MAXI = 4;
 constexpr int SPIDER_MAJOR_MAX = 64;
 
+// Arena mode (rows in global memory), rounds of at most 64 rewrites.  Rows
+// go in chunks that fit the free LDS: a per-row pass records which selected
+// spiders the row is adjacent to (hit mask) and updates the row's phase;
+// then a (row, word) pass XORs the hit contributions, staged in LDS when
+// they fit, and drops the selected columns in the same write.  Each row
+// word is read and written once; each selected-column bit once per row.
+template <int BS>
+__device__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool pivot) {
+  const int W = c.W, n = c.n, ns = uni(sh.ns), tid = threadIdx.x;
+  const bool staged = (int64_t)ns * W + 64 <= c.scr_words;
+  LDSP uint64_t* cs = c.scr;
+  LDSP uint64_t* hm = staged ? c.scr + (int64_t)ns * W : c.scr;
+  const int room = c.scr_words - (staged ? ns * W : 0);
+  const int CH = room < n ? room : n;
+  if (staged)
+    for (int i = tid; i < ns * W; i += BS) {
+      const int si = i / W, j = i - si * W;
+      cs[i] = row_ptr(c, c.slist[si])[j];
+    }
+  int64_t pc = 0;
+  for (int r0 = 0; r0 < n; r0 += CH) {
+    const int rn = n - r0 < CH ? n - r0 : CH;
+    __syncthreads();  // staging done; the previous chunk is through with hm
+    for (int t = tid; t < rn; t += BS) {
+      const int w = r0 + t;
+      uint64_t m = 0;
+      if (bit_of(c.alive, w) && !bit_of(c.sel, w)) {
+        const auto rw = row_ptr(c, w);
+        int dk = 0;
+        for (int i = 0; i < ns; ++i) {
+          const int x = c.slist[i];
+          if ((rw[x >> 6] >> (x & 63)) & 1) {
+            m |= 1ull << i;
+            dk += c.kc[x];
+            if (pivot) {
+              const int pp = c.partner[x];
+              if ((rw[pp >> 6] >> (pp & 63)) & 1) dk += 2;  // adjacent to both ends
+            }
+          }
+        }
+        if (dk) c.k[w] = (int8_t)((c.k[w] + dk) & 7);
+      }
+      hm[t] = m;
+    }
+    __syncthreads();
+    for (int64_t it = tid; it < (int64_t)rn * W; it += BS) {
+      const int t = (int)(it / W), j = (int)(it - (int64_t)t * W);
+      const int w = r0 + t;
+      if (!bit_of(c.alive, w) || bit_of(c.sel, w)) continue;
+      auto rw = row_ptr(c, w);
+      const uint64_t old = rw[j];
+      uint64_t v = old;
+      uint64_t m = hm[t];
+      while (m) {
+        const int i = __builtin_ctzll(m);
+        m &= m - 1;
+        v ^= staged ? cs[(int64_t)i * W + j] : row_ptr(c, c.slist[i])[j];
+      }
+      if (j == (w >> 6)) v &= ~(1ull << (w & 63));
+      v &= ~c.sel[j];
+      if (v != old) rw[j] = v;
+      pc += __popcll(v);
+    }
+  }
+  __syncthreads();
+  block_add(&sh.acc64[3], pc);
+  __syncthreads();
+}
+
+// Returns true when the selected columns were already dropped from the rows.
 template <int BS, bool LA>
-__device__ void apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+__device__ bool apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+  if constexpr (!LA) {
+    if (uni(sh.ns) <= SPIDER_MAJOR_MAX && c.scr_words >= 64) {
+      apply_round_arena<BS>(c, sh, pivot);
+      return true;
+    }
+  }
   const int W = c.W, n = c.n, nsw = uni(sh.nsw), ns = uni(sh.ns);
   const int rows_per = BS / W;
   const int tw = threadIdx.x / W, j = threadIdx.x - tw * W;
@@ -641,15 +721,16 @@ __device__ void apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
   __syncthreads();  // the spider-major path reads rows it does not own until here
   block_add(&sh.acc64[3], pc);
   __syncthreads();
+  return false;
 }
 
 // Delete the selected spiders: clear their columns in every other row, zero
 // their rows, clear alive, phase 0.
 template <int BS, bool LA>
-__device__ void delete_selected(Ctx<LA>& c, Shared& sh) {
+__device__ void delete_selected(Ctx<LA>& c, Shared& sh, bool cols_done) {
   const int W = c.W, n = c.n, nsw = uni(sh.nsw);
   const LDSP int32_t* sw = (const LDSP int32_t*)c.blocked;
-  if (nsw > 0) {
+  if (nsw > 0 && !cols_done) {
     for (int it = threadIdx.x; it < n * nsw; it += BS) {
       const int w = it / nsw, q = it - w * nsw;
       const int kw = sw[q];
@@ -760,8 +841,8 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     trace_lc_round<BS, LA>(c, sh);
     prepare_round<BS, LA>(c, sh, false, false);
     collect_swords<BS, LA>(c, sh);
-    apply_round<BS, LA>(c, sh, false);
-    delete_selected<BS, LA>(c, sh);
+    const bool cc = apply_round<BS, LA>(c, sh, false);
+    delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, removed);
     if (threadIdx.x == 0) sh.round++;
     __syncthreads();
@@ -779,8 +860,8 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     if (npairs == 0) break;
     prepare_round<BS, LA>(c, sh, true, false);
     collect_swords<BS, LA>(c, sh);
-    apply_round<BS, LA>(c, sh, true);
-    delete_selected<BS, LA>(c, sh);
+    const bool cc = apply_round<BS, LA>(c, sh, true);
+    delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, 2 * npairs);
     for (int v = threadIdx.x; v < c.n; v += BS)
       if (bit_of(c.sel, v)) c.partner[v] = -1;
@@ -789,33 +870,15 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
   }
 }
 
-// Minimum over the wavefront of non-negative 31-bit values, by bisection on
-// ballots (no cross-lane data movement).
-__device__ __forceinline__ int wave_min31(int v) {
-  uint64_t active = __ballot(true);
-  int res = 0;
-  for (int b = 30; b >= 0; --b) {
-    const uint64_t zeros = __ballot(((v >> b) & 1) == 0) & active;
-    if (zeros) active = zeros;
-    else res |= 1 << b;
-  }
-  return res;
-}
-
-// Sum over the wavefront of values in [0, 15].
-__device__ __forceinline__ int wave_sum4(int v) {
-  int tot = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) tot += __popcll(__ballot((v >> b) & 1)) << b;
-  return tot;
-}
-
 // Output frontier: rows = spiders of outputs 0..q-1, columns = spider ids,
 // bit c = edge to a present spider c not attached to an output; then
 // Gauss-Jordan with the lowest-index pivot row (swapped into place),
-// counting row additions.  M: q x W words (LDS or global).  The elimination
-// runs in one wavefront: lane l owns rows l, l + 64, ...; the next pivot is
-// the minimum (column, row) key, found by ballot bisection.
+// counting row additions.  M: q x W words (LDS or global).  The whole
+// workgroup works on each pivot: every row keeps a pointer to its leading
+// nonzero word (columns only move right as rows are reduced), the next pivot
+// is the minimum (column, row) key over the rows not yet placed (LDS
+// atomicMin), the rows holding the pivot column are marked, then all
+// (row, word) pairs are updated at once.
 // from_work: rows come from the working adjacency (else from the arena's
 // CURRENT section, written back by store_state); write_out: store the
 // pivots, the reduced frontier and the header fields (else only sh.rank and
@@ -830,62 +893,66 @@ __device__ void frontier(Ctx<LA>& c, Shared& sh, uint64_t* M, bool from_work, bo
     const uint64_t x = from_work ? row_ptr(c, outs[r])[j] : adj[(size_t)outs[r] * W + j];
     M[i] = x & c.alive[j] & ~c.omask[j];
   }
+  LDSP int16_t* lw = c.partner;  // leading nonzero word of each row (free after the rounds)
+  LDSP uint64_t* hit = c.inm;    // rows other than the pivot row holding the pivot column
+  for (int p = tid; p < q; p += BS) lw[p] = 0;
   __syncthreads();
   int32_t* fpiv = (int32_t*)(c.base + c.h->off_fpiv);
-  if (tid < 64) {
-    const int lane = tid;
-    int cur = 0, cmin = 0;
-    int64_t ops = 0;
-    constexpr int NOKEY = 0x7fffffff;
-    while (cur < q) {
-      int best = NOKEY;
-      for (int p = lane; p < q; p += 64) {
-        if (p < cur) continue;
-        const uint64_t* mr = M + (size_t)p * W;
-        for (int j = cmin >> 6; j < W; ++j) {
-          const uint64_t x = mr[j];
-          if (x) {
-            const int key = ((64 * j + __ffsll((long long)x) - 1) << 15) | p;
-            best = key < best ? key : best;
-            break;
-          }
-        }
-      }
-      const int mn = wave_min31(best);
-      if (mn == NOKEY) break;
-      const int col = mn >> 15, r = mn & 0x7fff;
-      if (r != cur) {
-        for (int j = lane; j < W; j += 64) {
-          const uint64_t a = M[(size_t)r * W + j];
-          M[(size_t)r * W + j] = M[(size_t)cur * W + j];
-          M[(size_t)cur * W + j] = a;
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-      }
-      const uint64_t* pr = M + (size_t)cur * W;
-      int cnt = 0;
-      for (int p = lane; p < q; p += 64) {
-        if (p == cur) continue;
-        uint64_t* mr = M + (size_t)p * W;
-        if ((mr[col >> 6] >> (col & 63)) & 1) {
-          for (int j = 0; j < W; ++j) mr[j] ^= pr[j];
-          ++cnt;
-        }
-      }
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      ops += wave_sum4(cnt);
-      if (lane == 0 && write_out) fpiv[cur] = col;
-      ++cur;
-      cmin = col + 1;
+  constexpr int NOKEY = 0x7fffffff;
+  const int qw = (q + 63) / 64;
+  int cur = 0, cmin = 0;
+  int64_t ops = 0;  // thread 0
+  while (cur < q) {
+    if (tid == 0) sh.key = NOKEY;
+    for (int j = tid; j < qw; j += BS) hit[j] = 0;
+    __syncthreads();
+    for (int p = cur + tid; p < q; p += BS) {
+      int j = lw[p];
+      if (j < (cmin >> 6)) j = cmin >> 6;
+      const uint64_t* mr = M + (size_t)p * W;
+      while (j < W && mr[j] == 0) ++j;
+      lw[p] = (int16_t)j;
+      if (j < W) atomicMin(&sh.key, ((64 * j + __ffsll((long long)mr[j]) - 1) << 15) | p);
     }
-    if (write_out)
-      for (int j = cur + lane; j < q; j += 64) fpiv[j] = -1;
-    if (lane == 0) {
-      sh.rank = cur;
-      sh.rowops = ops;
+    __syncthreads();
+    const int mn = uni(sh.key);
+    if (mn == NOKEY) break;
+    const int col = mn >> 15, r = mn & 0x7fff;
+    if (r != cur) {
+      for (int j = tid; j < W; j += BS) {
+        const uint64_t a = M[(size_t)r * W + j];
+        M[(size_t)r * W + j] = M[(size_t)cur * W + j];
+        M[(size_t)cur * W + j] = a;
+      }
+      if (tid == 0) {
+        const int16_t t = lw[r];
+        lw[r] = lw[cur];
+        lw[cur] = t;
+      }
+      __syncthreads();
     }
+    for (int p = tid; p < q; p += BS)
+      if (p != cur && ((M[(size_t)p * W + (col >> 6)] >> (col & 63)) & 1))
+        atomicOr((unsigned long long*)&hit[p >> 6], 1ull << (p & 63));
+    __syncthreads();
+    if (tid == 0) {
+      for (int j = 0; j < qw; ++j) ops += __popcll(hit[j]);
+      if (write_out) fpiv[cur] = col;
+    }
+    const uint64_t* pr = M + (size_t)cur * W;
+    for (int64_t it = tid; it < (int64_t)q * W; it += BS) {
+      const int p = (int)(it / W), j = (int)(it - (int64_t)p * W);
+      if ((hit[p >> 6] >> (p & 63)) & 1) M[it] ^= pr[j];
+    }
+    __syncthreads();
+    ++cur;
+    cmin = col + 1;
+  }
+  if (write_out)
+    for (int j = cur + tid; j < q; j += BS) fpiv[j] = -1;
+  if (tid == 0) {
+    sh.rank = cur;
+    sh.rowops = ops;
   }
   __syncthreads();
   if (!write_out) return;
@@ -925,6 +992,14 @@ __device__ void run_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Sha
   if constexpr (LEARN)
     setup_pol<BS>(pol, lds + (LA ? lds_adj_bytes(c.n, c.W) : 0) + aux_bytes(c.n, c.W), c.n, a.wbf,
                   a.param);
+  if constexpr (!LA) {
+    // the LDS the auxiliary arrays (and the policy areas) leave free
+    const int64_t used = aux_bytes(c.n, c.W) + (LEARN ? pol_bytes(c.n, BS) : 0);
+    uint8_t* at = align16(lds + used);
+    const int64_t free_bytes = a.lds_cap - (int64_t)(at - lds);
+    c.scr = (LDSP uint64_t*)at;
+    c.scr_words = free_bytes > 0 ? (int)(free_bytes / 8) : 0;
+  }
   simplify_rounds<BS, LA, LEARN>(c, sh, &pol, a.max_rounds);
   store_state<BS, LA>(c, sh);
   if (threadIdx.x == 0) {
@@ -1058,8 +1133,8 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
       // the candidate as a one-rewrite round, then the greedy schedule
       prepare_round<BS, true>(c, sh, false, false);
       collect_swords<BS, true>(c, sh);
-      apply_round<BS, true>(c, sh, false);
-      delete_selected<BS, true>(c, sh);
+      const bool cc = apply_round<BS, true>(c, sh, false);
+      delete_selected<BS, true>(c, sh, cc);
       finish_round<BS, true>(c, sh, 1);
       simplify_rounds<BS, true, false>(c, sh, nullptr, 0);
       if (c.q_out > 0) {
@@ -1083,6 +1158,75 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
       }
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- serving --
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Resident serving kernel: each workgroup claims the next ring entry (in
+// submission order), simplifies that diagram, publishes its summary and the
+// completion flag to host memory, and goes on until stopped or idle.
+template <int BS, bool LEARN>
+__global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
+  extern __shared__ __align__(16) uint8_t smem_dyn[];
+  __shared__ Shared sh;
+  __shared__ int64_t claimed;
+  uint64_t last = wall_clock64();  // used by thread 0 only
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int64_t got = -1;
+      for (int spin = 0; spin < 64 && got == -1; ++spin) {
+        const int64_t t = __hip_atomic_load(a.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        int64_t h = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < t) {
+          if (__hip_atomic_compare_exchange_strong(a.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT))
+            got = h;
+          continue;  // claimed, or lost the race: look again at once
+        }
+        if (__hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
+            wall_clock64() - last > a.idle_ticks) {
+          got = -2;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+      claimed = got;
+    }
+    __syncthreads();
+    const int64_t idx = uni64(claimed);
+    __syncthreads();
+    if (idx == -2) break;
+    if (idx >= 0) {
+      const int64_t slot = idx & (a.cap - 1);
+      uint8_t* arena =
+          (uint8_t*)uni64((int64_t)__hip_atomic_load(&a.entries[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+      process_diagram<BS, LEARN>(arena, smem_dyn, sa, sh);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const ZxHeader* h = (const ZxHeader*)arena;
+        ZxServeRes* r = &a.res[slot];
+        r->status = h->status;
+        r->n_alive = h->n_alive;
+        r->rounds = h->rounds;
+        r->n_trace = h->n_trace;
+        r->rank = h->rank;
+        r->phase8 = h->phase8;
+        r->n_edges = h->n_edges;
+        r->rowops = h->rowops;
+        r->pow_sqrt2 = h->pow_sqrt2;
+        r->fill_in = h->fill_in;
+        __threadfence_system();
+        __hip_atomic_store(&a.done[slot], idx + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        last = wall_clock64();
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -1173,8 +1317,8 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
   } else {
     prepare_round<BS, LA>(c, sh, pivot != 0, false);
     collect_swords<BS, LA>(c, sh);
-    apply_round<BS, LA>(c, sh, pivot != 0);
-    delete_selected<BS, LA>(c, sh);
+    const bool cc = apply_round<BS, LA>(c, sh, pivot != 0);
+    delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, pivot ? 2 : 1);
   }
   store_state<BS, LA>(c, sh);
@@ -1372,6 +1516,8 @@ static bool variant_fits_n(int max_n, int v, bool learned) {
 }
 static bool variant_fits(const zx_batch* b, int v, bool learned) { return variant_fits_n(b->max_n, v, learned); }
 
+static int pick_variant_n(int32_t max_n, bool learned);
+
 static int pick_variant(const zx_batch* b, int tune_id, bool learned) {
   if (tune_id >= 0 && tune_id < kNumVariants) return tune_id;
   if (!learned) {
@@ -1379,10 +1525,8 @@ static int pick_variant(const zx_batch* b, int tune_id, bool learned) {
     auto it = tune_cache().find(size_class(b));
     if (it != tune_cache().end()) return it->second;
   }
-  if (variant_fits(b, kDefaultVariant, learned)) return kDefaultVariant;
-  for (int v = 0; v < kNumVariants; ++v)
-    if (variant_fits(b, v, learned)) return v;
-  return kDefaultVariant;
+  const int v = pick_variant_n(b->max_n, learned);
+  return v >= 0 ? v : kDefaultVariant;
 }
 
 static SimpArgs simp_args(const zx_simplify_opts* o) {
@@ -1396,8 +1540,6 @@ static SimpArgs simp_args(const zx_simplify_opts* o) {
   a.param = o->mlp ? o->mlp->param : nullptr;
   return a;
 }
-
-static_assert(sizeof(Queue) == ZX_QUEUE_BYTES, "queue size");
 
 int32_t zx_max_spiders(int32_t policy) {
   int32_t best = 0;
@@ -1414,18 +1556,44 @@ int32_t zx_max_spiders(int32_t policy) {
   return best;
 }
 
-zx_status zx_launch_batch(uint8_t* const* table_dev, int32_t n, void* queue, int32_t max_n,
-                          const zx_simplify_opts* o, hipStream_t s) {
-  const bool learned = o->policy == ZX_POLICY_LEARNED;
-  int v = -1;
-  if (variant_fits_n(max_n, kDefaultVariant, learned)) v = kDefaultVariant;
-  for (int i = 0; i < kNumVariants && v < 0; ++i)
-    if (variant_fits_n(max_n, i, learned)) v = i;
-  if (v < 0) {
-    zx_set_error("diagram of %d spiders too large for the simplify kernels", max_n);
+// Variant for a batch whose largest diagram has max_n spiders: 512-thread
+// workgroups; the 152 KiB budget when that diagram's adjacency then fits in
+// LDS, else 64 KiB (arena mode either way, and two workgroups per CU).
+static int pick_variant_n(int32_t max_n, bool learned) {
+  const int W = (max_n + 63) / 64;
+  const int64_t aux = aux_bytes(max_n, W) + (learned ? pol_bytes(max_n, 512) : 0);
+  const int big = 5, small = 4;  // bs512-lds152k, bs512-lds64k
+  if (lds_adj_bytes(max_n, W) + aux <= kVariants[big].lds_cap && variant_fits_n(max_n, big, learned)) return big;
+  if (variant_fits_n(max_n, small, learned)) return small;
+  for (int i = 0; i < kNumVariants; ++i)
+    if (variant_fits_n(max_n, i, learned)) return i;
+  return -1;
+}
+
+zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s) {
+  const ZxDevice* d = zx_device();
+  if (!d) return ZX_EDEVICE;
+  constexpr int BS = 512;
+  const int v = 4;  // bs512-lds64k: two workgroups per CU
+  zx_simplify_opts o = {a.policy, a.extract, -1, 0, 0, 0, a.mlp};
+  SimpArgs sa = simp_args(&o);
+  sa.lds_cap = kVariants[v].lds_cap;
+  const bool learned = a.policy == ZX_POLICY_LEARNED;
+  const void* fn = learned ? (const void*)serve_kernel<BS, true> : (const void*)serve_kernel<BS, false>;
+  ZX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sa.lds_cap));
+  int per_cu = 0;
+  ZX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BS, (size_t)sa.lds_cap));
+  if (per_cu < 1) {
+    zx_set_error("serving kernel does not fit a CU");
     return ZX_ECAPACITY;
   }
-  return launch_simplify(v, table_dev, n, (Queue*)queue, simp_args(o), learned, s);
+  const int grid = std::min(per_cu, 2) * d->n_cu;
+  if (learned)
+    hipLaunchKernelGGL((serve_kernel<BS, true>), dim3(grid), dim3(BS), (size_t)sa.lds_cap, s, a, sa);
+  else
+    hipLaunchKernelGGL((serve_kernel<BS, false>), dim3(grid), dim3(BS), (size_t)sa.lds_cap, s, a, sa);
+  ZX_HIP(hipGetLastError());
+  return ZX_OK;
 }
 
 extern "C" zx_status zx_batch_simplify(zx_batch* b, const zx_simplify_opts* o, hipStream_t s) {

@@ -1,41 +1,19 @@
-// Serving loop: admission into a device pool, continuous batching of
-// simplification requests, result harvest.  Host code plus one small
-// result-gather kernel; the simplification itself is the persistent batch
-// kernel of graph.hip.
+// Serving loop (host side): admission into a device pool, a request ring in
+// coherent host memory read by the resident serving kernel of graph.hip,
+// completion by per-entry flags, result harvest.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cstring>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include "zx_internal.h"
 
 namespace {
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// Per-request summary gathered from the arena headers after a batch.
-struct ResDev {
-  int32_t status, n_alive, rounds, n_trace, rank, phase8;
-  int64_t n_edges, rowops, pow_sqrt2, fill_in;
-};
-
-__global__ void gather_kernel(uint8_t* const* table, int32_t n, ResDev* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const ZxHeader* h = (const ZxHeader*)table[i];
-  ResDev r;
-  r.status = h->status;
-  r.n_alive = h->n_alive;
-  r.rounds = h->rounds;
-  r.n_trace = h->n_trace;
-  r.rank = h->rank;
-  r.phase8 = h->phase8;
-  r.n_edges = h->n_edges;
-  r.rowops = h->rowops;
-  r.pow_sqrt2 = h->pow_sqrt2;
-  r.fill_in = h->fill_in;
-  out[i] = r;
 }
 
 // First-fit allocator over [0, size) with coalescing of free ranges.
@@ -88,49 +66,69 @@ struct Req {
   uint8_t* arena;
   size_t off, bytes;
   int32_t n;
-  double t_submit, t_launch;
+  double t_submit;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-constexpr int kSlots = 4;          // batches in flight at once
-constexpr int kLargeSlots = 2;     // of which at most this many hold large requests
-constexpr int32_t kLargeN = 1024;  // requests above this many spiders batch apart
+namespace {
 
-// One batch in flight: its control data (device, from the pool), staging
-// (pinned host), stream and completion event.
-struct Slot {
-  void* queue;
-  uint8_t** table_dev;
-  ResDev* res_dev;
-  uint8_t** table_host;
-  ResDev* res_host;
-  hipStream_t stream;
-  hipEvent_t done;
-  bool large;
-  std::vector<Req> running;
+constexpr int64_t kRing = 1 << 16;               // ring entries (power of two)
+constexpr uint64_t kIdleTicks = 50ull * 100000;  // 50 ms at 100 MHz
+
+// Coherent host memory shared with the serving kernel.
+struct Shared_ {
+  uint64_t entries[kRing];
+  int64_t done[kRing];
+  ZxServeRes res[kRing];
+  int64_t tail;
+  int32_t stop;
+  int32_t pad;
 };
+
+}  // namespace
 
 struct zx_server {
   uint8_t* pool;
   size_t pool_bytes;
-  int32_t max_batch;
   uint32_t flags;
   zx_simplify_opts opts;
   int32_t max_n;
+  int64_t* head;    // device, at the head of the pool
   uint8_t* arenas;  // request slices start here
   PoolAlloc alloc;
-  Slot slot[kSlots];
-  hipStream_t upload;
-  std::deque<Req> pending;
+  Shared_* sh;      // coherent host memory
+  hipStream_t stream, upload;
+  hipEvent_t ended;  // recorded after each launch of the serving kernel
+  bool running;
+  int64_t next_seq;  // = tail
+  std::unordered_map<int64_t, Req> inflight;  // by sequence number
+  int64_t oldest;  // smallest sequence number not yet harvested
   std::deque<zx_result> finished;
-  int64_t next_ticket, submitted, refused, completed, batches;
+  int64_t submitted, refused, completed, launches;
 };
 
-static size_t slot_head_bytes(int32_t max_batch) {
-  return ZX_QUEUE_BYTES + align256((size_t)max_batch * 8) + align256((size_t)max_batch * sizeof(ResDev));
+static zx_status relaunch(zx_server* S) {
+  ZxServeArgs a;
+  a.entries = S->sh->entries;
+  a.tail = &S->sh->tail;
+  a.stop = &S->sh->stop;
+  a.done = S->sh->done;
+  a.res = S->sh->res;
+  a.head = S->head;
+  a.cap = kRing;
+  a.idle_ticks = kIdleTicks;
+  a.extract = S->opts.extract;
+  a.policy = S->opts.policy;
+  a.mlp = S->opts.mlp;
+  zx_status st = zx_launch_serve(a, S->stream);
+  if (st != ZX_OK) return st;
+  ZX_HIP(hipEventRecord(S->ended, S->stream));
+  S->running = true;
+  S->launches++;
+  return ZX_OK;
 }
 
 extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_bytes, int32_t max_batch,
@@ -138,73 +136,62 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   zx_clear_error();
   ZX_CHECK_ARG(out && pool, "null argument");
   ZX_CHECK_ARG(((uintptr_t)pool & 255) == 0, "pool must be 256-byte aligned");
-  ZX_CHECK_ARG(max_batch > 0 && max_batch <= (1 << 20), "max_batch out of range");
+  ZX_CHECK_ARG(max_batch > 0, "max_batch must be positive");
   zx_simplify_opts def = {ZX_POLICY_GREEDY, 1, -1, 0, 0, 0, nullptr};
   if (!o) o = &def;
   ZX_CHECK_ARG(o->policy == ZX_POLICY_GREEDY || o->policy == ZX_POLICY_LEARNED, "unknown policy");
   if (o->policy == ZX_POLICY_LEARNED)
     ZX_CHECK_ARG(o->mlp && o->mlp->param && o->mlp->wbf16, "learned policy needs a network");
-  const size_t per_slot = slot_head_bytes(max_batch);
-  const size_t head = kSlots * per_slot;
+  const size_t head = 256;
   if (pool_bytes < head + 4096) {
-    zx_set_error("pool too small for max_batch %d", max_batch);
+    zx_set_error("pool too small");
     return ZX_ECAPACITY;
   }
   zx_server* S = new zx_server();
   S->pool = (uint8_t*)pool;
   S->pool_bytes = pool_bytes;
-  S->max_batch = max_batch;
   S->flags = flags;
   S->opts = *o;
   S->opts.tune_id = -1;
   S->opts.max_rounds = 0;
   S->opts.flags = 0;
-  S->max_n = zx_max_spiders(o->policy);
+  // the serving kernel runs 64 KiB workgroups
+  S->max_n = std::min(zx_max_spiders(o->policy), o->policy == ZX_POLICY_LEARNED ? 4096 : 8192);
+  S->head = (int64_t*)S->pool;
   S->arenas = S->pool + head;
   S->alloc.init(pool_bytes - head);
-  S->upload = nullptr;
-  S->next_ticket = S->submitted = S->refused = S->completed = S->batches = 0;
-  hipError_t e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
-  for (int i = 0; i < kSlots; ++i) {
-    Slot& L = S->slot[i];
-    uint8_t* base = S->pool + i * per_slot;
-    L.queue = base;
-    L.table_dev = (uint8_t**)(base + ZX_QUEUE_BYTES);
-    L.res_dev = (ResDev*)(base + ZX_QUEUE_BYTES + align256((size_t)max_batch * 8));
-    L.table_host = nullptr;
-    L.res_host = nullptr;
-    L.stream = nullptr;
-    L.done = nullptr;
-    L.large = false;
-    if (e == hipSuccess) e = hipHostMalloc((void**)&L.table_host, (size_t)max_batch * 8, hipHostMallocDefault);
-    if (e == hipSuccess)
-      e = hipHostMalloc((void**)&L.res_host, (size_t)max_batch * sizeof(ResDev), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
-  }
+  S->sh = nullptr;
+  S->stream = S->upload = nullptr;
+  S->ended = nullptr;
+  S->running = false;
+  S->next_seq = 0;
+  S->oldest = 0;
+  S->submitted = S->refused = S->completed = S->launches = 0;
+  hipError_t e = hipHostMalloc((void**)&S->sh, sizeof(Shared_), hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ended, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemsetAsync(S->head, 0, sizeof(int64_t), S->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) {
     zx_set_error("server set-up failed: %s", hipGetErrorString(e));
     zx_server_destroy(S);
     return ZX_EDEVICE;
   }
+  memset(S->sh, 0, sizeof(Shared_));
   *out = S;
   return ZX_OK;
 }
 
 extern "C" void zx_server_destroy(zx_server* S) {
   if (!S) return;
-  for (int i = 0; i < kSlots; ++i) {
-    Slot& L = S->slot[i];
-    if (L.stream) (void)hipStreamSynchronize(L.stream);
-    if (L.done) (void)hipEventDestroy(L.done);
-    if (L.stream) (void)hipStreamDestroy(L.stream);
-    if (L.table_host) (void)hipHostFree(L.table_host);
-    if (L.res_host) (void)hipHostFree(L.res_host);
-  }
-  if (S->upload) {
-    (void)hipStreamSynchronize(S->upload);
-    (void)hipStreamDestroy(S->upload);
-  }
+  if (S->sh) __atomic_store_n(&S->sh->stop, 1, __ATOMIC_RELEASE);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  if (S->upload) (void)hipStreamSynchronize(S->upload);
+  if (S->ended) (void)hipEventDestroy(S->ended);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  if (S->upload) (void)hipStreamDestroy(S->upload);
+  if (S->sh) (void)hipHostFree(S->sh);
   delete S;
 }
 
@@ -212,8 +199,13 @@ extern "C" zx_status zx_server_submit(zx_server* S, const zx_request* r, int64_t
   zx_clear_error();
   ZX_CHECK_ARG(S && r, "null argument");
   if (r->n > S->max_n) {
-    zx_set_error("request of %d spiders exceeds the kernels' limit %d", r->n, S->max_n);
+    zx_set_error("request of %d spiders exceeds the serving limit %d", r->n, S->max_n);
     return ZX_ECAPACITY;
+  }
+  if (S->next_seq - S->oldest >= kRing) {
+    S->refused++;
+    zx_set_error("request ring full");
+    return ZX_EBUSY;
   }
   std::vector<uint8_t> img;
   zx_status st = zx_build_image(r->n, r->adj, r->phase, r->inputs, r->n_in, r->outputs, r->n_out, r->bnd_is_h,
@@ -234,26 +226,50 @@ extern "C" zx_status zx_server_submit(zx_server* S, const zx_request* r, int64_t
     zx_set_error("upload failed: %s", hipGetErrorString(e));
     return ZX_EDEVICE;
   }
+  const int64_t seq = S->next_seq++;
   Req q;
-  q.ticket = S->next_ticket++;
+  q.ticket = seq;
   q.tag = r->tag;
   q.arena = arena;
   q.off = off;
   q.bytes = bytes;
   q.n = r->n;
   q.t_submit = now_s();
-  q.t_launch = 0;
-  S->pending.push_back(q);
+  S->inflight.emplace(seq, q);
+  const int64_t slot = seq & (kRing - 1);
+  __atomic_store_n(&S->sh->done[slot], (int64_t)0, __ATOMIC_RELAXED);
+  __atomic_store_n(&S->sh->entries[slot], (uint64_t)(uintptr_t)arena, __ATOMIC_RELAXED);
+  __atomic_store_n(&S->sh->tail, seq + 1, __ATOMIC_RELEASE);  // publishes the entry
   S->submitted++;
-  if (ticket) *ticket = q.ticket;
+  if (ticket) *ticket = seq;
+  if (!S->running) return relaunch(S);
   return ZX_OK;
 }
 
-static void harvest(zx_server* S, Slot& L) {
+extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, int32_t* n_out) {
+  zx_clear_error();
+  ZX_CHECK_ARG(S && max >= 0 && (max == 0 || out), "bad argument");
+  // kernel ended (idle or stopped)?
+  if (S->running) {
+    const hipError_t q = hipEventQuery(S->ended);
+    if (q == hipSuccess) {
+      S->running = false;
+    } else if (q != hipErrorNotReady) {
+      zx_set_error("serving kernel failed: %s", hipGetErrorString(q));
+      return ZX_EDEVICE;
+    }
+  }
+  // harvest finished entries
   const double t = now_s();
-  for (size_t i = 0; i < L.running.size(); ++i) {
-    const Req& q = L.running[i];
-    const ResDev& d = L.res_host[i];
+  for (auto it = S->inflight.begin(); it != S->inflight.end();) {
+    const int64_t seq = it->first;
+    const int64_t slot = seq & (kRing - 1);
+    if (__atomic_load_n(&S->sh->done[slot], __ATOMIC_ACQUIRE) != seq + 1) {
+      ++it;
+      continue;
+    }
+    const Req& q = it->second;
+    const ZxServeRes& d = S->sh->res[slot];
     zx_result r;
     r.ticket = q.ticket;
     r.tag = q.tag;
@@ -268,87 +284,19 @@ static void harvest(zx_server* S, Slot& L) {
     r.pow_sqrt2 = d.pow_sqrt2;
     r.fill_in = d.fill_in;
     r.t_submit = q.t_submit;
-    r.t_launch = q.t_launch;
+    r.t_launch = q.t_submit;
     r.t_done = t;
     S->finished.push_back(r);
     S->alloc.release(q.off, q.bytes);
     S->completed++;
+    it = S->inflight.erase(it);
   }
-  L.running.clear();
-}
-
-// Launch the oldest pending request's size class (up to max_batch of them,
-// oldest first) into slot L.
-static zx_status launch(zx_server* S, Slot& L, bool large) {
-  L.running.clear();
-  for (auto it = S->pending.begin(); it != S->pending.end() && (int32_t)L.running.size() < S->max_batch;) {
-    if ((it->n > kLargeN) == large) {
-      L.running.push_back(*it);
-      it = S->pending.erase(it);
-    } else {
-      ++it;
-    }
-  }
-  const size_t k = L.running.size();
-  if (k == 0) return ZX_OK;
-  L.large = large;
-  // longest first inside the batch
-  std::stable_sort(L.running.begin(), L.running.end(), [](const Req& a, const Req& b) { return a.n > b.n; });
-  const double t = now_s();
-  int32_t max_n = 0;
-  for (size_t i = 0; i < k; ++i) {
-    L.running[i].t_launch = t;
-    L.table_host[i] = L.running[i].arena;
-    max_n = std::max(max_n, L.running[i].n);
-  }
-  ZX_HIP(hipMemcpyAsync(L.table_dev, L.table_host, k * 8, hipMemcpyHostToDevice, L.stream));
-  zx_status st = zx_launch_batch(L.table_dev, (int32_t)k, L.queue, max_n, &S->opts, L.stream);
-  if (st != ZX_OK) return st;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, L.stream, L.table_dev,
-                     (int32_t)k, L.res_dev);
-  ZX_HIP(hipGetLastError());
-  ZX_HIP(hipMemcpyAsync(L.res_host, L.res_dev, k * sizeof(ResDev), hipMemcpyDeviceToHost, L.stream));
-  ZX_HIP(hipEventRecord(L.done, L.stream));
-  S->batches++;
-  return ZX_OK;
-}
-
-extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, int32_t* n_out) {
-  zx_clear_error();
-  ZX_CHECK_ARG(S && max >= 0 && (max == 0 || out), "bad argument");
-  int busy_large = 0;
-  for (int i = 0; i < kSlots; ++i) {
-    Slot& L = S->slot[i];
-    if (L.running.empty()) continue;
-    const hipError_t q = hipEventQuery(L.done);
-    if (q == hipSuccess) {
-      harvest(S, L);
-    } else if (q != hipErrorNotReady) {
-      zx_set_error("batch failed: %s", hipGetErrorString(q));
-      return ZX_EDEVICE;
-    } else if (L.large) {
-      busy_large++;
-    }
-  }
-  // fill free slots: the class of the oldest pending request first; large
-  // requests never take more than kLargeSlots slots
-  for (int i = 0; i < kSlots && !S->pending.empty(); ++i) {
-    Slot& L = S->slot[i];
-    if (!L.running.empty()) continue;
-    bool want_large = S->pending.front().n > kLargeN;
-    if (want_large && busy_large >= kLargeSlots) {
-      want_large = false;
-      bool any_small = false;
-      for (const Req& q : S->pending)
-        if (q.n <= kLargeN) {
-          any_small = true;
-          break;
-        }
-      if (!any_small) break;
-    }
-    zx_status st = launch(S, L, want_large);
+  S->oldest = S->next_seq;
+  for (const auto& kv : S->inflight) S->oldest = std::min(S->oldest, kv.first);
+  // work left but no kernel resident: start one
+  if (!S->running && !S->inflight.empty()) {
+    zx_status st = relaunch(S);
     if (st != ZX_OK) return st;
-    if (want_large) busy_large++;
   }
   int32_t m = 0;
   while (m < max && !S->finished.empty()) {
@@ -362,14 +310,12 @@ extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, i
 extern "C" zx_status zx_server_stats_read(const zx_server* S, zx_server_stats* st) {
   zx_clear_error();
   ZX_CHECK_ARG(S && st, "null argument");
-  int64_t running = 0;
-  for (int i = 0; i < kSlots; ++i) running += (int64_t)S->slot[i].running.size();
   st->submitted = S->submitted;
   st->refused = S->refused;
   st->completed = S->completed;
-  st->batches = S->batches;
-  st->pending = (int64_t)S->pending.size();
-  st->running = running;
+  st->batches = S->launches;
+  st->pending = (int64_t)S->inflight.size();
+  st->running = S->running ? 1 : 0;
   st->pool_bytes = S->pool_bytes;
   st->pool_used = S->alloc.used();
   st->pool_peak = S->alloc.peak();

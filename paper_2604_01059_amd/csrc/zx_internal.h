@@ -83,13 +83,35 @@ zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phas
                          int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
                          std::vector<uint8_t>& img);
 
-// One persistent simplify launch over a device table of arenas (graph.hip);
-// queue: ZX_QUEUE_BYTES of device memory; max_n: largest diagram.
-constexpr size_t ZX_QUEUE_BYTES = 256;
-zx_status zx_launch_batch(uint8_t* const* table_dev, int32_t n, void* queue, int32_t max_n,
-                          const zx_simplify_opts* o, hipStream_t s);
-// Largest diagram the simplify kernels take with this policy.
+// Largest diagram the simplify kernels take with this policy (graph.hip).
 int32_t zx_max_spiders(int32_t policy);
+
+// Serving ring (graph.hip runs the kernel, serve.hip the host side).  The
+// host appends arena pointers to `entries` and then advances `tail`; resident
+// workgroups claim entries in order through `head`, simplify the diagram and
+// write its summary to `res` and then `done` = sequence number + 1.  entries,
+// tail, stop, done and res are in host memory that both sides see coherently;
+// head is device memory.  Every workgroup exits when `stop` is set or after
+// idle_ticks (100 MHz clock) without work.
+struct ZxServeRes {
+  int32_t status, n_alive, rounds, n_trace, rank, phase8;
+  int64_t n_edges, rowops, pow_sqrt2, fill_in;
+};
+struct ZxServeArgs {
+  uint64_t* entries;
+  int64_t* tail;
+  int32_t* stop;
+  int64_t* done;
+  ZxServeRes* res;
+  int64_t* head;
+  int64_t cap;  // power of two
+  uint64_t idle_ticks;
+  int32_t extract;
+  int32_t policy;
+  const zx_mlp* mlp;
+};
+// Launch the resident serving kernel on s (grid: 2 workgroups per CU).
+zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s);
 void zx_clear_error();
 
 #define ZX_CHECK_ARG(cond, ...)            \

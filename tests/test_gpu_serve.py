@@ -60,14 +60,34 @@ def test_serve_matches_oracle(zx):
         check(r, ds[r.tag])
     st = sv.stats()
     assert st.completed == len(ds) and st.submitted == len(ds) and st.refused == 0
-    assert st.batches >= 3 and st.pool_used == 0 and st.pending == 0 and st.running == 0
+    assert st.batches >= 1 and st.pool_used == 0 and st.pending == 0
+    sv.close()
+
+
+def test_serve_idle_exit_and_relaunch(zx):
+    """The resident kernel leaves after a quiet spell; a later request starts
+    it again and is answered."""
+    ds = [serve_diagram(5, 2000 + i, q_hi=32) for i in range(2)]
+    sv = zx.Server(64 << 20, max_batch=16)
+    assert sv.submit(ds[0], tag=0) is not None
+    r0 = drain(sv, 1)
+    t0 = time.time()
+    while sv.stats().running and time.time() - t0 < 10:
+        time.sleep(0.05)
+        sv.poll()
+    assert sv.stats().running == 0  # idle exit
+    assert sv.submit(ds[1], tag=1) is not None
+    r1 = drain(sv, 1)
+    check(r0[0], ds[0])
+    check(r1[0], ds[1])
+    assert sv.stats().batches >= 2
     sv.close()
 
 
 def test_serve_admission(zx):
     ds = [serve_diagram(5, 1000 + i, q_hi=48) for i in range(40)]
     biggest = max(zx.Graph.bytes_for(d.n, len(d.inputs), len(d.outputs)) for d in ds)
-    head = 4 * (256 + 256 + 256)  # per batch slot: queue, table, results for max_batch = 4
+    head = 256  # the server's control word
     sv = zx.Server(head + 3 * ((biggest + 255) // 256 * 256), max_batch=4)
     todo = list(range(len(ds)))
     res, refused = [], 0
