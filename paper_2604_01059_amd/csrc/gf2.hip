@@ -47,6 +47,11 @@
 
 namespace {
 
+// LDS pointers carry their address space, so that every access compiles to a
+// ds_* instruction: a flat access counts on vmcnt as well, and its wait would
+// also wait for every global store still in flight.
+#define LDS __attribute__((address_space(3)))
+
 constexpr int BS = 512;           // threads per workgroup
 constexpr int NWAVE = BS / 64;
 constexpr int SW = 32;            // columns per strip
@@ -154,11 +159,9 @@ __global__ void rref_init(Ctl* ctl, int32_t* status, uint64_t* prof) {
 struct Smem {
   uint64_t tab[MAX_CW][128];   // 8 nibble tables of reduced pivot words, per column
   uint64_t otab[MAX_CW][128];  // 8 nibble tables of original pivot words, per column
-  uint64_t orig[MAX_CW][SW];
   uint64_t pp[MAX_CW][SW];
   uint64_t Q[MAX_CW][SW];      // reduced pivot word by strip bit position
-  uint64_t cmask[MAX_SL * NWAVE];  // candidate ballots by (slice, wave) = row order
-  int32_t cpre[MAX_SL * NWAVE];    // exclusive prefix of their popcounts
+  int32_t wcnt[NWAVE];         // candidates per wave
   uint32_t L[SW];
   int32_t rows[SW];
   int32_t bits[SW];
@@ -166,119 +169,137 @@ struct Smem {
   int32_t prow[SW];            // sorted pivot list of a multi-pass strip
   int32_t pcol[SW];
   uint32_t pivmask;
+  uint32_t ackc[RING];         // acknowledgements known per ring slot (a lower bound)
   int32_t k, last, total, flag, cnt, efirst, pad;
 };
+
+// 64-bit words of LDS before the columns (the Smem block, 16-byte aligned)
+__host__ __device__ constexpr int smem_head_words() { return (int)((sizeof(Smem) + 15) / 16 * 2); }
 
 __device__ __forceinline__ void prof_mark(const Args& a, int s, int slot) {
   if (a.prof && s < MAX_STRIPS) st_dev64(&a.prof[(size_t)s * PROF_SLOTS + slot], wall_clock64());
 }
 
-__device__ __forceinline__ bool bit_of(const uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1; }
+__device__ __forceinline__ bool bit_of(const LDS uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1; }
 
-// Position of the n-th (0-based) set bit of x; x must have more than n bits.
-__device__ __forceinline__ int select_bit(uint64_t x, int n) {
-  int pos = 0;
-#pragma unroll
-  for (int w = 32; w >= 1; w >>= 1) {
-    const uint64_t lowmask = (w == 64) ? ~0ull : ((1ull << w) - 1);
-    const int c = __popcll(x & lowmask);
-    if (n >= c) {
-      n -= c;
-      x >>= w;
-      pos += w;
-    }
-  }
-  return pos;
-}
-
-// Exclusive prefix sum over the wavefront of values in [0, 127] and their
-// total, from one ballot per bit and the lane-prefix bit count (v_mbcnt).
-__device__ __forceinline__ void wave_exclusive_scan7(int v, int& ex, int& tot) {
-  ex = 0;
-  tot = 0;
-#pragma unroll
-  for (int bit = 0; bit < 7; ++bit) {
-    const uint64_t b = __ballot((v >> bit) & 1);
-    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
-    ex += below << bit;
-    tot += __popcll(b) << bit;
-  }
-}
-
-// Candidates in row order from per-thread flags (bit i = row tid + i*BS):
-// the first NCAND go to S.cand, the count of all to S.total.
-__device__ void compact_candidates(uint32_t flags, int nsl, Smem& S) {
+// Candidates from per-thread flags (bit i = row tid + i*BS): up to NCAND of
+// them go to S.cand, the count of all to S.total.  Any set of candidate rows
+// gives the same basis (the reduced echelon form is unique), so each wave
+// places its own candidates after those of lower waves: one count per wave,
+// one barrier, then a lane-prefix (v_mbcnt) per slice.
+__device__ void compact_candidates(uint32_t flags, int nsl, LDS Smem& S) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = 0; i < nsl; ++i) {
-    const uint64_t b = __ballot((flags >> i) & 1);
-    if (lane == 0) S.cmask[i * NWAVE + wv] = b;
-  }
+  int cnt = 0;
+  for (int i = 0; i < nsl; ++i) cnt += __popcll(__ballot((flags >> i) & 1));
+  if (lane == 0) S.wcnt[wv] = cnt;
   __syncthreads();
-  if (tid < 64) {
-    const int ne = nsl * NWAVE;
-    int base = 0, efirst = -1;
-    for (int e0 = 0; e0 < ne; e0 += 64) {
-      const int e = e0 + lane;
-      const uint64_t msk = e < ne ? S.cmask[e] : 0;
-      const int c = __popcll(msk);
-      int ex, tot;
-      wave_exclusive_scan7(c, ex, tot);
-      if (e < ne) S.cpre[e] = base + ex;
-      const uint64_t nz = __ballot(c > 0);
-      if (efirst < 0 && nz) efirst = e0 + __builtin_ctzll(nz);
-      base += tot;
-    }
-    // lane p fills candidate slot p: scan entries from the first non-empty one
-    const int p = lane;
-    if (efirst >= 0) {
-      for (int e = efirst; e < ne; ++e) {
-        const int pe = S.cpre[e];
-        if (pe >= NCAND) break;
-        const uint64_t msk = S.cmask[e];
-        const int c = __popcll(msk);
-        if (p >= pe && p < pe + c) S.cand[p] = (e / NWAVE) * BS + (e % NWAVE) * 64 + select_bit(msk, p - pe);
-      }
-    }
-    if (lane == 0) S.total = base;
+  int base = 0, total = 0;
+#pragma unroll
+  for (int v = 0; v < NWAVE; ++v) {
+    const int c = S.wcnt[v];
+    base += v < wv ? c : 0;
+    total += c;
+  }
+  if (tid == 0) S.total = total;
+  for (int i = 0; i < nsl && base < NCAND; ++i) {
+    const bool f = (flags >> i) & 1;
+    const uint64_t b = __ballot(f);
+    const int idx = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
+    if (f && idx < NCAND) S.cand[idx] = i * BS + tid;
+    base += __popcll(b);
   }
   __syncthreads();
 }
 
-// Wave 0: reduce the candidates (S.cand, min(S.total, NCAND) of them), using
-// bits [shift, shift + 32) of the LDS column `col`.  Fills S.k, rows, bits,
-// L, pivmask.  The bit loop is unrolled and branch-free: a bit with no
-// candidate is a no-op, every other bit costs one ballot, one s_ff1, two
-// readlanes and a few selects.
-__device__ void factor_candidates(const uint64_t* col, int shift, Smem& S) {
+// Waves 1..7 (while wave 0 reduces the candidates): write the strip snapshot,
+// bits [shift, shift+32) of LDS column `col` of every row, to `snap`.  They do
+// not wait for these stores here, and wave 0 issues none, so the reduction
+// never waits on them (vmcnt counts stores as well as loads on this
+// architecture); the publishing barrier waits for them.
+__device__ void store_snapshot(const LDS uint64_t* col, int shift, int m, uint32_t* snap) {
+  constexpr int T = BS - 64, U = 4;
+  for (int r0 = (int)threadIdx.x - 64; r0 < m; r0 += U * T) {
+    uint32_t v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) v[q] = r0 + q * T < m ? (uint32_t)(col[r0 + q * T] >> shift) : 0u;
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+      if (r0 + q * T < m) st_dev(&snap[r0 + q * T], v[q]);
+  }
+}
+
+// One elimination step of the candidate reduction, for strip bit B, in
+// wavefront registers: w = the lane's candidate strip word, L = its mask of
+// original pivots, jb = 1 + pivot index | B << 8 on pivot lanes; P = lanes
+// already pivots, k = pivots so far, pm = strip bits holding pivots.
+//   h = lanes holding bit B; c = h & ~P; if c is empty the step is a no-op;
+//   else src = first lane of c becomes pivot k: every other lane of h gets
+//   w ^= w[src], L ^= L[src] | 1 << k, and lane src gets L = L[src] | 1 << k.
+// Written out by hand (about twenty instructions; a single wave issues about
+// one instruction per four cycles, so the count sets the cost): the XORs run
+// under an exec mask of h minus src, the pivot's own update under an exec
+// mask of src alone, and exec is restored before the block ends.
+template <int B>
+__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k,
+                                            uint32_t& pm) {
+  uint64_t c, m, sv;
+  uint32_t t, spw, spl, sjb;
+  int src;
+  asm volatile(
+      "v_and_b32 %[t], %[bit], %[w]\n\t"
+      "v_cmp_ne_u32 vcc, 0, %[t]\n\t"
+      "s_andn2_b64 %[c], vcc, %[P]\n\t"
+      "s_cmp_eq_u64 %[c], 0\n\t"
+      "s_cbranch_scc1 .Lfactor_skip%=\n\t"
+      "s_ff1_i32_b64 %[src], %[c]\n\t"
+      "s_lshl_b64 %[m], 1, %[src]\n\t"
+      "s_or_b64 %[P], %[P], %[m]\n\t"
+      "s_andn2_b64 vcc, vcc, %[m]\n\t"
+      "v_readlane_b32 %[spw], %[w], %[src]\n\t"
+      "v_readlane_b32 %[spl], %[L], %[src]\n\t"
+      "s_bitset1_b32 %[spl], %[k]\n\t"
+      "s_add_u32 %[sjb], %[k], %[jbk]\n\t"
+      "s_and_saveexec_b64 %[sv], vcc\n\t"
+      "v_xor_b32 %[w], %[spw], %[w]\n\t"
+      "v_xor_b32 %[L], %[spl], %[L]\n\t"
+      "s_and_b64 exec, %[sv], %[m]\n\t"
+      "v_mov_b32 %[L], %[spl]\n\t"
+      "v_mov_b32 %[jb], %[sjb]\n\t"
+      "s_mov_b64 exec, %[sv]\n\t"
+      "s_add_u32 %[k], %[k], 1\n\t"
+      "s_or_b32 %[pm], %[pm], %[bit]\n"
+      ".Lfactor_skip%=:"
+      : [w] "+v"(w), [L] "+v"(L), [jb] "+v"(jb), [P] "+s"(P), [k] "+s"(k), [pm] "+s"(pm), [t] "=&v"(t),
+        [c] "=&s"(c), [m] "=&s"(m), [sv] "=&s"(sv), [spw] "=&s"(spw), [spl] "=&s"(spl), [sjb] "=&s"(sjb),
+        [src] "=&s"(src)
+      : [bit] "s"(1u << B), [jbk] "s"((uint32_t)((B << 8) + 1))
+      : "vcc", "scc");
+}
+
+template <int B>
+__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k,
+                                             uint32_t& pm) {
+  factor_step<B>(w, L, jb, P, k, pm);
+  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, jb, P, k, pm);
+}
+
+// Wave 0 (all 64 lanes active): reduce the candidates (S.cand, min(S.total,
+// NCAND) of them), using bits [shift, shift + 32) of the LDS column `col`:
+// Gauss-Jordan over the strip bits in ascending order.  Fills S.k, rows,
+// bits, L, pivmask.
+__device__ void factor_candidates(const LDS uint64_t* col, int shift, LDS Smem& S) {
   const int lane = threadIdx.x & 63;
   const int nc = S.total < NCAND ? S.total : NCAND;
   uint32_t w = lane < nc ? (uint32_t)(col[S.cand[lane]] >> shift) : 0;
-  uint32_t L = 0, pm = 0;
-  uint64_t P = 0;  // lanes already chosen as pivots (uniform)
-  int j = -1, bb = 0, k = 0;
-#pragma unroll
-  for (int b = 0; b < SW; ++b) {
-    const bool mine = (w >> b) & 1;
-    const uint64_t h = __ballot(mine);
-    const uint64_t c = h & ~P;
-    const bool valid = c != 0;
-    const int src = valid ? (int)__builtin_ctzll(c) : 0;
-    const uint32_t pw = __builtin_amdgcn_readlane(w, src);
-    const uint32_t pl = __builtin_amdgcn_readlane(L, src) | (1u << (k & 31));
-    const bool is_src = valid && lane == src;
-    const bool elim = valid && mine && !is_src;
-    w ^= elim ? pw : 0u;
-    L = is_src ? pl : (L ^ (elim ? pl : 0u));
-    j = is_src ? k : j;
-    bb = is_src ? b : bb;
-    P |= valid ? (1ull << src) : 0ull;
-    pm |= valid ? (1u << b) : 0u;
-    k += valid ? 1 : 0;
-  }
-  if (j >= 0) {
+  uint32_t L = 0, jb = 0, pm = 0;
+  uint64_t P = 0;
+  int k = 0;
+  factor_steps<0>(w, L, jb, P, k, pm);
+  if (jb) {
+    const int j = (int)(jb & 0xff) - 1;
     S.L[j] = L;
     S.rows[j] = S.cand[lane];
-    S.bits[j] = bb;
+    S.bits[j] = (int)(jb >> 8);
   }
   if (lane == 0) {
     S.k = k;
@@ -286,23 +307,29 @@ __device__ void factor_candidates(const uint64_t* col, int shift, Smem& S) {
   }
 }
 
-// Reduced pivot words and nibble tables of `nc` columns for the pass in S.
-__device__ void make_tables(uint64_t* const* cols, int nc, Smem& S) {
+// Reduced pivot words and nibble tables of `nc` columns for the pass in S;
+// also marks this pass's pivot rows in newpiv.  Three barriers: nibble
+// tables of the original pivot words (read straight from the columns), then
+// the reduced words P'_t (eight lookups by the nibbles of L_t) placed at
+// their strip bits, then the nibble tables of those.
+__device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* newpiv, LDS Smem& S) {
   const int tid = threadIdx.x, k = S.k;
-  for (int x = tid; x < nc * SW; x += BS) {
-    const int j = x / SW, t = x % SW;
-    S.Q[j][t] = 0;
-    S.orig[j][t] = t < k ? cols[j][S.rows[t]] : 0;
+  if (tid < k) {
+    const int r = S.rows[tid];
+    __hip_atomic_fetch_or(&newpiv[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  __syncthreads();
   for (int x = tid; x < nc * 128; x += BS) {
     const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
+    const LDS uint64_t* c = cols[j];
+    uint64_t o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = c[4 * q + i < k ? S.rows[4 * q + i] : 0];
     uint64_t v = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if ((sel >> i) & 1) v ^= S.orig[j][4 * q + i];
+    for (int i = 0; i < 4; ++i) v ^= (((sel >> i) & 1) && 4 * q + i < k) ? o[i] : 0ull;
     S.otab[j][e] = v;
   }
+  for (int x = tid; x < nc * SW; x += BS) S.Q[x / SW][x % SW] = 0;
   __syncthreads();
   for (int x = tid; x < nc * SW; x += BS) {
     const int j = x / SW, t = x % SW;
@@ -327,91 +354,127 @@ __device__ void make_tables(uint64_t* const* cols, int nc, Smem& S) {
   __syncthreads();
 }
 
-__device__ __forceinline__ uint64_t lookup8(const uint64_t* tab, uint32_t mr) {
-  uint64_t acc = 0;
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // v_bitop3: a ^ b ^ c in one instruction
+}
+
+// v ^ (XOR of the 8 nibble-table entries selected by mr)
+__device__ __forceinline__ uint64_t lookup8(const LDS uint64_t* tab, uint32_t mr, uint64_t v) {
+  uint64_t t[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc ^= tab[16 * q + ((mr >> (4 * q)) & 15)];
-  return acc;
+  for (int q = 0; q < 8; ++q) t[q] = tab[16 * q + __builtin_amdgcn_ubfe(mr, 4 * q, 4)];
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int q = 0; q < 8; q += 2) {
+    lo = xor3(lo, (uint32_t)t[q], (uint32_t)t[q + 1]);
+    hi = xor3(hi, (uint32_t)(t[q] >> 32), (uint32_t)(t[q + 1] >> 32));
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// One group of GROUP row slices of one column: v ^= T(mr) row by row, all
+// loads of the group in flight together (no branch between rows).  FULL:
+// every slice of the group exists.  With FUSE, returns the candidate flags
+// of the group's rows (bits [fshift, fshift+32) non-zero, not done).
+template <bool FULL, bool FUSE>
+__device__ __forceinline__ uint32_t apply_group(LDS uint64_t* c, const LDS uint64_t* tab, const uint32_t* mr,
+                                                const uint64_t* done, int i0, int nsl, int fshift) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  uint64_t v[GROUP];
+#pragma unroll
+  for (int q = 0; q < GROUP; ++q)
+    if (FULL || i0 + q < nsl) v[q] = c[(i0 + q) * BS + tid];
+#pragma unroll
+  for (int q = 0; q < GROUP; ++q)
+    if (FULL || i0 + q < nsl) v[q] = lookup8(tab, mr[q], v[q]);
+#pragma unroll
+  for (int q = 0; q < GROUP; ++q)
+    if (FULL || i0 + q < nsl) c[(i0 + q) * BS + tid] = v[q];
+  uint32_t f = 0;
+  if (FUSE) {
+#pragma unroll
+    for (int q = 0; q < GROUP; ++q)
+      if (FULL || i0 + q < nsl)
+        f |= (((uint32_t)(v[q] >> fshift) != 0u) && !((done[q] >> lane) & 1)) ? (1u << (i0 + q)) : 0u;
+  }
+  return f;
+}
+
+template <bool FULL>
+__device__ __forceinline__ uint32_t apply_cols(LDS uint64_t* const* cols, int nc, const uint32_t* mr,
+                                               const uint64_t* done, int i0, int nsl, int fuse, int fshift,
+                                               LDS Smem& S) {
+  if (nc == 1)  // the usual case: table at a fixed address
+    return fuse == 0 ? apply_group<FULL, true>(cols[0], S.tab[0], mr, done, i0, nsl, fshift)
+                     : apply_group<FULL, false>(cols[0], S.tab[0], mr, done, i0, nsl, fshift);
+  uint32_t f = 0;
+  for (int j = 0; j < nc; ++j)
+    f |= j == fuse ? apply_group<FULL, true>(cols[j], S.tab[j], mr, done, i0, nsl, fshift)
+                   : apply_group<FULL, false>(cols[j], S.tab[j], mr, done, i0, nsl, fshift);
+  return f;
 }
 
 // Apply the pass in S to `nc` LDS word columns.  Multipliers (the strip word
 // of every row before the pass) come from the global snapshot `snap`
 // (consumers) or from bits [shift, shift+32) of the LDS column `strip` (the
-// owner; that column may be one of `cols`: each row's multiplier is read
-// before the row is updated).  newpiv must hold this pass's pivot rows.
-// With fuse >= 0, bits [fshift, fshift+32) of column cols[fuse] after the
-// update are written to `snap_out` and the non-pivot rows where they are
-// non-zero are returned as candidate flags (bit i = row tid + i*BS).  `pre`
-// (optional) holds the first GROUP multipliers, already loaded.
-// On return pivot rows hold P' and pivflag includes them.
-__device__ uint32_t apply_record(uint64_t* const* cols, int nc, const uint32_t* snap, const uint64_t* strip,
-                                 int shift, int m, uint64_t* pivflag, uint64_t* newpiv, int fuse,
-                                 int fshift, uint32_t* snap_out, const uint32_t* pre, Smem& S) {
-  const int tid = threadIdx.x;
+// owner; that column may be one of `cols`: a group's multipliers are all read
+// before its rows are updated).  newpiv must hold this pass's pivot rows;
+// they are not updated here (multiplier 0 looks up table entry 0, which is
+// zero).  With fuse >= 0, the rows not yet pivots whose bits
+// [fshift, fshift+32) of column cols[fuse] are non-zero after the update are
+// returned as candidate flags (bit i = row tid + i*BS).  `pre` (optional)
+// holds the first GROUP multipliers, already loaded.  LDS work only: no
+// global stores.  On return pivot rows hold P' and pivflag includes them.
+__device__ uint32_t apply_record(LDS uint64_t* const* cols, int nc, const uint32_t* snap,
+                                 const LDS uint64_t* strip, int shift, int m, LDS uint64_t* pivflag,
+                                 LDS uint64_t* newpiv, int fuse, int fshift, const uint32_t* pre, LDS Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nsl = (m + BS - 1) / BS;
   const uint32_t pm = S.pivmask;
   uint32_t flags = 0;
   for (int i0 = 0; i0 < nsl; i0 += GROUP) {
-    uint32_t mv[GROUP];
+    uint32_t mr[GROUP];
+    uint64_t done[GROUP];
 #pragma unroll
     for (int q = 0; q < GROUP; ++q) {
-      const int r = (i0 + q) * BS + tid;
-      if (i0 == 0 && pre) mv[q] = pre[q];
-      else if (r >= m) mv[q] = 0;
-      else mv[q] = snap ? ld_dev(&snap[r]) : (uint32_t)(strip[r] >> shift);
+      const int i = i0 + q, r = i * BS + tid;
+      uint32_t x = 0;
+      if (i0 == 0 && pre) x = pre[q];
+      else if (r < m) x = snap ? ld_dev(&snap[r]) : (uint32_t)(strip[r] >> shift);
+      // the wave's 64 rows of slice i share one word of each flag array
+      const uint64_t npw = i < nsl ? newpiv[i * NWAVE + wv] : ~0ull;
+      done[q] = i < nsl ? (pivflag[i * NWAVE + wv] | npw) : ~0ull;
+      mr[q] = ((npw >> lane) & 1) ? 0u : (x & pm);
     }
-#pragma unroll
-    for (int q = 0; q < GROUP; ++q) {
-      const int i = i0 + q;
-      const int r = i * BS + tid;
-      if (r >= m) continue;
-      const uint32_t mr = mv[q] & pm;
-      const bool np = bit_of(newpiv, r);
-      for (int j = 0; j < nc; ++j) {
-        uint64_t v = cols[j][r];
-        if (mr && !np) {
-          v ^= lookup8(S.tab[j], mr);
-          cols[j][r] = v;
-        }
-        if (j == fuse && !np) {
-          const uint32_t h = (uint32_t)(v >> fshift);
-          st_dev(&snap_out[r], h);
-          if (h != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
-        }
-      }
-    }
+    flags |= i0 + GROUP <= nsl ? apply_cols<true>(cols, nc, mr, done, i0, nsl, fuse, fshift, S)
+                               : apply_cols<false>(cols, nc, mr, done, i0, nsl, fuse, fshift, S);
   }
   __syncthreads();
   const int k = S.k;
   for (int x = tid; x < nc * SW; x += BS) {
     const int j = x / SW, t = x % SW;
-    if (t < k) {
-      cols[j][S.rows[t]] = S.pp[j][t];
-      if (j == fuse) st_dev(&snap_out[S.rows[t]], (uint32_t)(S.pp[j][t] >> fshift));
-    }
+    if (t < k) cols[j][S.rows[t]] = S.pp[j][t];
   }
   if (tid < k) {
     const int r = S.rows[tid];
-    atomicOr((unsigned long long*)&pivflag[r >> 6], 1ull << (r & 63));
-    atomicAnd((unsigned long long*)&newpiv[r >> 6], ~(1ull << (r & 63)));
+    __hip_atomic_fetch_or(&pivflag[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_and(&newpiv[r >> 6], ~(1ull << (r & 63)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __syncthreads();
   return flags;
 }
 
-__device__ void mark_newpiv(uint64_t* newpiv, Smem& S) {
-  if ((int)threadIdx.x < S.k) {
-    const int r = S.rows[threadIdx.x];
-    atomicOr((unsigned long long*)&newpiv[r >> 6], 1ull << (r & 63));
-  }
-  __syncthreads();
-}
-
 // Thread 0 waits until ring slot `slot` may be overwritten by record `idx`.
-__device__ bool wait_slot(uint32_t idx, int G, const Args& a, Smem& S) {
+// Acknowledgements are monotonic: a count read earlier (S.ackc, prefetched
+// off the critical path) that already suffices saves the device-scope load.
+__device__ bool wait_slot(uint32_t idx, int G, const Args& a, LDS Smem& S) {
+  const uint32_t need = (idx / RING) * (uint32_t)(G - 1);
+  if ((uint32_t)__builtin_amdgcn_readfirstlane((int)S.ackc[idx % RING]) >= need) return true;
+  __syncthreads();  // every wave has read S.ackc before thread 0 rewrites it
   if (threadIdx.x == 0) {
-    const uint32_t need = (idx / RING) * (uint32_t)(G - 1);
-    S.flag = spin_until(&a.ctl->ack[idx % RING], need, a) ? 1 : 0;
+    const bool ok = spin_until(&a.ctl->ack[idx % RING], need, a);
+    S.flag = ok ? 1 : 0;
+    if (ok) S.ackc[idx % RING] = need;
   }
   __syncthreads();
   return S.flag != 0;
@@ -424,35 +487,43 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   const int m = a.m;
   const int nsl = (m + BS - 1) / BS;
   const int nown = (a.nw - g + G - 1) / G;  // word columns owned: g, g+G, ...
-  const int pw = (m + 63) / 64;
-  uint64_t* cols = smem;                              // [cw][m]
-  uint64_t* pivflag = cols + (size_t)a.cw * m;        // [pw]
-  uint64_t* newpiv = pivflag + pw;                    // [pw]
-  Smem& S = *reinterpret_cast<Smem*>(newpiv + pw);
+  const int ms = nsl * BS;                  // column stride: rows padded with zeros
+  const int pw = ms / 64;
+  // the pass tables first, at a fixed LDS address (immediate offsets)
+  LDS uint64_t* base = (LDS uint64_t*)smem;
+  LDS Smem& S = *reinterpret_cast<LDS Smem*>(base);
+  LDS uint64_t* cols = base + smem_head_words();                 // [cw][ms]
+  LDS uint64_t* pivflag = cols + (size_t)a.cw * ms;              // [pw]
+  LDS uint64_t* newpiv = pivflag + pw;                           // [pw]
 
   for (int j = 0; j < nown; ++j) {
     const int c = g + j * G;
     const int tail = a.n_cols - 64 * c;
     const uint64_t cm = tail >= 64 ? ~0ull : ((1ull << tail) - 1);
-    for (int r = tid; r < m; r += BS) cols[(size_t)j * m + r] = a.A[(size_t)r * a.ld + c] & cm;
+    for (int r = tid; r < ms; r += BS) cols[(size_t)j * ms + r] = r < m ? a.A[(size_t)r * a.ld + c] & cm : 0;
   }
   for (int i = tid; i < pw; i += BS) {
     pivflag[i] = 0;
     newpiv[i] = 0;
   }
+  if (tid < RING) S.ackc[tid] = 0;
   __syncthreads();
 
   uint32_t seq = 0;       // next record index
   int rank = 0;
   bool ok = true;
-  bool prepared = false;  // snapshot of my next strip written, its candidates in S
+  bool prepared = false;  // candidates of my next strip in S, its snapshot pending
+  // snapshot to be written by waves 1..7 during the next reduction
+  const LDS uint64_t* pend_col = nullptr;
+  int pend_shift = 0;
+  uint32_t* pend_snap = nullptr;
   for (int t = 0; t < a.nstrips && rank < m && ok; ++t) {
     const int wc = t >> 1, shift = SW * (t & 1);
     const int owner = wc % G;
     if (owner == g) {
       // ---------------- produce strip t ----------------
       const int js = wc / G;
-      uint64_t* col = cols + (size_t)js * m;
+      LDS uint64_t* col = cols + (size_t)js * ms;
       const int rank0 = rank;
       bool multi = false;
       if (tid == 0) prof_mark(a, t, 0);
@@ -464,21 +535,27 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           uint32_t flags = 0;
           for (int i = 0; i < nsl; ++i) {
             const int r = i * BS + tid;
-            if (r < m) {
-              const uint32_t v = (uint32_t)(col[r] >> shift);
-              st_dev(&snap[r], v);
-              if (v != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
-            }
+            if (r < m && (uint32_t)(col[r] >> shift) != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
           }
           compact_candidates(flags, nsl, S);
+          pend_col = col;
+          pend_shift = shift;
+          pend_snap = snap;
         }
         prepared = false;
         if (tid == 0) prof_mark(a, t, 1);
         const int total = S.total;
         if (tid < 64) {
+          // the next slot's acknowledgements, loaded while the reduction runs
+          const uint32_t nslot = (seq + 1) % RING;
+          const uint32_t ackv = tid == 0 ? ld_dev(&a.ctl->ack[nslot]) : 0u;
           if (total > 0) factor_candidates(col, shift, S);
           else if (tid == 0) { S.k = 0; S.pivmask = 0; }
+          if (tid == 0 && ackv > S.ackc[nslot]) S.ackc[nslot] = ackv;
+        } else if (pend_snap) {
+          store_snapshot(pend_col, pend_shift, m, pend_snap);
         }
+        pend_snap = nullptr;
         __syncthreads();
         if (tid == 0) prof_mark(a, t, 6);
         const int k = S.k;
@@ -534,27 +611,28 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           wait_stores();
           __syncthreads();
         }
-        if (tid == 0) {
-          st_dev(&a.ctl->seq, seq + 1);
-          prof_mark(a, t, 2);
-        }
+        // the flag and the acknowledgements are stored from wave 1, which
+        // never reduces candidates: wave 0 then has no store in flight
+        if (tid == 64) st_dev(&a.ctl->seq, seq + 1);
+        if (tid == 0) prof_mark(a, t, 2);
         ++seq;
         if (k > 0) {
           // the high half of this word column is my next strip: write its
           // snapshot and candidates while applying this pass
           const bool fused = last && (t & 1) == 0 && t + 1 < a.nstrips;
           if (fused && !wait_slot(seq, G, a, S)) { ok = false; break; }
-          uint64_t* list[MAX_CW];
+          LDS uint64_t* list[MAX_CW];
           int nc = 0;
-          for (int j = js; j < nown; ++j) list[nc++] = cols + (size_t)j * m;
-          mark_newpiv(newpiv, S);
-          make_tables(list, nc, S);
+          for (int j = js; j < nown; ++j) list[nc++] = cols + (size_t)j * ms;
+          make_tables(list, nc, newpiv, S);
           const uint32_t flags = apply_record(list, nc, nullptr, col, shift, m, pivflag, newpiv,
-                                              fused ? 0 : -1, SW, a.snaps + (size_t)(seq % RING) * m,
-                                              nullptr, S);
+                                              fused ? 0 : -1, SW, nullptr, S);
           rank += k;
           if (fused) {
             compact_candidates(flags, nsl, S);
+            pend_col = col;
+            pend_shift = SW;
+            pend_snap = a.snaps + (size_t)(seq % RING) * m;
             prepared = true;
           }
         }
@@ -585,6 +663,10 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           S.k = ld_dev32(&rec->k);
           S.last = ld_dev32(&rec->last);
           S.pivmask = ld_dev(&rec->pivmask);
+          if (own_next) {
+            const uint32_t nslot = (seq + 1) % RING, v = ld_dev(&a.ctl->ack[nslot]);
+            if (v > S.ackc[nslot]) S.ackc[nslot] = v;
+          }
         }
         if (tid < SW) {
           S.rows[tid] = ld_dev32(&rec->rows[tid]);
@@ -599,28 +681,28 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         if (k > 0) {
           rank += k;  // every workgroup tracks the rank (the loops end together)
           // owned word columns after wc
-          uint64_t* list[MAX_CW];
+          LDS uint64_t* list[MAX_CW];
           int nc = 0, fuse = -1;
           for (int j = (wc - g) >= 0 ? (wc - g) / G + 1 : 0; j < nown; ++j) {
             if (fused && g + j * G == ((t + 1) >> 1)) fuse = nc;
-            list[nc++] = cols + (size_t)j * m;
+            list[nc++] = cols + (size_t)j * ms;
           }
           if (nc > 0) {
-            mark_newpiv(newpiv, S);
-            make_tables(list, nc, S);
+            make_tables(list, nc, newpiv, S);
             const uint32_t flags = apply_record(list, nc, snap, nullptr, 0, m, pivflag, newpiv, fuse, 0,
-                                                a.snaps + (size_t)((seq + 1) % RING) * m, pre, S);
+                                                pre, S);
             if (fused) {
               compact_candidates(flags, nsl, S);
+              pend_col = list[fuse];
+              pend_shift = 0;
+              pend_snap = a.snaps + (size_t)((seq + 1) % RING) * m;
               prepared = true;
             }
           }
         }
         __syncthreads();
-        if (tid == 0) {
-          __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (own_next && last) prof_mark(a, t, 5);
-        }
+        if (tid == 64) __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0 && own_next && last) prof_mark(a, t, 5);
         ++seq;
         if (last) break;
       }
@@ -630,7 +712,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   // ---------------- write the result ----------------
   for (int j = 0; j < nown; ++j) {
     const int c = g + j * G;
-    const uint64_t* col = cols + (size_t)j * m;
+    const LDS uint64_t* col = cols + (size_t)j * ms;
     for (int i = tid; i < m; i += BS) {
       uint64_t v = 0;
       if (i < rank) v = col[ld_dev32(&a.piv_row[i])];
@@ -657,7 +739,8 @@ int co_resident_blocks(size_t lds) {
 }
 
 size_t smem_bytes(int m, int cw) {
-  return (size_t)cw * m * 8 + 2 * (size_t)((m + 63) / 64) * 8 + sizeof(Smem);
+  const size_t ms = (size_t)(m + BS - 1) / BS * BS;
+  return (size_t)smem_head_words() * 8 + (size_t)cw * ms * 8 + 2 * (ms / 64) * 8;
 }
 
 }  // namespace
