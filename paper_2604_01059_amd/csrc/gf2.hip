@@ -62,7 +62,9 @@ constexpr int MAX_SL = MAX_M / BS;  // row slices per thread
 constexpr int MAX_CW = 4;         // word columns per workgroup
 constexpr int MAX_STRIPS = 8192;  // strips with profile slots
 constexpr int PROF_SLOTS = 8;     // timestamps per strip (profiling only)
-constexpr int GROUP = 8;          // row slices whose multipliers are loaded together
+constexpr int GROUP = 4;          // row slices updated together (loads in flight together)
+constexpr int PRE = 2 * GROUP;    // row slices whose snapshot multipliers are loaded with the record
+constexpr int EARLY_MIN = 48;     // wave-0 candidates that allow reducing the next strip early
 
 struct PassRec {
   int32_t strip;
@@ -156,21 +158,30 @@ __global__ void rref_init(Ctl* ctl, int32_t* status, uint64_t* prof) {
   if (t == 0) *status = 0;
 }
 
+// One pass in LDS: its pivot rows, their strip bits and masks of original
+// pivots.  Two are kept: the pass being applied and the pass a wavefront
+// reduces meanwhile.
+struct Pass {
+  int32_t k, last;
+  uint32_t pivmask;
+  int32_t rows[SW];
+  int32_t bits[SW];
+  uint32_t L[SW];
+};
+
 struct Smem {
   uint64_t tab[MAX_CW][128];   // 8 nibble tables of reduced pivot words, per column
   uint64_t otab[MAX_CW][128];  // 8 nibble tables of original pivot words, per column
   uint64_t pp[MAX_CW][SW];
   uint64_t Q[MAX_CW][SW];      // reduced pivot word by strip bit position
+  Pass ps[2];
   int32_t wcnt[NWAVE];         // candidates per wave
-  uint32_t L[SW];
-  int32_t rows[SW];
-  int32_t bits[SW];
   int32_t cand[NCAND];
   int32_t prow[SW];            // sorted pivot list of a multi-pass strip
   int32_t pcol[SW];
-  uint32_t pivmask;
   uint32_t ackc[RING];         // acknowledgements known per ring slot (a lower bound)
-  int32_t k, last, total, flag, cnt, efirst, pad;
+  uint64_t emask[NWAVE];       // candidate lanes of the early slice, per wave
+  int32_t total, used, early, flag, cnt;
 };
 
 // 64-bit words of LDS before the columns (the Smem block, 16-byte aligned)
@@ -283,13 +294,11 @@ __device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t&
   if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, jb, P, k, pm);
 }
 
-// Wave 0 (all 64 lanes active): reduce the candidates (S.cand, min(S.total,
-// NCAND) of them), using bits [shift, shift + 32) of the LDS column `col`:
-// Gauss-Jordan over the strip bits in ascending order.  Fills S.k, rows,
-// bits, L, pivmask.
-__device__ void factor_candidates(const LDS uint64_t* col, int shift, LDS Smem& S) {
+// Wave 0 (all 64 lanes active): reduce the first nc candidates of S.cand,
+// using bits [shift, shift + 32) of the LDS column `col`: Gauss-Jordan over
+// the strip bits in ascending order.  Fills N (k, rows, bits, L, pivmask).
+__device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LDS Pass& N, LDS Smem& S) {
   const int lane = threadIdx.x & 63;
-  const int nc = S.total < NCAND ? S.total : NCAND;
   uint32_t w = lane < nc ? (uint32_t)(col[S.cand[lane]] >> shift) : 0;
   uint32_t L = 0, jb = 0, pm = 0;
   uint64_t P = 0;
@@ -297,33 +306,37 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, LDS Smem& 
   factor_steps<0>(w, L, jb, P, k, pm);
   if (jb) {
     const int j = (int)(jb & 0xff) - 1;
-    S.L[j] = L;
-    S.rows[j] = S.cand[lane];
-    S.bits[j] = (int)(jb >> 8);
+    N.L[j] = L;
+    N.rows[j] = S.cand[lane];
+    N.bits[j] = (int)(jb >> 8);
   }
   if (lane == 0) {
-    S.k = k;
-    S.pivmask = pm;
+    N.k = k;
+    N.pivmask = pm;
   }
 }
 
-// Reduced pivot words and nibble tables of `nc` columns for the pass in S;
-// also marks this pass's pivot rows in newpiv.  Three barriers: nibble
-// tables of the original pivot words (read straight from the columns), then
-// the reduced words P'_t (eight lookups by the nibbles of L_t) placed at
-// their strip bits, then the nibble tables of those.
-__device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* newpiv, LDS Smem& S) {
-  const int tid = threadIdx.x, k = S.k;
+// Tables of pass R for `nc` columns, and R's pivot rows: marks them in
+// newpiv (this pass) and pivflag (all passes), and writes their reduced
+// words P' into the columns.  Three barriers: nibble tables of the original
+// pivot words (read straight from the columns), then P'_t (eight lookups by
+// the nibbles of L_t) placed at their strip bits, then the nibble tables of
+// those, with P' stored into the pivot rows.  The row update that follows
+// leaves newpiv rows as they are.
+__device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* newpiv, LDS uint64_t* pivflag,
+                            const LDS Pass& R, LDS Smem& S) {
+  const int tid = threadIdx.x, k = R.k;
   if (tid < k) {
-    const int r = S.rows[tid];
+    const int r = R.rows[tid];
     __hip_atomic_fetch_or(&newpiv[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_or(&pivflag[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   for (int x = tid; x < nc * 128; x += BS) {
     const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
     const LDS uint64_t* c = cols[j];
     uint64_t o[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = c[4 * q + i < k ? S.rows[4 * q + i] : 0];
+    for (int i = 0; i < 4; ++i) o[i] = c[4 * q + i < k ? R.rows[4 * q + i] : 0];
     uint64_t v = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) v ^= (((sel >> i) & 1) && 4 * q + i < k) ? o[i] : 0ull;
@@ -334,12 +347,12 @@ __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* new
   for (int x = tid; x < nc * SW; x += BS) {
     const int j = x / SW, t = x % SW;
     if (t < k) {
-      const uint32_t Lm = S.L[t];
+      const uint32_t Lm = R.L[t];
       uint64_t v = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) v ^= S.otab[j][16 * q + ((Lm >> (4 * q)) & 15)];
       S.pp[j][t] = v;
-      S.Q[j][S.bits[t]] = v;
+      S.Q[j][R.bits[t]] = v;
     }
   }
   __syncthreads();
@@ -351,7 +364,19 @@ __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* new
       if ((sel >> i) & 1) v ^= S.Q[j][4 * q + i];
     S.tab[j][e] = v;
   }
+  for (int x = tid; x < nc * SW; x += BS) {
+    const int j = x / SW, t = x % SW;
+    if (t < k) cols[j][R.rows[t]] = S.pp[j][t];
+  }
   __syncthreads();
+}
+
+// Clear R's rows from newpiv once the update is done (after a barrier).
+__device__ __forceinline__ void clear_newpiv(LDS uint64_t* newpiv, const LDS Pass& R) {
+  if ((int)threadIdx.x < R.k) {
+    const int r = R.rows[threadIdx.x];
+    __hip_atomic_fetch_and(&newpiv[r >> 6], ~(1ull << (r & 63)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
 }
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
@@ -414,23 +439,22 @@ __device__ __forceinline__ uint32_t apply_cols(LDS uint64_t* const* cols, int nc
   return f;
 }
 
-// Apply the pass in S to `nc` LDS word columns.  Multipliers (the strip word
-// of every row before the pass) come from the global snapshot `snap`
-// (consumers) or from bits [shift, shift+32) of the LDS column `strip` (the
-// owner; that column may be one of `cols`: a group's multipliers are all read
-// before its rows are updated).  newpiv must hold this pass's pivot rows;
-// they are not updated here (multiplier 0 looks up table entry 0, which is
-// zero).  With fuse >= 0, the rows not yet pivots whose bits
-// [fshift, fshift+32) of column cols[fuse] are non-zero after the update are
-// returned as candidate flags (bit i = row tid + i*BS).  `pre` (optional)
-// holds the first GROUP multipliers, already loaded.  LDS work only: no
-// global stores.  On return pivot rows hold P' and pivflag includes them.
-__device__ uint32_t apply_record(LDS uint64_t* const* cols, int nc, const uint32_t* snap,
-                                 const LDS uint64_t* strip, int shift, int m, LDS uint64_t* pivflag,
-                                 LDS uint64_t* newpiv, int fuse, int fshift, const uint32_t* pre, LDS Smem& S) {
+// This thread's rows of `nc` LDS word columns updated by the pass whose
+// tables are in S (pivmask pm).  Multipliers (the strip word of every row
+// before the pass) come from the global snapshot `snap` (consumers) or from
+// bits [shift, shift+32) of the LDS column `strip` (the owner; that column
+// may be one of `cols`: a group's multipliers are all read before its rows
+// are updated).  Rows in newpiv keep their value (multiplier 0 looks up table
+// entry 0, which is zero).  With fuse >= 0, the rows not yet pivots whose
+// bits [fshift, fshift+32) of column cols[fuse] are non-zero after the update
+// are returned as candidate flags (bit i = row tid + i*BS).  `pre` (optional)
+// holds the first PRE multipliers, already loaded.  LDS work only; no
+// barrier.
+__device__ uint32_t apply_rows(LDS uint64_t* const* cols, int nc, const uint32_t* snap, const LDS uint64_t* strip,
+                               int shift, int m, const LDS uint64_t* pivflag, const LDS uint64_t* newpiv,
+                               uint32_t pm, int fuse, int fshift, const uint32_t* pre, LDS Smem& S) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nsl = (m + BS - 1) / BS;
-  const uint32_t pm = S.pivmask;
   uint32_t flags = 0;
   for (int i0 = 0; i0 < nsl; i0 += GROUP) {
     uint32_t mr[GROUP];
@@ -439,7 +463,8 @@ __device__ uint32_t apply_record(LDS uint64_t* const* cols, int nc, const uint32
     for (int q = 0; q < GROUP; ++q) {
       const int i = i0 + q, r = i * BS + tid;
       uint32_t x = 0;
-      if (i0 == 0 && pre) x = pre[q];
+      if (pre && i0 == 0) x = pre[q];
+      else if (pre && i0 == GROUP) x = pre[GROUP + q];
       else if (r < m) x = snap ? ld_dev(&snap[r]) : (uint32_t)(strip[r] >> shift);
       // the wave's 64 rows of slice i share one word of each flag array
       const uint64_t npw = i < nsl ? newpiv[i * NWAVE + wv] : ~0ull;
@@ -449,22 +474,212 @@ __device__ uint32_t apply_record(LDS uint64_t* const* cols, int nc, const uint32
     flags |= i0 + GROUP <= nsl ? apply_cols<true>(cols, nc, mr, done, i0, nsl, fuse, fshift, S)
                                : apply_cols<false>(cols, nc, mr, done, i0, nsl, fuse, fshift, S);
   }
-  __syncthreads();
-  const int k = S.k;
-  for (int x = tid; x < nc * SW; x += BS) {
-    const int j = x / SW, t = x % SW;
-    if (t < k) cols[j][S.rows[t]] = S.pp[j][t];
+  return flags;
+}
+
+// Candidate count of this wave from its threads' flags.
+__device__ __forceinline__ int wave_count(uint32_t flags, int nsl) {
+  int c = 0;
+  for (int i = 0; i < nsl; ++i) c += __popcll(__ballot((flags >> i) & 1));
+  return c;
+}
+
+// This wave's candidates (rows of its own threads), up to NCAND of them,
+// into S.cand; returns how many were placed.  Wavefront-local: no barrier.
+__device__ int wave_candidates(uint32_t flags, int nsl, LDS Smem& S) {
+  const int tid = threadIdx.x;
+  int base = 0;
+  for (int i = 0; i < nsl && base < NCAND; ++i) {
+    const bool f = (flags >> i) & 1;
+    const uint64_t b = __ballot(f);
+    const int idx = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
+    if (f && idx < NCAND) S.cand[idx] = i * BS + tid;
+    base += __popcll(b);
   }
-  if (tid < k) {
-    const int r = S.rows[tid];
-    __hip_atomic_fetch_or(&pivflag[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_and(&newpiv[r >> 6], ~(1ull << (r & 63)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return base < NCAND ? base : NCAND;
+}
+
+// Bits [shift, shift+32) of this thread's rows of LDS column `col` to `snap`.
+__device__ __forceinline__ void store_own_snapshot(const LDS uint64_t* col, int shift, int m, uint32_t* snap) {
+  const int nsl = (m + BS - 1) / BS;
+  for (int i = 0; i < nsl; ++i) {
+    const int r = i * BS + (int)threadIdx.x;
+    if (r < m) st_dev(&snap[r], (uint32_t)(col[r] >> shift));
+  }
+}
+
+// The update by pass R (tables already in S) of this workgroup's columns
+// when column cols[fuse] holds its next strip (bits [fshift, fshift+32)).
+// Every wave updates its own rows and writes their next-strip snapshot words
+// to snap_out.  Wave fw then takes the next strip's candidates among its own
+// rows and, if it has at least EARLY_MIN of them, reduces them into N while
+// the other waves are still updating (and loads the acknowledgements of ring
+// slot ack_slot meanwhile).  fw rotates with the strip, so that pivots are
+// drawn from every wave's rows alike.  Ends with a barrier.  Returns the
+// thread's candidate flags; S.wcnt holds every wave's count, S.early /
+// S.used whether wave fw reduced and how many candidates it used.
+__device__ uint32_t update_and_reduce(LDS uint64_t* const* cols, int nc, const uint32_t* snap,
+                                      const LDS uint64_t* strip, int shift, int m, LDS uint64_t* pivflag,
+                                      LDS uint64_t* newpiv, uint32_t pm, int fuse, int fshift, const uint32_t* pre,
+                                      uint32_t* snap_out, LDS Pass& N, int fw, const Args& a,
+                                      uint32_t ack_slot, LDS Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nsl = (m + BS - 1) / BS;
+  const uint32_t flags = apply_rows(cols, nc, snap, strip, shift, m, pivflag, newpiv, pm, fuse, fshift, pre, S);
+  store_own_snapshot(cols[fuse], fshift, m, snap_out);
+  const int cnt = wave_count(flags, nsl);
+  if (lane == 0) S.wcnt[wv] = cnt;
+  if (wv == fw) {
+    const bool early = cnt >= EARLY_MIN;
+    if (early) {
+      const uint32_t ackv = lane == 0 ? ld_dev(&a.ctl->ack[ack_slot]) : 0u;
+      const int used = wave_candidates(flags, nsl, S);
+      factor_candidates(cols[fuse], fshift, used, N, S);
+      if (lane == 0) {
+        S.used = used;
+        if (ackv > S.ackc[ack_slot]) S.ackc[ack_slot] = ackv;
+      }
+    }
+    if (lane == 0) S.early = early ? 1 : 0;
   }
   __syncthreads();
   return flags;
 }
 
-// Thread 0 waits until ring slot `slot` may be overwritten by record `idx`.
+// One row r of `nc` columns updated by the pass whose tables are in S
+// (multiplier mv before masking with pm); returns whether the row is a
+// candidate of the next strip (bits [fshift, fshift+32) of column cols[fuse]
+// non-zero, not a pivot).  r lies in a 64-row block that the whole wave
+// handles, so the flag words are uniform loads.
+__device__ __forceinline__ bool update_row(LDS uint64_t* const* cols, int nc, int r, uint32_t mv, uint32_t pm,
+                                           const LDS uint64_t* pivflag, const LDS uint64_t* newpiv, int fuse,
+                                           int fshift, LDS Smem& S) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t npw = newpiv[r >> 6];
+  const uint64_t done = pivflag[r >> 6] | npw;
+  const uint32_t mr = ((npw >> lane) & 1) ? 0u : (mv & pm);
+  bool f = false;
+  if (nc == 1) {
+    const uint64_t v = lookup8(S.tab[0], mr, cols[0][r]);
+    cols[0][r] = v;
+    f = ((uint32_t)(v >> fshift) != 0u) && !((done >> lane) & 1);
+  } else {
+    for (int j = 0; j < nc; ++j) {
+      const uint64_t v = lookup8(S.tab[j], mr, cols[j][r]);
+      cols[j][r] = v;
+      if (j == fuse) f = ((uint32_t)(v >> fshift) != 0u) && !((done >> lane) & 1);
+    }
+  }
+  return f;
+}
+
+// The early slice, the reducing wave and the extra slice a wave updates for
+// it, for the strip that follows strip t (every workgroup derives the same).
+__device__ __forceinline__ int early_slice(int t, int nsl) { return (t + 1) % nsl; }
+__device__ __forceinline__ int early_wave(int t) { return (t + 1) % NWAVE; }
+__device__ __forceinline__ int extra_slice(int wv, int fw, int e) {
+  const int kx = (wv - fw + NWAVE - 1) % NWAVE;
+  return kx < e ? kx : kx + 1;
+}
+
+// The fused update with the next strip's reduction split off, for at most
+// PRE row slices.  First every wave updates its row of slice e (the early
+// slice, rotating with the strip) and records which of them are candidates;
+// after a barrier wave fw takes up to NCAND of the slice's candidates and
+// reduces them into N, while the other seven waves update their remaining
+// slices and, one slice each, the rows of wave fw.  Every updated row's
+// next-strip word goes to snap_out.  Multipliers: pre[i] (consumers: the
+// thread's row of slice i) and prex (its extra row of wave fw), or the strip
+// bits of LDS column `strip` (the owner).  Ends with a barrier; S.wcnt holds
+// the candidate counts (each row counted once), S.early / S.used whether wave
+// fw reduced and how many candidates it used.
+__device__ void split_update_and_reduce(LDS uint64_t* const* cols, int nc, const LDS uint64_t* strip, int shift,
+                                        int m, LDS uint64_t* pivflag, LDS uint64_t* newpiv, uint32_t pm, int fuse,
+                                        int fshift, const uint32_t* pre, uint32_t prex, uint32_t* snap_out,
+                                        LDS Pass& N, int fw, int e, const Args& a, uint32_t ack_slot, LDS Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nsl = (m + BS - 1) / BS;
+  const LDS uint64_t* fc = cols[fuse];
+  // phase A: slice e
+  {
+    const int r = e * BS + tid;
+    uint32_t mv = 0;
+#pragma unroll
+    for (int i = 0; i < PRE; ++i)
+      if (i == e) mv = pre ? pre[i] : (r < m ? (uint32_t)(strip[r] >> shift) : 0u);
+    const bool f = r < m && update_row(cols, nc, r, mv, pm, pivflag, newpiv, fuse, fshift, S);
+    const uint64_t b = __ballot(f);
+    if (lane == 0) S.emask[wv] = b;
+    if (r < m) st_dev(&snap_out[r], (uint32_t)(fc[r] >> fshift));
+  }
+  __syncthreads();
+  int cnt = 0;
+  if (wv == fw) {
+    int base = 0;
+#pragma unroll
+    for (int v = 0; v < NWAVE; ++v) {
+      const uint64_t msk = S.emask[v];
+      const int idx = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0));
+      if (((msk >> lane) & 1) && idx < NCAND) S.cand[idx] = e * BS + v * 64 + lane;
+      base += __popcll(msk);
+    }
+    cnt = base;
+    const bool early = base >= EARLY_MIN;
+    if (early) {
+      const uint32_t ackv = lane == 0 ? ld_dev(&a.ctl->ack[ack_slot]) : 0u;
+      const int used = base < NCAND ? base : NCAND;
+      factor_candidates(fc, fshift, used, N, S);
+      if (lane == 0) {
+        S.used = used;
+        if (ackv > S.ackc[ack_slot]) S.ackc[ack_slot] = ackv;
+      }
+    }
+    if (lane == 0) S.early = early ? 1 : 0;
+  } else {
+    // own rows of the other slices
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int r = i * BS + tid;
+      if (i != e && i < nsl && r < m) {
+        const uint32_t mv = pre ? pre[i] : (uint32_t)(strip[r] >> shift);
+        cnt += __popcll(__ballot(update_row(cols, nc, r, mv, pm, pivflag, newpiv, fuse, fshift, S)));
+        st_dev(&snap_out[r], (uint32_t)(fc[r] >> fshift));
+      }
+    }
+    // one slice of wave fw's rows: the k-th slice other than e, k = this
+    // wave's rank among the waves other than fw
+    const int xs = extra_slice(wv, fw, e);
+    const int r = xs * BS + fw * 64 + lane;
+    if (xs < nsl && r < m) {
+      const uint32_t mv = pre ? prex : (uint32_t)(strip[r] >> shift);
+      cnt += __popcll(__ballot(update_row(cols, nc, r, mv, pm, pivflag, newpiv, fuse, fshift, S)));
+      st_dev(&snap_out[r], (uint32_t)(fc[r] >> fshift));
+    }
+  }
+  if (lane == 0) S.wcnt[wv] = cnt;
+  __syncthreads();
+}
+
+// Candidate flags (bit i = row tid + i*BS) of the strip at bits [shift,
+// shift+32) of LDS column `col`: non-zero and not a pivot.
+__device__ __forceinline__ uint32_t strip_flags(const LDS uint64_t* col, int shift, int m,
+                                                const LDS uint64_t* pivflag) {
+  const int nsl = (m + BS - 1) / BS;
+  uint32_t flags = 0;
+  for (int i = 0; i < nsl; ++i) {
+    const int r = i * BS + (int)threadIdx.x;
+    if (r < m && (uint32_t)(col[r] >> shift) != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
+  }
+  return flags;
+}
+
+__device__ __forceinline__ int candidates_total(const LDS Smem& S) {
+  int total = 0;
+#pragma unroll
+  for (int v = 0; v < NWAVE; ++v) total += S.wcnt[v];
+  return total;
+}
+
 // Acknowledgements are monotonic: a count read earlier (S.ackc, prefetched
 // off the critical path) that already suffices saves the device-scope load.
 __device__ bool wait_slot(uint32_t idx, int G, const Args& a, LDS Smem& S) {
@@ -512,7 +727,10 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   uint32_t seq = 0;       // next record index
   int rank = 0;
   bool ok = true;
-  bool prepared = false;  // candidates of my next strip in S, its snapshot pending
+  int cur = 0;            // S.ps[cur]: the pass being published or applied
+  bool prepared = false;  // candidates of my next strip in S.cand (all rows), S.total set
+  bool factored = false;  // my next strip already reduced into S.ps[cur] during an update
+  int early_total = 0, early_used = 0;
   // snapshot to be written by waves 1..7 during the next reduction
   const LDS uint64_t* pend_col = nullptr;
   int pend_shift = 0;
@@ -530,53 +748,65 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
       for (;;) {
         PassRec* rec = a.recs + seq % RING;
         uint32_t* snap = a.snaps + (size_t)(seq % RING) * m;
-        if (!prepared) {
-          if (!wait_slot(seq, G, a, S)) { ok = false; break; }
-          uint32_t flags = 0;
-          for (int i = 0; i < nsl; ++i) {
-            const int r = i * BS + tid;
-            if (r < m && (uint32_t)(col[r] >> shift) != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
+        int total, used;
+        // an early reduction that found no pivot while other candidates
+        // exist is redone as a full pass (the snapshot is already written)
+        if (factored && S.ps[cur].k == 0 && early_total > 0) factored = false;
+        if (factored) {
+          factored = false;
+          total = early_total;
+          used = early_used;
+          if (tid == 0) prof_mark(a, t, 1);
+        } else {
+          if (!prepared) {
+            if (!wait_slot(seq, G, a, S)) { ok = false; break; }
+            uint32_t flags = 0;
+            for (int i = 0; i < nsl; ++i) {
+              const int r = i * BS + tid;
+              if (r < m && (uint32_t)(col[r] >> shift) != 0 && !bit_of(pivflag, r)) flags |= 1u << i;
+            }
+            compact_candidates(flags, nsl, S);
+            pend_col = col;
+            pend_shift = shift;
+            pend_snap = snap;
           }
-          compact_candidates(flags, nsl, S);
-          pend_col = col;
-          pend_shift = shift;
-          pend_snap = snap;
+          prepared = false;
+          if (tid == 0) prof_mark(a, t, 1);
+          total = S.total;
+          used = total < NCAND ? total : NCAND;
+          if (tid < 64) {
+            // the next slot's acknowledgements, loaded while the reduction runs
+            const uint32_t nslot = (seq + 1) % RING;
+            const uint32_t ackv = tid == 0 ? ld_dev(&a.ctl->ack[nslot]) : 0u;
+            factor_candidates(col, shift, used, S.ps[cur], S);
+            if (tid == 0 && ackv > S.ackc[nslot]) S.ackc[nslot] = ackv;
+          } else if (pend_snap) {
+            store_snapshot(pend_col, pend_shift, m, pend_snap);
+          }
+          pend_snap = nullptr;
+          __syncthreads();
         }
-        prepared = false;
-        if (tid == 0) prof_mark(a, t, 1);
-        const int total = S.total;
-        if (tid < 64) {
-          // the next slot's acknowledgements, loaded while the reduction runs
-          const uint32_t nslot = (seq + 1) % RING;
-          const uint32_t ackv = tid == 0 ? ld_dev(&a.ctl->ack[nslot]) : 0u;
-          if (total > 0) factor_candidates(col, shift, S);
-          else if (tid == 0) { S.k = 0; S.pivmask = 0; }
-          if (tid == 0 && ackv > S.ackc[nslot]) S.ackc[nslot] = ackv;
-        } else if (pend_snap) {
-          store_snapshot(pend_col, pend_shift, m, pend_snap);
-        }
-        pend_snap = nullptr;
-        __syncthreads();
         if (tid == 0) prof_mark(a, t, 6);
-        const int k = S.k;
-        const int last = (total == 0 || k == SW || total <= NCAND) ? 1 : 0;
+        LDS Pass& Pc = S.ps[cur];
+        const int k = Pc.k;
+        const int last = (total == 0 || k == SW || total <= used) ? 1 : 0;
         if (tid < k) {
-          st_dev32(&rec->rows[tid], S.rows[tid]);
-          st_dev32(&rec->bits[tid], S.bits[tid]);
-          st_dev(&rec->L[tid], S.L[tid]);
-          st_dev32(&a.piv_row[rank + tid], S.rows[tid]);
-          st_dev32(&a.piv_col[rank + tid], SW * t + S.bits[tid]);
+          st_dev32(&rec->rows[tid], Pc.rows[tid]);
+          st_dev32(&rec->bits[tid], Pc.bits[tid]);
+          st_dev(&rec->L[tid], Pc.L[tid]);
+          st_dev32(&a.piv_row[rank + tid], Pc.rows[tid]);
+          st_dev32(&a.piv_col[rank + tid], SW * t + Pc.bits[tid]);
         }
         if (tid == 0) {
           st_dev32(&rec->strip, t);
           st_dev32(&rec->k, k);
           st_dev32(&rec->last, last);
-          st_dev(&rec->pivmask, S.pivmask);
+          st_dev(&rec->pivmask, Pc.pivmask);
         }
         if (last && multi && tid == 64) {
           // multi-pass strip (rare): sort its pivot list by column.  A strip
           // holds at most 32 pivots; earlier passes' entries are read back,
-          // this pass's come from the factor output.
+          // this pass's come from the reduction.
           int cnt = 0;
           for (int i = rank0; i < rank; ++i) {
             S.prow[cnt] = ld_dev32(&a.piv_row[i]);
@@ -584,8 +814,8 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
             ++cnt;
           }
           for (int j = 0; j < k; ++j) {
-            S.prow[cnt] = S.rows[j];
-            S.pcol[cnt] = SW * t + S.bits[j];
+            S.prow[cnt] = Pc.rows[j];
+            S.pcol[cnt] = SW * t + Pc.bits[j];
             ++cnt;
           }
           for (int i = 1; i < cnt; ++i) {
@@ -617,24 +847,41 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         if (tid == 0) prof_mark(a, t, 2);
         ++seq;
         if (k > 0) {
-          // the high half of this word column is my next strip: write its
-          // snapshot and candidates while applying this pass
+          // the high half of this word column is my next strip: reduce it
+          // during this update
           const bool fused = last && (t & 1) == 0 && t + 1 < a.nstrips;
           if (fused && !wait_slot(seq, G, a, S)) { ok = false; break; }
           LDS uint64_t* list[MAX_CW];
           int nc = 0;
           for (int j = js; j < nown; ++j) list[nc++] = cols + (size_t)j * ms;
-          make_tables(list, nc, newpiv, S);
-          const uint32_t flags = apply_record(list, nc, nullptr, col, shift, m, pivflag, newpiv,
-                                              fused ? 0 : -1, SW, nullptr, S);
-          rank += k;
+          make_tables(list, nc, newpiv, pivflag, Pc, S);
           if (fused) {
-            compact_candidates(flags, nsl, S);
-            pend_col = col;
-            pend_shift = SW;
-            pend_snap = a.snaps + (size_t)(seq % RING) * m;
-            prepared = true;
+            uint32_t* snap_out = a.snaps + (size_t)(seq % RING) * m;
+            uint32_t flags = 0;
+            if (nsl <= PRE)
+              split_update_and_reduce(list, nc, col, shift, m, pivflag, newpiv, Pc.pivmask, 0, SW, nullptr, 0u,
+                                      snap_out, S.ps[cur ^ 1], early_wave(t), early_slice(t, nsl), a,
+                                      (seq + 1) % RING, S);
+            else
+              flags = update_and_reduce(list, nc, nullptr, col, shift, m, pivflag, newpiv, Pc.pivmask, 0, SW,
+                                        nullptr, snap_out, S.ps[cur ^ 1], early_wave(t), a, (seq + 1) % RING, S);
+            clear_newpiv(newpiv, Pc);
+            early_total = candidates_total(S);
+            if (S.early) {
+              factored = true;
+              early_used = S.used;
+              cur ^= 1;
+            } else {
+              if (nsl <= PRE) flags = strip_flags(col, SW, m, pivflag);
+              compact_candidates(flags, nsl, S);
+              prepared = true;
+            }
+          } else {
+            apply_rows(list, nc, nullptr, col, shift, m, pivflag, newpiv, Pc.pivmask, -1, SW, nullptr, S);
+            __syncthreads();
+            clear_newpiv(newpiv, Pc);
           }
+          rank += k;
         }
         if (tid == 0) prof_mark(a, t, 3);
         if (last) break;
@@ -652,29 +899,37 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         if (!S.flag) { ok = false; break; }
         const PassRec* rec = a.recs + slot;
         const uint32_t* snap = a.snaps + (size_t)slot * m;
+        LDS Pass& Pc = S.ps[cur];
         // the record and the first multipliers are loaded together
-        uint32_t pre[GROUP];
+        uint32_t pre[PRE];
 #pragma unroll
-        for (int q = 0; q < GROUP; ++q) {
+        for (int q = 0; q < PRE; ++q) {
           const int r = q * BS + tid;
           pre[q] = r < m ? ld_dev(&snap[r]) : 0;
         }
+        // the row of the reducing wave this thread updates in a split update
+        uint32_t prex = 0;
+        if (own_next && nsl <= PRE) {
+          const int fw = early_wave(t), xs = extra_slice(tid >> 6, fw, early_slice(t, nsl));
+          const int r = xs * BS + fw * 64 + (tid & 63);
+          if ((tid >> 6) != fw && xs < nsl && r < m) prex = ld_dev(&snap[r]);
+        }
         if (tid == 0) {
-          S.k = ld_dev32(&rec->k);
-          S.last = ld_dev32(&rec->last);
-          S.pivmask = ld_dev(&rec->pivmask);
+          Pc.k = ld_dev32(&rec->k);
+          Pc.last = ld_dev32(&rec->last);
+          Pc.pivmask = ld_dev(&rec->pivmask);
           if (own_next) {
             const uint32_t nslot = (seq + 1) % RING, v = ld_dev(&a.ctl->ack[nslot]);
             if (v > S.ackc[nslot]) S.ackc[nslot] = v;
           }
         }
         if (tid < SW) {
-          S.rows[tid] = ld_dev32(&rec->rows[tid]);
-          S.bits[tid] = ld_dev32(&rec->bits[tid]);
-          S.L[tid] = ld_dev(&rec->L[tid]);
+          Pc.rows[tid] = ld_dev32(&rec->rows[tid]);
+          Pc.bits[tid] = ld_dev32(&rec->bits[tid]);
+          Pc.L[tid] = ld_dev(&rec->L[tid]);
         }
         __syncthreads();
-        const int k = S.k, last = S.last;
+        const int k = Pc.k, last = Pc.last;
         const bool fused = own_next && last && k > 0;
         if (tid == 0 && own_next && last) prof_mark(a, t, 4);
         if (fused && !wait_slot(seq + 1, G, a, S)) { ok = false; break; }
@@ -688,15 +943,32 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
             list[nc++] = cols + (size_t)j * ms;
           }
           if (nc > 0) {
-            make_tables(list, nc, newpiv, S);
-            const uint32_t flags = apply_record(list, nc, snap, nullptr, 0, m, pivflag, newpiv, fuse, 0,
-                                                pre, S);
+            make_tables(list, nc, newpiv, pivflag, Pc, S);
             if (fused) {
-              compact_candidates(flags, nsl, S);
-              pend_col = list[fuse];
-              pend_shift = 0;
-              pend_snap = a.snaps + (size_t)((seq + 1) % RING) * m;
-              prepared = true;
+              uint32_t* snap_out = a.snaps + (size_t)((seq + 1) % RING) * m;
+              uint32_t flags = 0;
+              if (nsl <= PRE)
+                split_update_and_reduce(list, nc, nullptr, 0, m, pivflag, newpiv, Pc.pivmask, fuse, 0, pre, prex,
+                                        snap_out, S.ps[cur ^ 1], early_wave(t), early_slice(t, nsl), a,
+                                        (seq + 2) % RING, S);
+              else
+                flags = update_and_reduce(list, nc, snap, nullptr, 0, m, pivflag, newpiv, Pc.pivmask, fuse, 0, pre,
+                                          snap_out, S.ps[cur ^ 1], early_wave(t), a, (seq + 2) % RING, S);
+              clear_newpiv(newpiv, Pc);
+              early_total = candidates_total(S);
+              if (S.early) {
+                factored = true;
+                early_used = S.used;
+                cur ^= 1;
+              } else {
+                if (nsl <= PRE) flags = strip_flags(list[fuse], 0, m, pivflag);
+                compact_candidates(flags, nsl, S);
+                prepared = true;
+              }
+            } else {
+              apply_rows(list, nc, snap, nullptr, 0, m, pivflag, newpiv, Pc.pivmask, -1, 0, pre, S);
+              __syncthreads();
+              clear_newpiv(newpiv, Pc);
             }
           }
         }
