@@ -172,8 +172,6 @@ struct Pass {
 struct Smem {
   uint64_t tab[MAX_CW][128];   // 8 nibble tables of reduced pivot words, per column
   uint64_t otab[MAX_CW][128];  // 8 nibble tables of original pivot words, per column
-  uint64_t pp[MAX_CW][SW];
-  uint64_t Q[MAX_CW][SW];      // reduced pivot word by strip bit position
   Pass ps[2];
   int32_t wcnt[NWAVE];         // candidates per wave
   int32_t cand[NCAND];
@@ -181,6 +179,7 @@ struct Smem {
   int32_t pcol[SW];
   uint32_t ackc[RING];         // acknowledgements known per ring slot (a lower bound)
   uint64_t emask[NWAVE];       // candidate lanes of the early slice, per wave
+  int32_t tinv[SW];            // pivot index of each strip bit of the pass being applied
   int32_t total, used, early, flag, cnt;
 };
 
@@ -318,11 +317,12 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LD
 
 // Tables of pass R for `nc` columns, and R's pivot rows: marks them in
 // newpiv (this pass) and pivflag (all passes), and writes their reduced
-// words P' into the columns.  Three barriers: nibble tables of the original
-// pivot words (read straight from the columns), then P'_t (eight lookups by
-// the nibbles of L_t) placed at their strip bits, then the nibble tables of
-// those, with P' stored into the pivot rows.  The row update that follows
-// leaves newpiv rows as they are.
+// words P' into the columns.  Two barriers: first the nibble tables of the
+// original pivot words (read straight from the columns) and the pivot index
+// of each strip bit; then the nibble tables of the reduced words, each entry
+// the XOR of up to four P'_t, each P'_t eight lookups by the nibbles of L_t,
+// with P' stored into the pivot rows.  The row update that follows leaves
+// newpiv rows as they are.
 __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* newpiv, LDS uint64_t* pivflag,
                             const LDS Pass& R, LDS Smem& S) {
   const int tid = threadIdx.x, k = R.k;
@@ -330,6 +330,7 @@ __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* new
     const int r = R.rows[tid];
     __hip_atomic_fetch_or(&newpiv[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_or(&pivflag[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    S.tinv[R.bits[tid]] = tid;  // read only for strip bits in the pivot mask
   }
   for (int x = tid; x < nc * 128; x += BS) {
     const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
@@ -342,31 +343,34 @@ __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* new
     for (int i = 0; i < 4; ++i) v ^= (((sel >> i) & 1) && 4 * q + i < k) ? o[i] : 0ull;
     S.otab[j][e] = v;
   }
-  for (int x = tid; x < nc * SW; x += BS) S.Q[x / SW][x % SW] = 0;
   __syncthreads();
-  for (int x = tid; x < nc * SW; x += BS) {
-    const int j = x / SW, t = x % SW;
-    if (t < k) {
-      const uint32_t Lm = R.L[t];
+  const uint32_t pm = R.pivmask;
+  for (int x = tid; x < nc * (128 + SW); x += BS) {
+    if (x < nc * 128) {
+      const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
+      const LDS uint64_t* ot = S.otab[j];
       uint64_t v = 0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v ^= S.otab[j][16 * q + ((Lm >> (4 * q)) & 15)];
-      S.pp[j][t] = v;
-      S.Q[j][R.bits[t]] = v;
-    }
-  }
-  __syncthreads();
-  for (int x = tid; x < nc * 128; x += BS) {
-    const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
-    uint64_t v = 0;
+      for (int i = 0; i < 4; ++i) {
+        const int b = 4 * q + i;
+        if (((sel >> i) & 1) && ((pm >> b) & 1)) {
+          const uint32_t Lm = R.L[S.tinv[b]];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if ((sel >> i) & 1) v ^= S.Q[j][4 * q + i];
-    S.tab[j][e] = v;
-  }
-  for (int x = tid; x < nc * SW; x += BS) {
-    const int j = x / SW, t = x % SW;
-    if (t < k) cols[j][R.rows[t]] = S.pp[j][t];
+          for (int qq = 0; qq < 8; ++qq) v ^= ot[16 * qq + ((Lm >> (4 * qq)) & 15)];
+        }
+      }
+      S.tab[j][e] = v;
+    } else {
+      const int y = x - nc * 128, j = y / SW, t = y % SW;
+      if (t < k) {
+        const LDS uint64_t* ot = S.otab[j];
+        const uint32_t Lm = R.L[t];
+        uint64_t v = 0;
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) v ^= ot[16 * qq + ((Lm >> (4 * qq)) & 15)];
+        cols[j][R.rows[t]] = v;
+      }
+    }
   }
   __syncthreads();
 }
