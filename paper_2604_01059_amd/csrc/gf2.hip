@@ -949,6 +949,10 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           if (nc > 0) {
             make_tables(list, nc, newpiv, pivflag, Pc, S);
             if (fused) {
+              // the multipliers loaded with the record have landed by now;
+              // waiting here keeps the loop below from waiting on them after
+              // its snapshot stores (vmcnt counts both in issue order)
+              wait_stores();
               uint32_t* snap_out = a.snaps + (size_t)((seq + 1) % RING) * m;
               uint32_t flags = 0;
               if (nsl <= PRE)
