@@ -206,20 +206,30 @@ zx_status zx_batch_autotune(zx_batch* b, int32_t extract, int32_t reps, int32_t*
 void zx_batch_destroy(zx_batch* b);
 
 /* ======================================================================
- * GF(2) reduced row echelon form
+ * GF(2) reduced row echelon form (Gauss-Jordan elimination over F2, as the
+ * paper uses to keep a linearly independent basis of a binary matrix:
+ * detectors/observables section, around equation detector_sampling)
  *
  * R = RREF(A) for an m x n_cols bit matrix (ld words per row; bits >= n_cols
  * are ignored and written as zero).  A and R may be the same buffer (in
  * place); otherwise they must not overlap.  rank_dev: one device int32.
  * pivot_cols_dev: m device int32, pivot column of output row i, -1 for rows
- * beyond the rank.  One cooperative persistent launch: every word column
- * lives in one workgroup's LDS, so m * 8 bytes per column must fit
+ * beyond the rank.
+ * T (optional, NULL = none): m x ld_t words (ld_t >= ceil(m/64)), written
+ * with an invertible transform such that T * A = R over F2: its first rank
+ * rows give the reduced pivot rows as combinations of A's rows, the others
+ * (rows of A that are no pivot, ascending) span the left null space.  T is
+ * unique when A has full row rank; it must not overlap A or R.
+ * One cooperative persistent launch: every word column (of A, and of T when
+ * requested) lives in one workgroup's LDS, so m * 8 bytes per column must fit
  * (m <= 16384) and the grid must be co-resident; otherwise ZX_ECAPACITY.
+ * Device buffers are the caller's; the call only reads A and writes R, T,
+ * rank, pivots and the workspace.  Asynchronous on s.
  * ==================================================================== */
 size_t zx_gf2_workspace_bytes(int32_t m, int32_t n_cols);
 zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
                            int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
-                           void* ws, size_t ws_bytes, hipStream_t s);
+                           uint64_t* T, int64_t ld_t, void* ws, size_t ws_bytes, hipStream_t s);
 /* Sticky status of the last elimination that used this workspace (syncs). */
 zx_status zx_gf2_status(const void* ws, hipStream_t s);
 /* Per-strip timestamps (100 MHz real-time counter) of the last elimination in

@@ -103,8 +103,9 @@ WsLayout ws_layout(int m) {
 struct Args {
   const uint64_t* A;
   uint64_t* R;
-  int32_t m, n_cols, nw, cw, nstrips;
-  int64_t ld;
+  uint64_t* T;          // optional transform (NULL = none), m x ldt words
+  int32_t m, n_cols, nw, nw_a, cw, nstrips;  // nw: word columns held (A's nw_a, then T's)
+  int64_t ld, ldt;
   int32_t* rank_dev;
   int32_t* piv_dev;
   int32_t* status;
@@ -717,9 +718,17 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
 
   for (int j = 0; j < nown; ++j) {
     const int c = g + j * G;
-    const int tail = a.n_cols - 64 * c;
-    const uint64_t cm = tail >= 64 ? ~0ull : ((1ull << tail) - 1);
-    for (int r = tid; r < ms; r += BS) cols[(size_t)j * ms + r] = r < m ? a.A[(size_t)r * a.ld + c] & cm : 0;
+    if (c < a.nw_a) {
+      const int tail = a.n_cols - 64 * c;
+      const uint64_t cm = tail >= 64 ? ~0ull : ((1ull << tail) - 1);
+      for (int r = tid; r < ms; r += BS) cols[(size_t)j * ms + r] = r < m ? a.A[(size_t)r * a.ld + c] & cm : 0;
+    } else {
+      // the transform's columns start as the identity; every pass updates
+      // them like A's columns, no strip of theirs is ever reduced
+      const int tc = c - a.nw_a;
+      for (int r = tid; r < ms; r += BS)
+        cols[(size_t)j * ms + r] = (r < m && (r >> 6) == tc) ? (1ull << (r & 63)) : 0ull;
+    }
   }
   for (int i = tid; i < pw; i += BS) {
     pivflag[i] = 0;
@@ -990,13 +999,40 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   }
   if (!ok) return;
   // ---------------- write the result ----------------
+  // T: rows in pivot order, then the rows that are no pivot, ascending (their
+  // transform rows span the left null space); piv_base[w] = non-pivot rows in
+  // flag words before w
+  const bool has_t = a.T && nown > 0 && g + (nown - 1) * G >= a.nw_a;
+  if (has_t) {
+    if (tid == 0) {
+      int acc = 0;
+      for (int w = 0; w < pw; ++w) {
+        newpiv[w] = (uint64_t)acc;  // free now: reused for the prefix counts
+        const int lo = 64 * w;
+        const uint64_t valid = lo + 64 <= m ? ~0ull : (lo >= m ? 0ull : ((1ull << (m - lo)) - 1));
+        acc += __popcll(~pivflag[w] & valid);
+      }
+    }
+    __syncthreads();
+  }
   for (int j = 0; j < nown; ++j) {
     const int c = g + j * G;
     const LDS uint64_t* col = cols + (size_t)j * ms;
-    for (int i = tid; i < m; i += BS) {
-      uint64_t v = 0;
-      if (i < rank) v = col[ld_dev32(&a.piv_row[i])];
-      a.R[(size_t)i * a.ld + c] = v;
+    if (c < a.nw_a) {
+      for (int i = tid; i < m; i += BS) {
+        uint64_t v = 0;
+        if (i < rank) v = col[ld_dev32(&a.piv_row[i])];
+        a.R[(size_t)i * a.ld + c] = v;
+      }
+    } else {
+      const int tc = c - a.nw_a;
+      for (int i = tid; i < rank; i += BS) a.T[(size_t)i * a.ldt + tc] = col[ld_dev32(&a.piv_row[i])];
+      for (int r = tid; r < m; r += BS) {
+        const uint64_t pf = pivflag[r >> 6];
+        if ((pf >> (r & 63)) & 1) continue;
+        const int idx = rank + (int)newpiv[r >> 6] + __popcll(~pf & ((1ull << (r & 63)) - 1));
+        a.T[(size_t)idx * a.ldt + tc] = col[r];
+      }
     }
   }
   if (g == 0) {
@@ -1053,12 +1089,24 @@ extern "C" zx_status zx_gf2_profile_read(const void* ws, int32_t m, int64_t* tic
 
 extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
                                       int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
-                                      void* ws, size_t ws_bytes, hipStream_t s) {
+                                      uint64_t* T, int64_t ld_t, void* ws, size_t ws_bytes, hipStream_t s) {
   zx_clear_error();
   ZX_CHECK_ARG(A && R && rank_dev && pivot_cols_dev && ws, "null argument");
   ZX_CHECK_ARG(m > 0 && n_cols > 0, "empty matrix: m=%d n_cols=%d", m, n_cols);
-  const int nw = (n_cols + 63) / 64;
-  ZX_CHECK_ARG(ld_words >= nw, "ld_words %lld < %d", (long long)ld_words, nw);
+  const int nw_a = (n_cols + 63) / 64;
+  ZX_CHECK_ARG(ld_words >= nw_a, "ld_words %lld < %d", (long long)ld_words, nw_a);
+  const int mw = (m + 63) / 64;
+  if (T) {
+    ZX_CHECK_ARG(ld_t >= mw, "ld_t %lld < %d", (long long)ld_t, mw);
+    const char* t0 = (const char*)T;
+    const char* t1 = t0 + (size_t)m * ld_t * 8;
+    const char* a0 = (const char*)A;
+    const char* a1 = a0 + (size_t)m * ld_words * 8;
+    const char* r0 = (const char*)R;
+    const char* r1 = r0 + (size_t)m * ld_words * 8;
+    ZX_CHECK_ARG((t1 <= a0 || a1 <= t0) && (t1 <= r0 || r1 <= t0), "T overlaps A or R");
+  }
+  const int nw = nw_a + (T ? mw : 0);
   ZX_CHECK_ARG(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
   if (A != R) {
     const char* a0 = (const char*)A;
@@ -1100,9 +1148,12 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
   Args a;
   a.A = A;
   a.R = R;
+  a.T = T;
+  a.ldt = T ? ld_t : 0;
   a.m = m;
   a.n_cols = n_cols;
   a.nw = nw;
+  a.nw_a = nw_a;
   a.cw = cw;
   a.nstrips = (n_cols + SW - 1) / SW;
   a.ld = ld_words;

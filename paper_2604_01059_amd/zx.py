@@ -108,7 +108,7 @@ def load():
         "zx_batch_autotune": ([P, i32, i32, C.POINTER(i32), C.POINTER(C.c_float), P], i32),
         "zx_batch_destroy": ([P], None),
         "zx_gf2_workspace_bytes": ([i32, i32], sz),
-        "zx_gf2_eliminate": ([P, P, i32, i32, i64, P, P, P, sz, P], i32),
+        "zx_gf2_eliminate": ([P, P, i32, i32, i64, P, P, P, i64, P, sz, P], i32),
         "zx_gf2_status": ([P, P], i32),
         "zx_gf2_profile_read": ([P, i32, P, i32, P], i32),
         "zx_pauli_commute": ([P, P, i64, i32, i64, P, i64, u32, P], i32),
@@ -472,9 +472,10 @@ def gf2_workspace_bytes(m, n_cols):
     return load().zx_gf2_workspace_bytes(m, n_cols)
 
 
-def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, stream=None):
+def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, stream=None, T=None):
     """RREF of A (torch int64/uint64-view device tensor, m x ld words).
-    Returns (R, rank tensor, pivots tensor, ws)."""
+    T: optional device tensor (m x >= ceil(m/64) words) that receives the
+    transform with T A = R.  Returns (R, rank tensor, pivots tensor, ws)."""
     import torch
     m, ld = A.shape
     n_cols = 64 * ld if n_cols is None else n_cols
@@ -486,8 +487,10 @@ def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, strea
         pivots = torch.zeros(m, dtype=torch.int32, device=A.device)
     if ws is None:
         ws = torch.empty(gf2_workspace_bytes(m, n_cols), dtype=torch.uint8, device=A.device)
+    ldt = T.shape[1] if T is not None else 0
     _check(load().zx_gf2_eliminate(_ptr(A), _ptr(R), m, n_cols, ld, _ptr(rank), _ptr(pivots),
-                                   _ptr(ws), ws.numel(), _stream(stream)))
+                                   _ptr(T) if T is not None else None, ldt, _ptr(ws), ws.numel(),
+                                   _stream(stream)))
     return R, rank, pivots, ws
 
 

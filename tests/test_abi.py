@@ -44,10 +44,15 @@ def test_host_argument_errors(lib):
     P = C.c_void_p
     dummy = P(256)
     # null pointers and bad shapes are caught before any device work
-    assert lib.zx_gf2_eliminate(None, None, 4, 64, 1, None, None, None, 0, None) == zx.ZX_EINVAL
+    assert lib.zx_gf2_eliminate(None, None, 4, 64, 1, None, None, None, 0, None, 0, None) == zx.ZX_EINVAL
     assert b"null" in lib.zx_last_error()
-    assert lib.zx_gf2_eliminate(dummy, dummy, 0, 64, 1, dummy, dummy, dummy, 1 << 20, None) == zx.ZX_EINVAL
-    assert lib.zx_gf2_eliminate(dummy, dummy, 4, 640, 2, dummy, dummy, dummy, 1 << 20, None) == zx.ZX_EINVAL
+    assert lib.zx_gf2_eliminate(dummy, dummy, 0, 64, 1, dummy, dummy, None, 0, dummy, 1 << 20, None) == zx.ZX_EINVAL
+    assert lib.zx_gf2_eliminate(dummy, dummy, 4, 640, 2, dummy, dummy, None, 0, dummy, 1 << 20, None) == zx.ZX_EINVAL
+    # the transform needs ceil(m/64) words per row and may not overlap A
+    assert lib.zx_gf2_eliminate(dummy, dummy, 100, 64, 1, dummy, dummy, P(1 << 20), 1, dummy, 1 << 20,
+                                None) == zx.ZX_EINVAL
+    assert lib.zx_gf2_eliminate(P(4096), P(4096), 4, 64, 1, dummy, dummy, P(4096), 1, dummy, 1 << 20,
+                                None) == zx.ZX_EINVAL
     assert lib.zx_pauli_commute(None, None, 10, 10, 1, None, 1, 0, None) == zx.ZX_EINVAL
     assert lib.zx_local_comp(None, 0, 0, None) == zx.ZX_EINVAL
     assert lib.zx_batch_simplify(None, None, None) == zx.ZX_EINVAL

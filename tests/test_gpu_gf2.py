@@ -112,3 +112,75 @@ def test_capacity_error(zx):
     with pytest.raises(zx.ZxError) as e:
         zx.gf2_eliminate(dA, n_cols=64)
     assert e.value.code == zx.ZX_ECAPACITY
+
+
+# ---------------------------------------------------------------- transform --
+
+def gf2_matmul(Tw, Aw, m, n_cols):
+    """T A over F2 (packed rows in, packed rows out), by unpacked integer products."""
+    from workloads.generators import unpack_rows
+    Tb = unpack_rows(Tw, m).astype(np.int64)
+    Ab = unpack_rows(Aw, n_cols).astype(np.int64)
+    return pack_rows(((Tb @ Ab) & 1).astype(np.uint8))
+
+
+def run_gpu_t(zx, A, n_cols, ldt_extra=0):
+    import torch
+    m = A.shape[0]
+    mw = (m + 63) // 64
+    dA = zx.to_device_words(A)
+    dT = torch.full((m, mw + ldt_extra), -1, dtype=torch.int64, device="cuda")
+    R, rank, piv, ws = zx.gf2_eliminate(dA, n_cols=n_cols, T=dT)
+    torch.cuda.synchronize()
+    assert zx.gf2_status(ws) == 0
+    T = zx.to_host_words(dT)
+    if ldt_extra:
+        assert np.all(T[:, mw:] == np.uint64(0xFFFFFFFFFFFFFFFF))  # padding words untouched
+    return zx.to_host_words(R), int(rank.item()), piv.cpu().numpy(), T[:, :mw]
+
+
+@pytest.mark.parametrize("m,n", [(1, 64), (64, 64), (100, 300), (130, 700), (700, 2000), (1000, 700)])
+def test_transform_random(zx, m, n):
+    """R and pivots as without T; T A = R; T equals the oracle's transform when
+    A has full row rank (the transform is unique then), and is invertible."""
+    A = bernoulli_matrix(2000 + m, m, n)
+    print("gf2 transform", m, n, flush=True)
+    R, rank, piv, T = run_gpu_t(zx, A, n, ldt_extra=1 if m == 100 else 0)
+    Ro, pivo, ranko, _, To = oracle.gf2_rref(A, n, want_T=True)
+    nw = (n + 63) // 64
+    assert rank == ranko and np.array_equal(piv, pivo)
+    assert np.array_equal(R[:, :nw], Ro[:, :nw])
+    assert np.array_equal(gf2_matmul(T, A, m, n)[:, :nw], Ro[:, :nw])
+    if ranko == m:
+        assert np.array_equal(T, To)
+    assert oracle.gf2_rref(T, m)[2] == m
+
+
+def test_transform_rank_deficient(zx):
+    """Low rank: T A = R, T invertible, and the rows of T beyond the rank lie in
+    the left null space (the transform is not unique here)."""
+    rng = np.random.default_rng(23)
+    for r, m, n in ((5, 300, 500), (70, 400, 900), (200, 1000, 1500)):
+        L = rng.integers(0, 2, (m, r)).astype(np.uint8)
+        Rm = rng.integers(0, 2, (r, n)).astype(np.uint8)
+        A = pack_rows((L.astype(np.int64) @ Rm.astype(np.int64) % 2).astype(np.uint8))
+        print("gf2 transform low rank", r, m, n, flush=True)
+        R, rank, piv, T = run_gpu_t(zx, A, n)
+        Ro, pivo, ranko, _ = oracle.gf2_rref(A, n)
+        nw = (n + 63) // 64
+        assert rank == ranko and np.array_equal(R[:, :nw], Ro[:, :nw])
+        TA = gf2_matmul(T, A, m, n)[:, :nw]
+        assert np.array_equal(TA, Ro[:, :nw])
+        assert not TA[rank:].any()
+        assert oracle.gf2_rref(T, m)[2] == m
+
+
+def test_transform_full_size(zx):
+    """The benchmark matrix with its transform: unique (full row rank), so T
+    equals the oracle's bit for bit."""
+    A = bernoulli_matrix(21, 4096, 16384)
+    R, rank, piv, T = run_gpu_t(zx, A, 16384)
+    Ro, pivo, ranko, _, To = oracle.gf2_rref(A, 16384, want_T=True)
+    assert rank == ranko == 4096
+    assert np.array_equal(R, Ro) and np.array_equal(piv, pivo)
+    assert np.array_equal(T, To)
