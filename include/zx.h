@@ -301,6 +301,20 @@ zx_status zx_mlp_backward(const zx_mlp* w, const uint16_t* x, const float* dscor
 zx_status zx_mlp_adam(const zx_mlp* w, const float* grad, float* m, float* v, float lr,
                       float beta1, float beta2, float eps, int32_t step, hipStream_t s);
 
+/* The learned proposal's view of one diagram state (its CURRENT section):
+ * the candidates of the next local-complementation round, ascending (none
+ * once the state is past its LC phase), and for each the ZX_MLP_IN bf16
+ * features the learned simplification scores (listed under zx_rollout).
+ * Writes the count to *n_cand (one device int32) and the first
+ * min(count, max_cand) candidates and feature rows to cand (int32) and feats
+ * (row-major, ZX_MLP_IN per row), all device memory of the caller.
+ * ZX_ECAPACITY when the diagram does not fit the kernel's LDS (about 1000
+ * spiders).  Asynchronous on s; the arena is only read.  The paper leaves the
+ * proposal's inputs open: these are the features of this library's
+ * network. */
+zx_status zx_policy_features(const zx_graph* g, int32_t* cand, uint16_t* feats, int32_t max_cand,
+                             int32_t* n_cand, hipStream_t s);
+
 /* Rollouts for training labels.  Item i = (state i / per_state, slot
  * k = i % per_state) on states[i / per_state] (CURRENT diagrams, read only;
  * at most 1024 spiders).  The kernel lists the state's local-complementation

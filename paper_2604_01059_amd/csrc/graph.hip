@@ -1161,6 +1161,55 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
   }
 }
 
+// ------------------------------------------------------------ features --
+struct FeatArgs {
+  uint8_t* arena;
+  int32_t* cand;
+  uint16_t* feats;
+  int32_t max_cand;
+  int32_t* n_cand;
+};
+
+// One workgroup: the candidates of the next local-complementation round of
+// one diagram's CURRENT state (ascending) and the learned proposal's
+// features of each (one wavefront per candidate), as the learned
+// simplification computes them before scoring.  The host checked that the
+// diagram fits the LDS (roll_lds_bytes).
+template <int BS>
+__global__ __launch_bounds__(BS) void features_kernel(FeatArgs a) {
+  extern __shared__ __align__(16) uint8_t smem_dyn[];
+  __shared__ Shared sh;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const ZxHeader* h = (const ZxHeader*)a.arena;
+  const int n = uni(h->n), W = uni(h->W);
+  Ctx<true> c;
+  setup_ctx<BS, true>(c, a.arena, smem_dyn);
+  c.trace = nullptr;
+  Pol pol;
+  pol.wbf = nullptr;
+  pol.param = nullptr;
+  pol.cap = pol_cap(n);
+  pol.key = nullptr;
+  uint8_t* pa = align16(smem_dyn + lds_adj_bytes(n, W) + aux_bytes(n, W));
+  pol.list = (LDSP uint32_t*)pa;
+  pol.fbuf = (LDSP uint16_t*)(pa + (int64_t)pol.cap * 4);  // one row of features per wavefront
+  load_state<BS, true>(c, sh, false);
+  int C = 0;
+  if (build_candidates<BS, true>(c, sh, 0)) C = list_lc<BS, true>(c, sh, pol);
+  const float invN = pauli_mask_and_scale<BS, true>(c, sh);
+  const int out = C < a.max_cand ? C : a.max_cand;
+  LDSP uint16_t* f = pol.fbuf + wv * zxmlp::IN;
+  for (int i = wv; i < out; i += BS / 64) {
+    const int u = uni((int)pol.list[i]);
+    candidate_features(c, u, invN, f);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < zxmlp::IN) a.feats[(int64_t)i * zxmlp::IN + lane] = f[lane];
+    if (lane == 0) a.cand[i] = u;
+  }
+  if (tid == 0) *a.n_cand = C;
+}
+
 // ------------------------------------------------------------- serving --
 __device__ __forceinline__ int64_t uni64(int64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -1732,6 +1781,31 @@ int roll_grid_max() {
   return (d ? d->n_cu : 256) * kRollBlocksPerCU;
 }
 }  // namespace
+
+extern "C" zx_status zx_policy_features(const zx_graph* g, int32_t* cand, uint16_t* feats, int32_t max_cand,
+                                        int32_t* n_cand, hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(g && n_cand && max_cand >= 0, "bad argument");
+  ZX_CHECK_ARG(max_cand == 0 || (cand && feats), "null buffer");
+  const ZxDevice* d = zx_device();
+  if (!d) return ZX_EDEVICE;
+  const int64_t lds = std::min<int64_t>(kRollLds, (int64_t)d->lds_per_block);
+  if (g->W > MAXW || g->n > 32767 || roll_lds_bytes(g->n, g->W) > lds) {
+    zx_set_error("diagram with %d spiders does not fit the features kernel's LDS", g->n);
+    return ZX_ECAPACITY;
+  }
+  const void* fn = (const void*)features_kernel<kRollBS>;
+  ZX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  FeatArgs a;
+  a.arena = g->arena;
+  a.cand = cand;
+  a.feats = feats;
+  a.max_cand = max_cand;
+  a.n_cand = n_cand;
+  hipLaunchKernelGGL(features_kernel<kRollBS>, dim3(1), dim3(kRollBS), (size_t)lds, s, a);
+  ZX_HIP(hipGetLastError());
+  return ZX_OK;
+}
 
 extern "C" size_t zx_rollout_workspace_bytes(zx_graph* const* states, int32_t n_states) {
   if (!states || n_states <= 0) return 0;

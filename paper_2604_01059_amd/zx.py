@@ -121,6 +121,7 @@ def load():
                         i32),
         "zx_rollout_workspace_bytes": ([P, i32], sz),
         "zx_rollout": ([P, i32, i32, P, P, P, P, P, sz, P], i32),
+        "zx_policy_features": ([P, P, P, i32, P, P], i32),
         "zx_server_create": ([C.POINTER(P), P, sz, i32, C.POINTER(SimplifyOpts), u32], i32),
         "zx_server_submit": ([P, C.POINTER(Request), C.POINTER(i64)], i32),
         "zx_server_poll": ([P, P, i32, C.POINTER(i32)], i32),
@@ -144,7 +145,7 @@ def exported_symbols():
             "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
             "zx_gf2_eliminate", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
             "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
-            "zx_mlp_adam", "zx_rollout_workspace_bytes", "zx_rollout", "zx_server_create",
+            "zx_mlp_adam", "zx_rollout_workspace_bytes", "zx_rollout", "zx_policy_features", "zx_server_create",
             "zx_server_submit", "zx_server_poll", "zx_server_stats_read", "zx_server_destroy"]
 
 
@@ -459,6 +460,21 @@ def rollout(states, per_state, stream=None):
     _check(load().zx_rollout(arr, n, per_state, _ptr(cost), _ptr(fill), _ptr(move), _ptr(feats), _ptr(ws),
                              ws.numel(), _stream(stream)))
     return cost, fill, move, feats
+
+
+def policy_features(graph, max_cand=None, stream=None):
+    """Candidates of the next LC round of graph's CURRENT state and their
+    learned-proposal features: (cand int32 tensor [C], feats int16 tensor
+    [C, MLP_IN] holding bf16 bits), C the full count (synchronous)."""
+    import torch
+    cap = graph.n if max_cand is None else max_cand
+    cand = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    feats = torch.empty((max(cap, 1), MLP_IN), dtype=torch.int16, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _check(load().zx_policy_features(graph.h, _ptr(cand), _ptr(feats), cap, _ptr(cnt), _stream(stream)))
+    C = int(cnt.item())
+    k = min(C, cap)
+    return cand[:k], feats[:k], C
 
 
 def simplify_variants():

@@ -239,3 +239,32 @@ def test_learned_first_round_follows_scores(zx):
         assert sorted(int(u) for u in tr[:, 2]) == sorted(taken), i
         checked += 1
     assert checked >= 5
+
+
+@pytest.mark.parametrize("item", range(6))
+def test_policy_features_match_oracle(zx, item):
+    """zx_policy_features: the next LC round's candidates (ascending) and their
+    features equal the oracle's, bit for bit, at the start and after some
+    rounds; a state past its LC phase has none."""
+    d = batch_diagram(43, 300 + item, q_hi=24)
+    full = oracle.Graph.from_diagram(d)
+    full.simplify()
+    for r in [0, 1, 2, full.rounds]:
+        og = oracle.Graph.from_diagram(d)
+        if r:
+            og.simplify(max_rounds=r)
+        zg = zx.Graph.from_diagram(d)
+        if r:
+            zx.simplify([zg], extract=False, max_rounds=r)
+        print("features", item, d.n, r, flush=True)
+        cand, feats, C = zx.policy_features(zg)
+        ent = opol.candidate_list(og)
+        assert C == len(ent), (item, r)
+        assert [int(u) for u in cand.cpu().numpy()] == [u for u, _ in ent]
+        fb = feats.cpu().numpy().view(np.uint16)
+        for i, (u, _) in enumerate(ent):
+            np.testing.assert_array_equal(fb[i], opol.features(og, u), err_msg=str((item, r, u)))
+    # a short output buffer gets the first rows and the full count
+    zg = zx.Graph.from_diagram(d)
+    cand, feats, C = zx.policy_features(zg, max_cand=2)
+    assert C == len(opol.candidate_list(oracle.Graph.from_diagram(d))) and len(cand) == min(C, 2)
