@@ -172,7 +172,7 @@ struct Pass {
 
 struct Smem {
   uint64_t tab[MAX_CW][128];   // 8 nibble tables of reduced pivot words, per column
-  uint64_t otab[MAX_CW][128];  // 8 nibble tables of original pivot words, per column
+  uint64_t pp[MAX_CW][SW];     // reduced pivot word of each strip bit (zero off the pivot mask), per column
   Pass ps[2];
   int32_t wcnt[NWAVE];         // candidates per wave
   int32_t cand[NCAND];
@@ -180,7 +180,6 @@ struct Smem {
   int32_t pcol[SW];
   uint32_t ackc[RING];         // acknowledgements known per ring slot (a lower bound)
   uint64_t emask[NWAVE];       // candidate lanes of the early slice, per wave
-  int32_t tinv[SW];            // pivot index of each strip bit of the pass being applied
   int32_t total, used, early, flag, cnt;
 };
 
@@ -316,62 +315,65 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LD
   }
 }
 
+// XOR scan over each 16-lane DPP row of the wavefront: lane 15 of a row ends
+// with the XOR of the row's 16 values (row_shr by 1, 2, 4, 8; lanes shifted
+// in from outside the row contribute zero).
+__device__ __forceinline__ uint32_t row_xor16(uint32_t v) {
+  v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Tables of pass R for `nc` columns, and R's pivot rows: marks them in
 // newpiv (this pass) and pivflag (all passes), and writes their reduced
-// words P' into the columns.  Two barriers: first the nibble tables of the
-// original pivot words (read straight from the columns) and the pivot index
-// of each strip bit; then the nibble tables of the reduced words, each entry
-// the XOR of up to four P'_t, each P'_t eight lookups by the nibbles of L_t,
-// with P' stored into the pivot rows.  The row update that follows leaves
-// newpiv rows as they are.
+// words into the columns.  The reduction takes strip bits in ascending
+// order, so the pivot at strip bit b is pivot t(b) = popcount(pivmask below
+// b), and its reduced word is P'_b = XOR of the original words of the pivots
+// in L_t(b).  Strip bit b = 4w + r is DPP row r of wave w: each of its 16
+// lanes XORs the original words of two pivots of L_t(b), a row XOR scan
+// leaves P'_b in the row's last lane, and wave w, which then holds the four
+// strip bits of nibble table w, writes that table (entry e = XOR of the P'_b
+// selected by the bits of e) and keeps its P'_b in S.pp.  After a barrier
+// (every original word has been read) the pivot rows take their P'; a second
+// barrier ends the call.  The row update that follows leaves newpiv rows as
+// they are.
 __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* newpiv, LDS uint64_t* pivflag,
                             const LDS Pass& R, LDS Smem& S) {
-  const int tid = threadIdx.x, k = R.k;
+  static_assert(NWAVE * 4 == SW, "one wave per nibble table");
+  const int tid = threadIdx.x, lane = tid & 63, k = R.k;
   if (tid < k) {
     const int r = R.rows[tid];
     __hip_atomic_fetch_or(&newpiv[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_or(&pivflag[r >> 6], 1ull << (r & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    S.tinv[R.bits[tid]] = tid;  // read only for strip bits in the pivot mask
   }
-  for (int x = tid; x < nc * 128; x += BS) {
-    const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
+  const uint32_t pm = R.pivmask;
+  const int w = tid >> 6, b = 4 * w + (lane >> 4), sub = lane & 15;
+  const uint32_t Lm = ((pm >> b) & 1) ? R.L[__popc(pm & ((1u << b) - 1u))] : 0u;
+  const bool u0 = (Lm >> (2 * sub)) & 1, u1 = (Lm >> (2 * sub + 1)) & 1;
+  const int r0 = u0 ? R.rows[2 * sub] : 0, r1 = u1 ? R.rows[2 * sub + 1] : 0;
+  for (int j = 0; j < nc; ++j) {
     const LDS uint64_t* c = cols[j];
-    uint64_t o[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = c[4 * q + i < k ? R.rows[4 * q + i] : 0];
-    uint64_t v = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v ^= (((sel >> i) & 1) && 4 * q + i < k) ? o[i] : 0ull;
-    S.otab[j][e] = v;
+    const uint64_t x0 = c[r0], x1 = c[r1];
+    const uint64_t v = (u0 ? x0 : 0ull) ^ (u1 ? x1 : 0ull);
+    const uint64_t p = ((uint64_t)row_xor16((uint32_t)(v >> 32)) << 32) | row_xor16((uint32_t)v);
+    const uint64_t p0 = readlane64(p, 15), p1 = readlane64(p, 31), p2 = readlane64(p, 47), p3 = readlane64(p, 63);
+    if (lane < 16)
+      S.tab[j][16 * w + lane] = ((lane & 1) ? p0 : 0ull) ^ ((lane & 2) ? p1 : 0ull) ^ ((lane & 4) ? p2 : 0ull) ^
+                                ((lane & 8) ? p3 : 0ull);
+    if (sub == 15) S.pp[j][b] = p;
   }
   __syncthreads();
-  const uint32_t pm = R.pivmask;
-  for (int x = tid; x < nc * (128 + SW); x += BS) {
-    if (x < nc * 128) {
-      const int j = x >> 7, e = x & 127, q = e >> 4, sel = e & 15;
-      const LDS uint64_t* ot = S.otab[j];
-      uint64_t v = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int b = 4 * q + i;
-        if (((sel >> i) & 1) && ((pm >> b) & 1)) {
-          const uint32_t Lm = R.L[S.tinv[b]];
-#pragma unroll
-          for (int qq = 0; qq < 8; ++qq) v ^= ot[16 * qq + ((Lm >> (4 * qq)) & 15)];
-        }
-      }
-      S.tab[j][e] = v;
-    } else {
-      const int y = x - nc * 128, j = y / SW, t = y % SW;
-      if (t < k) {
-        const LDS uint64_t* ot = S.otab[j];
-        const uint32_t Lm = R.L[t];
-        uint64_t v = 0;
-#pragma unroll
-        for (int qq = 0; qq < 8; ++qq) v ^= ot[16 * qq + ((Lm >> (4 * qq)) & 15)];
-        cols[j][R.rows[t]] = v;
-      }
-    }
+  for (int x = tid; x < nc * SW; x += BS) {
+    const int j = x / SW, t = x % SW;
+    if (t < k) cols[j][R.rows[t]] = S.pp[j][R.bits[t]];
   }
   __syncthreads();
 }
