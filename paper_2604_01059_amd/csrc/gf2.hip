@@ -63,21 +63,22 @@ constexpr int MAX_CW = 4;         // word columns per workgroup
 constexpr int MAX_STRIPS = 8192;  // strips with profile slots
 constexpr int PROF_SLOTS = 8;     // timestamps per strip (profiling only)
 constexpr int GROUP = 4;          // row slices updated together (loads in flight together)
-constexpr int PRE = 2 * GROUP;    // row slices whose snapshot multipliers are loaded with the record
+constexpr int PRE = 2 * GROUP;    // row slices whose snapshot multipliers are loaded right after the record
 constexpr int EARLY_MIN = 48;     // wave-0 candidates that allow reducing the next strip early
 
+// A published pass: one 64-bit word per pivot slot t, each carrying the
+// record's tag, so that the record itself is the publication:
+//   bits 0-13 pivot row, 14-18 its strip bit, 19 last (the strip is finished
+//   with this record), 20 valid (t < k), 21-31 tag (record index mod 2048),
+//   32-63 L_t.
+// A record with no valid slot ends a strip without pivots.
 struct PassRec {
-  int32_t strip;
-  int32_t k;         // pivots in this pass (0 for an end-of-strip marker)
-  int32_t last;      // strip finished with this record
-  uint32_t pivmask;  // strip bit positions that hold pivots
-  int32_t rows[SW];
-  int32_t bits[SW];
-  uint32_t L[SW];
+  uint64_t e[SW];
 };
+static_assert(MAX_M <= (1 << 14), "pivot rows fit 14 bits of a record word");
 
 struct Ctl {
-  uint32_t seq;        // records published
+  uint32_t fin;        // workgroups done with every pass
   uint32_t pad[63];
   uint32_t ack[RING];  // cumulative acknowledgements per slot
   uint32_t pad2[64 - RING];
@@ -127,6 +128,9 @@ __device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v) {
 __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int32_t ld_dev32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -150,10 +154,15 @@ __device__ bool spin_until(const uint32_t* p, uint32_t target, const Args& a) {
   }
 }
 
-__global__ void rref_init(Ctl* ctl, int32_t* status, uint64_t* prof) {
+// Before every elimination: control words zero, and every ring slot filled
+// with all-ones words (tag 2047), which no record matches before its slot is
+// rewritten (slot s holds records s, s + RING, ...), so that records left in
+// a reused workspace by an earlier launch are never taken for this one's.
+__global__ void rref_init(Ctl* ctl, PassRec* recs, int32_t* status, uint64_t* prof) {
   const int t = threadIdx.x;
   uint32_t* c = (uint32_t*)ctl;
   for (int i = t; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
+  for (int i = t; i < RING * SW; i += blockDim.x) recs[i / SW].e[i % SW] = ~0ull;
   if (prof)
     for (int i = t; i < MAX_STRIPS * PROF_SLOTS; i += blockDim.x) prof[i] = 0;
   if (t == 0) *status = 0;
@@ -191,6 +200,49 @@ __device__ __forceinline__ void prof_mark(const Args& a, int s, int slot) {
 }
 
 __device__ __forceinline__ bool bit_of(const LDS uint64_t* m, int r) { return (m[r >> 6] >> (r & 63)) & 1; }
+
+__device__ __forceinline__ uint64_t rec_word(const LDS Pass& P, int t, int k, int last, uint32_t seq) {
+  const bool valid = t < k;
+  const uint32_t lo = (valid ? ((uint32_t)P.rows[t] | ((uint32_t)P.bits[t] << 14) | (1u << 20)) : 0u) |
+                      ((uint32_t)last << 19) | ((seq & 0x7FFu) << 21);
+  return ((uint64_t)(valid ? P.L[t] : 0u) << 32) | lo;
+}
+
+// Wave 0: wait until ring slot `rec` holds record `seq` (every word carries
+// its tag; words of the slot's previous record or of a partly landed one do
+// not) and unpack it into P.  False on time-out or abort.
+__device__ bool read_record(const PassRec* rec, uint32_t seq, const Args& a, LDS Pass& P) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t tag = seq & 0x7FFu;
+  const uint64_t t0 = wall_clock64();
+  uint64_t e;
+  for (;;) {
+    e = lane < SW ? ld_dev64(&rec->e[lane]) : ((uint64_t)tag << 21);
+    const int32_t st = lane == 0 ? __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    if (__ballot(((uint32_t)e >> 21) != tag) == 0) break;
+    if (__builtin_amdgcn_readfirstlane(st) != 0) return false;
+    if (wall_clock64() - t0 > a.spin_ticks) {
+      if (lane == 0) zx_dev_fail(a.status, ZX_EDEVICE);
+      return false;
+    }
+  }
+  const uint32_t lo = (uint32_t)e;
+  const bool valid = lane < SW && ((lo >> 20) & 1);
+  if (valid) {
+    P.rows[lane] = (int32_t)(lo & 0x3FFFu);
+    P.bits[lane] = (int32_t)((lo >> 14) & 31u);
+    P.L[lane] = (uint32_t)(e >> 32);
+  }
+  const uint64_t vmask = __ballot(valid);  // the valid slots are 0..k-1
+  if (lane == 0) {
+    P.k = __popcll(vmask);
+    P.last = (int32_t)((lo >> 19) & 1u);
+    P.pivmask = 0;
+  }
+  // LDS operations of one wave complete in order: the clear comes first
+  if (valid) __hip_atomic_fetch_or(&P.pivmask, 1u << ((lo >> 14) & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return true;
+}
 
 // Candidates from per-thread flags (bit i = row tid + i*BS): up to NCAND of
 // them go to S.cand, the count of all to S.total.  Any set of candidate rows
@@ -805,23 +857,20 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         LDS Pass& Pc = S.ps[cur];
         const int k = Pc.k;
         const int last = (total == 0 || k == SW || total <= used) ? 1 : 0;
-        if (tid < k) {
-          st_dev32(&rec->rows[tid], Pc.rows[tid]);
-          st_dev32(&rec->bits[tid], Pc.bits[tid]);
-          st_dev(&rec->L[tid], Pc.L[tid]);
+        // this pass's snapshot and every earlier store of the workgroup have
+        // landed; then the record words publish the pass
+        wait_stores();
+        __syncthreads();
+        if (tid < SW) st_dev64(&rec->e[tid], rec_word(Pc, tid, k, last, seq));
+        if (!(last && multi) && tid < k) {
+          // pivot list entries: read only after every workgroup is done
           st_dev32(&a.piv_row[rank + tid], Pc.rows[tid]);
           st_dev32(&a.piv_col[rank + tid], SW * t + Pc.bits[tid]);
         }
-        if (tid == 0) {
-          st_dev32(&rec->strip, t);
-          st_dev32(&rec->k, k);
-          st_dev32(&rec->last, last);
-          st_dev(&rec->pivmask, Pc.pivmask);
-        }
         if (last && multi && tid == 64) {
           // multi-pass strip (rare): sort its pivot list by column.  A strip
-          // holds at most 32 pivots; earlier passes' entries are read back,
-          // this pass's come from the reduction.
+          // holds at most 32 pivots; earlier passes' entries (landed, waited
+          // for above) are read back, this pass's come from the reduction.
           int cnt = 0;
           for (int i = rank0; i < rank; ++i) {
             S.prow[cnt] = ld_dev32(&a.piv_row[i]);
@@ -846,19 +895,13 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           }
           S.cnt = cnt;
         }
-        wait_stores();
-        __syncthreads();
         if (last && multi) {
+          __syncthreads();
           if (tid < S.cnt) {
             st_dev32(&a.piv_row[rank0 + tid], S.prow[tid]);
             st_dev32(&a.piv_col[rank0 + tid], S.pcol[tid]);
           }
-          wait_stores();
-          __syncthreads();
         }
-        // the flag and the acknowledgements are stored from wave 1, which
-        // never reduces candidates: wave 0 then has no store in flight
-        if (tid == 64) st_dev(&a.ctl->seq, seq + 1);
         if (tid == 0) prof_mark(a, t, 2);
         ++seq;
         if (k > 0) {
@@ -909,13 +952,22 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
       const bool own_next = (t + 1 < a.nstrips) && (((t + 1) >> 1) % G) == g && ((t + 1) & 1) == 0;
       for (;;) {
         const int slot = seq % RING;
-        if (tid == 0) S.flag = spin_until(&a.ctl->seq, seq + 1, a) ? 1 : 0;
-        __syncthreads();
-        if (!S.flag) { ok = false; break; }
         const PassRec* rec = a.recs + slot;
         const uint32_t* snap = a.snaps + (size_t)slot * m;
         LDS Pass& Pc = S.ps[cur];
-        // the record and the first multipliers are loaded together
+        if (tid < 64) {
+          const bool got = read_record(rec, seq, a, Pc);
+          if (tid == 0) {
+            S.flag = got ? 1 : 0;
+            if (got && own_next) {
+              const uint32_t nslot = (seq + 1) % RING, v = ld_dev(&a.ctl->ack[nslot]);
+              if (v > S.ackc[nslot]) S.ackc[nslot] = v;
+            }
+          }
+        }
+        __syncthreads();
+        if (!S.flag) { ok = false; break; }
+        // the first multipliers, in flight during the tables
         uint32_t pre[PRE];
 #pragma unroll
         for (int q = 0; q < PRE; ++q) {
@@ -929,21 +981,6 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           const int r = xs * BS + fw * 64 + (tid & 63);
           if ((tid >> 6) != fw && xs < nsl && r < m) prex = ld_dev(&snap[r]);
         }
-        if (tid == 0) {
-          Pc.k = ld_dev32(&rec->k);
-          Pc.last = ld_dev32(&rec->last);
-          Pc.pivmask = ld_dev(&rec->pivmask);
-          if (own_next) {
-            const uint32_t nslot = (seq + 1) % RING, v = ld_dev(&a.ctl->ack[nslot]);
-            if (v > S.ackc[nslot]) S.ackc[nslot] = v;
-          }
-        }
-        if (tid < SW) {
-          Pc.rows[tid] = ld_dev32(&rec->rows[tid]);
-          Pc.bits[tid] = ld_dev32(&rec->bits[tid]);
-          Pc.L[tid] = ld_dev(&rec->L[tid]);
-        }
-        __syncthreads();
         const int k = Pc.k, last = Pc.last;
         const bool fused = own_next && last && k > 0;
         if (tid == 0 && own_next && last) prof_mark(a, t, 4);
@@ -1000,6 +1037,15 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
     }
   }
   if (!ok) return;
+  // every workgroup's pivot list entries have landed before any reads them
+  wait_stores();
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_fetch_add(&a.ctl->fin, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    S.flag = spin_until(&a.ctl->fin, (uint32_t)G, a) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!S.flag) return;
   // ---------------- write the result ----------------
   // T: rows in pivot order, then the rows that are no pivot, ascending (their
   // transform rows span the left null space); piv_base[w] = non-pivot rows in
@@ -1170,7 +1216,7 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
   a.spin_ticks = 100000000ull * 5;  // 5 s at the 100 MHz real-time counter
   static const bool prof_on = getenv("ZX_RREF_PROFILE") && getenv("ZX_RREF_PROFILE")[0] == '1';
   a.prof = prof_on ? (uint64_t*)(base + W.prof) : nullptr;
-  hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.status, a.prof);
+  hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.recs, a.status, a.prof);
   ZX_HIP(hipGetLastError());
   void* args[] = {&a};
   ZX_HIP(hipLaunchCooperativeKernel((const void*)rref_kernel, dim3(G), dim3(BS), args, (unsigned)lds, s));

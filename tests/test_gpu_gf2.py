@@ -106,6 +106,30 @@ def test_repeat_reuses_workspace(zx):
     assert np.array_equal(zx.to_host_words(R), first)
 
 
+def test_workspace_reuse_different_inputs(zx):
+    """One workspace through eliminations of different matrices: the pass
+    records an earlier launch left in the workspace never stand in for this
+    launch's (each result equals the oracle's)."""
+    import torch
+    from workloads.generators import unpack_rows
+    m, n = 512, 4096
+    ws = None
+    rng = np.random.default_rng(5)
+    cases = [bernoulli_matrix(s, m, n) for s in (7, 8, 9)]
+    # rank-deficient: 200 independent rows repeated, so strips take residual passes
+    base = unpack_rows(bernoulli_matrix(10, 200, n), n)
+    cases.append(pack_rows(base[rng.integers(0, 200, m)]))
+    for A in cases:
+        dA = zx.to_device_words(A)
+        R, rank, piv, ws = zx.gf2_eliminate(dA, n_cols=n, ws=ws)
+        torch.cuda.synchronize()
+        assert zx.gf2_status(ws) == 0
+        Ro, pivo, ranko, _ = oracle.gf2_rref(A, n)
+        assert int(rank.item()) == ranko
+        assert np.array_equal(piv.cpu().numpy(), pivo)
+        assert np.array_equal(zx.to_host_words(R), Ro)
+
+
 def test_capacity_error(zx):
     import torch
     dA = torch.zeros((16385, 1), dtype=torch.int64, device="cuda")
