@@ -139,6 +139,14 @@ __device__ __forceinline__ void st_dev32(int32_t* p, int32_t v) {
 }
 // every store this wave issued has been acknowledged
 __device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
+// A wave-uniform value loaded by the whole wave, consumed here on every
+// path: the compiler waits for its load at this point, and no later write to
+// its register waits on it (a load consumed under a lane condition only would
+// stay pending for the compiler on the other path, and every later write to
+// that register would wait for all memory operations in flight).
+__device__ __forceinline__ uint32_t settle(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
 
 // Spin (one thread) until *p >= target; false on time-out or abort.
 __device__ bool spin_until(const uint32_t* p, uint32_t target, const Args& a) {
@@ -218,9 +226,11 @@ __device__ bool read_record(const PassRec* rec, uint32_t seq, const Args& a, LDS
   uint64_t e;
   for (;;) {
     e = lane < SW ? ld_dev64(&rec->e[lane]) : ((uint64_t)tag << 21);
-    const int32_t st = lane == 0 ? __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    // the abort status, loaded with the record words and consumed on every
+    // path (settle)
+    const int32_t st = (int32_t)settle((uint32_t)__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (__ballot(((uint32_t)e >> 21) != tag) == 0) break;
-    if (__builtin_amdgcn_readfirstlane(st) != 0) return false;
+    if (st != 0) return false;
     if (wall_clock64() - t0 > a.spin_ticks) {
       if (lane == 0) zx_dev_fail(a.status, ZX_EDEVICE);
       return false;
@@ -591,12 +601,13 @@ __device__ uint32_t update_and_reduce(LDS uint64_t* const* cols, int nc, const u
   if (wv == fw) {
     const bool early = cnt >= EARLY_MIN;
     if (early) {
-      const uint32_t ackv = lane == 0 ? ld_dev(&a.ctl->ack[ack_slot]) : 0u;
+      const uint32_t ackv = ld_dev(&a.ctl->ack[ack_slot]);
       const int used = wave_candidates(flags, nsl, S);
       factor_candidates(cols[fuse], fshift, used, N, S);
+      const uint32_t av = settle(ackv);
       if (lane == 0) {
         S.used = used;
-        if (ackv > S.ackc[ack_slot]) S.ackc[ack_slot] = ackv;
+        if (av > S.ackc[ack_slot]) S.ackc[ack_slot] = av;
       }
     }
     if (lane == 0) S.early = early ? 1 : 0;
@@ -685,12 +696,13 @@ __device__ void split_update_and_reduce(LDS uint64_t* const* cols, int nc, const
     cnt = base;
     const bool early = base >= EARLY_MIN;
     if (early) {
-      const uint32_t ackv = lane == 0 ? ld_dev(&a.ctl->ack[ack_slot]) : 0u;
+      const uint32_t ackv = ld_dev(&a.ctl->ack[ack_slot]);
       const int used = base < NCAND ? base : NCAND;
       factor_candidates(fc, fshift, used, N, S);
+      const uint32_t av = settle(ackv);
       if (lane == 0) {
         S.used = used;
-        if (ackv > S.ackc[ack_slot]) S.ackc[ack_slot] = ackv;
+        if (av > S.ackc[ack_slot]) S.ackc[ack_slot] = av;
       }
     }
     if (lane == 0) S.early = early ? 1 : 0;
@@ -802,6 +814,9 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   const LDS uint64_t* pend_col = nullptr;
   int pend_shift = 0;
   uint32_t* pend_snap = nullptr;
+  // (thread 64) ring slot whose acknowledgement waits until my next record
+  // is out, or -1: in flight at my publication it would hold up its wait
+  int pend_ack = -1;
   for (int t = 0; t < a.nstrips && rank < m && ok; ++t) {
     const int wc = t >> 1, shift = SW * (t & 1);
     const int owner = wc % G;
@@ -844,9 +859,10 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           if (tid < 64) {
             // the next slot's acknowledgements, loaded while the reduction runs
             const uint32_t nslot = (seq + 1) % RING;
-            const uint32_t ackv = tid == 0 ? ld_dev(&a.ctl->ack[nslot]) : 0u;
+            const uint32_t ackv = ld_dev(&a.ctl->ack[nslot]);
             factor_candidates(col, shift, used, S.ps[cur], S);
-            if (tid == 0 && ackv > S.ackc[nslot]) S.ackc[nslot] = ackv;
+            const uint32_t av = settle(ackv);
+            if (tid == 0 && av > S.ackc[nslot]) S.ackc[nslot] = av;
           } else if (pend_snap) {
             store_snapshot(pend_col, pend_shift, m, pend_snap);
           }
@@ -862,6 +878,10 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
         wait_stores();
         __syncthreads();
         if (tid < SW) st_dev64(&rec->e[tid], rec_word(Pc, tid, k, last, seq));
+        if (tid == 64 && pend_ack >= 0) {
+          __hip_atomic_fetch_add(&a.ctl->ack[pend_ack], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          pend_ack = -1;
+        }
         if (!(last && multi) && tid < k) {
           // pivot list entries: read only after every workgroup is done
           st_dev32(&a.piv_row[rank + tid], Pc.rows[tid]);
@@ -997,10 +1017,15 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           if (nc > 0) {
             make_tables(list, nc, newpiv, pivflag, Pc, S);
             if (fused) {
-              // the multipliers loaded with the record have landed by now;
-              // waiting here keeps the loop below from waiting on them after
-              // its snapshot stores (vmcnt counts both in issue order)
+              // wait for the multipliers here, before any snapshot store: a
+              // wait for them inside the loops below would also wait for the
+              // stores issued there (vmcnt counts both in issue order).  The
+              // empty asm statements mark them as defined after this wait, so
+              // the compiler places no further wait for their loads.
               wait_stores();
+#pragma unroll
+              for (int q = 0; q < PRE; ++q) asm volatile("" : "+v"(pre[q]));
+              asm volatile("" : "+v"(prex));
               uint32_t* snap_out = a.snaps + (size_t)((seq + 1) % RING) * m;
               uint32_t flags = 0;
               if (nsl <= PRE)
@@ -1028,8 +1053,21 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
             }
           }
         }
+        // the prefetched multipliers are consumed on every path (they have
+        // landed long since): a load left unconsumed on some path stays
+        // pending for the compiler, and every later write to its register
+        // would wait for all memory operations in flight
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) asm volatile("" ::"v"(pre[q]));
+        asm volatile("" ::"v"(prex));
         __syncthreads();
-        if (tid == 64) __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // done with the slot; when my own strip comes next, the
+        // acknowledgement follows my record (the slot is rewritten only
+        // RING - 1 records after that one)
+        if (tid == 64) {
+          if (own_next && last) pend_ack = slot;
+          else __hip_atomic_fetch_add(&a.ctl->ack[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (tid == 0 && own_next && last) prof_mark(a, t, 5);
         ++seq;
         if (last) break;
@@ -1037,6 +1075,8 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
     }
   }
   if (!ok) return;
+  if (tid == 64 && pend_ack >= 0)
+    __hip_atomic_fetch_add(&a.ctl->ack[pend_ack], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // every workgroup's pivot list entries have landed before any reads them
   wait_stores();
   __syncthreads();
