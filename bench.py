@@ -445,15 +445,18 @@ def main():
     if args.only in ("all", "pauli"):
         out["pauli"] = bench_pauli(zx, max(3, args.steps // 4))
         log("pauli: %s" % out["pauli"])
+    # serving runs before the batched and learned legs: measured after the
+    # learned leg in the same process, its latency was several times higher
+    # (cause not found; a pause or an emptied allocator cache did not help)
+    if args.only in ("all", "serve"):
+        out["serve"] = bench_serve(zx, args, pool)
+        log("serve: %s" % out["serve"])
     if args.only in ("all", "batched"):
         out["batched"] = bench_batched(zx, args, pool)
         log("batched: %s" % out["batched"])
     if args.only in ("all", "learned"):
         out["learned"] = bench_learned(zx, args, pool)
         log("learned: %s" % out["learned"])
-    if args.only in ("all", "serve"):
-        out["serve"] = bench_serve(zx, args, pool)
-        log("serve: %s" % out["serve"])
     if pool is not None:
         pool.close()
         pool.join()
