@@ -303,7 +303,7 @@ __device__ void store_snapshot(const LDS uint64_t* col, int shift, int m, uint32
 // One elimination step of the candidate reduction, for strip bit B, in
 // wavefront registers: w = the lane's candidate strip word, L = its mask of
 // original pivots, jb = 1 + pivot index | B << 8 on pivot lanes; P = lanes
-// already pivots, k = pivots so far, pm = strip bits holding pivots.
+// already pivots, k = pivots so far.
 //   h = lanes holding bit B; c = h & ~P; if c is empty the step is a no-op;
 //   else src = first lane of c becomes pivot k: every other lane of h gets
 //   w ^= w[src], L ^= L[src] | 1 << k, and lane src gets L = L[src] | 1 << k.
@@ -312,17 +312,15 @@ __device__ void store_snapshot(const LDS uint64_t* col, int shift, int m, uint32
 // under an exec mask of h minus src, the pivot's own update under an exec
 // mask of src alone, and exec is restored before the block ends.
 template <int B>
-__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k,
-                                            uint32_t& pm) {
+__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k) {
   uint64_t c, m, sv;
   uint32_t t, spw, spl, sjb;
   int src;
   asm volatile(
       "v_and_b32 %[t], %[bit], %[w]\n\t"
       "v_cmp_ne_u32 vcc, 0, %[t]\n\t"
-      "s_andn2_b64 %[c], vcc, %[P]\n\t"
-      "s_cmp_eq_u64 %[c], 0\n\t"
-      "s_cbranch_scc1 .Lfactor_skip%=\n\t"
+      "s_andn2_b64 %[c], vcc, %[P]\n\t"  // SCC = (c != 0)
+      "s_cbranch_scc0 .Lfactor_skip%=\n\t"
       "s_ff1_i32_b64 %[src], %[c]\n\t"
       "s_lshl_b64 %[m], 1, %[src]\n\t"
       "s_or_b64 %[P], %[P], %[m]\n\t"
@@ -338,10 +336,9 @@ __device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& 
       "v_mov_b32 %[L], %[spl]\n\t"
       "v_mov_b32 %[jb], %[sjb]\n\t"
       "s_mov_b64 exec, %[sv]\n\t"
-      "s_add_u32 %[k], %[k], 1\n\t"
-      "s_or_b32 %[pm], %[pm], %[bit]\n"
+      "s_add_u32 %[k], %[k], 1\n"
       ".Lfactor_skip%=:"
-      : [w] "+v"(w), [L] "+v"(L), [jb] "+v"(jb), [P] "+s"(P), [k] "+s"(k), [pm] "+s"(pm), [t] "=&v"(t),
+      : [w] "+v"(w), [L] "+v"(L), [jb] "+v"(jb), [P] "+s"(P), [k] "+s"(k), [t] "=&v"(t),
         [c] "=&s"(c), [m] "=&s"(m), [sv] "=&s"(sv), [spw] "=&s"(spw), [spl] "=&s"(spl), [sjb] "=&s"(sjb),
         [src] "=&s"(src)
       : [bit] "s"(1u << B), [jbk] "s"((uint32_t)((B << 8) + 1))
@@ -349,10 +346,9 @@ __device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& 
 }
 
 template <int B>
-__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k,
-                                             uint32_t& pm) {
-  factor_step<B>(w, L, jb, P, k, pm);
-  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, jb, P, k, pm);
+__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k) {
+  factor_step<B>(w, L, jb, P, k);
+  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, jb, P, k);
 }
 
 // Wave 0 (all 64 lanes active): reduce the first nc candidates of S.cand,
@@ -361,10 +357,10 @@ __device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t&
 __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LDS Pass& N, LDS Smem& S) {
   const int lane = threadIdx.x & 63;
   uint32_t w = lane < nc ? (uint32_t)(col[S.cand[lane]] >> shift) : 0;
-  uint32_t L = 0, jb = 0, pm = 0;
+  uint32_t L = 0, jb = 0;
   uint64_t P = 0;
   int k = 0;
-  factor_steps<0>(w, L, jb, P, k, pm);
+  factor_steps<0>(w, L, jb, P, k);
   if (jb) {
     const int j = (int)(jb & 0xff) - 1;
     N.L[j] = L;
@@ -373,8 +369,11 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LD
   }
   if (lane == 0) {
     N.k = k;
-    N.pivmask = pm;
+    N.pivmask = 0;
   }
+  // the pivot mask from the pivot lanes' strip bits (LDS operations of one
+  // wave complete in order: the clear comes first)
+  if (jb) __hip_atomic_fetch_or(&N.pivmask, 1u << (jb >> 8), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // XOR scan over each 16-lane DPP row of the wavefront: lane 15 of a row ends
