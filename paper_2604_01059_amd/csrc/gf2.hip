@@ -302,19 +302,18 @@ __device__ void store_snapshot(const LDS uint64_t* col, int shift, int m, uint32
 
 // One elimination step of the candidate reduction, for strip bit B, in
 // wavefront registers: w = the lane's candidate strip word, L = its mask of
-// original pivots, jb = 1 + pivot index | B << 8 on pivot lanes; P = lanes
-// already pivots, k = pivots so far.
+// original pivots; P = lanes already pivots, k = pivots so far.
 //   h = lanes holding bit B; c = h & ~P; if c is empty the step is a no-op;
 //   else src = first lane of c becomes pivot k: every other lane of h gets
 //   w ^= w[src], L ^= L[src] | 1 << k, and lane src gets L = L[src] | 1 << k.
-// Written out by hand (about twenty instructions; a single wave issues about
+// Written out by hand (eighteen instructions; a single wave issues about
 // one instruction per four cycles, so the count sets the cost): the XORs run
 // under an exec mask of h minus src, the pivot's own update under an exec
 // mask of src alone, and exec is restored before the block ends.
 template <int B>
-__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k) {
+__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint64_t& P, int& k) {
   uint64_t c, m, sv;
-  uint32_t t, spw, spl, sjb;
+  uint32_t t, spw, spl;
   int src;
   asm volatile(
       "v_and_b32 %[t], %[bit], %[w]\n\t"
@@ -328,27 +327,24 @@ __device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint32_t& 
       "v_readlane_b32 %[spw], %[w], %[src]\n\t"
       "v_readlane_b32 %[spl], %[L], %[src]\n\t"
       "s_bitset1_b32 %[spl], %[k]\n\t"
-      "s_add_u32 %[sjb], %[k], %[jbk]\n\t"
       "s_and_saveexec_b64 %[sv], vcc\n\t"
       "v_xor_b32 %[w], %[spw], %[w]\n\t"
       "v_xor_b32 %[L], %[spl], %[L]\n\t"
       "s_and_b64 exec, %[sv], %[m]\n\t"
       "v_mov_b32 %[L], %[spl]\n\t"
-      "v_mov_b32 %[jb], %[sjb]\n\t"
       "s_mov_b64 exec, %[sv]\n\t"
       "s_add_u32 %[k], %[k], 1\n"
       ".Lfactor_skip%=:"
-      : [w] "+v"(w), [L] "+v"(L), [jb] "+v"(jb), [P] "+s"(P), [k] "+s"(k), [t] "=&v"(t),
-        [c] "=&s"(c), [m] "=&s"(m), [sv] "=&s"(sv), [spw] "=&s"(spw), [spl] "=&s"(spl), [sjb] "=&s"(sjb),
-        [src] "=&s"(src)
-      : [bit] "s"(1u << B), [jbk] "s"((uint32_t)((B << 8) + 1))
+      : [w] "+v"(w), [L] "+v"(L), [P] "+s"(P), [k] "+s"(k), [t] "=&v"(t), [c] "=&s"(c), [m] "=&s"(m),
+        [sv] "=&s"(sv), [spw] "=&s"(spw), [spl] "=&s"(spl), [src] "=&s"(src)
+      : [bit] "s"(1u << B)
       : "vcc", "scc");
 }
 
 template <int B>
-__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t& jb, uint64_t& P, int& k) {
-  factor_step<B>(w, L, jb, P, k);
-  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, jb, P, k);
+__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint64_t& P, int& k) {
+  factor_step<B>(w, L, P, k);
+  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, P, k);
 }
 
 // Wave 0 (all 64 lanes active): reduce the first nc candidates of S.cand,
@@ -357,23 +353,31 @@ __device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint32_t&
 __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LDS Pass& N, LDS Smem& S) {
   const int lane = threadIdx.x & 63;
   uint32_t w = lane < nc ? (uint32_t)(col[S.cand[lane]] >> shift) : 0;
-  uint32_t L = 0, jb = 0;
+  uint32_t L = 0;
   uint64_t P = 0;
   int k = 0;
-  factor_steps<0>(w, L, jb, P, k);
-  if (jb) {
-    const int j = (int)(jb & 0xff) - 1;
-    N.L[j] = L;
-    N.rows[j] = S.cand[lane];
-    N.bits[j] = (int)(jb >> 8);
-  }
+  factor_steps<0>(w, L, P, k);
+  // A pivot lane's strip bit is the lowest set bit of its final word: bits
+  // below it that hold pivots were cleared at their steps, bits below it
+  // without a pivot are clear in every lane that was not yet a pivot at that
+  // step, and the pivots XORed in later are clear at both.  Its pivot index
+  // is the number of pivot bits below its own.
+  const bool piv = (P >> lane) & 1;
+  const int b = piv ? __builtin_ctz(w) : 0;
   if (lane == 0) {
     N.k = k;
     N.pivmask = 0;
   }
-  // the pivot mask from the pivot lanes' strip bits (LDS operations of one
-  // wave complete in order: the clear comes first)
-  if (jb) __hip_atomic_fetch_or(&N.pivmask, 1u << (jb >> 8), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  // LDS operations of one wave complete in order: the clear, the ORs, then
+  // the read of the mask
+  if (piv) __hip_atomic_fetch_or(&N.pivmask, 1u << b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const uint32_t pm = __hip_atomic_load(&N.pivmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (piv) {
+    const int j = __popc(pm & ((1u << b) - 1u));
+    N.L[j] = L;
+    N.rows[j] = S.cand[lane];
+    N.bits[j] = b;
+  }
 }
 
 // XOR scan over each 16-lane DPP row of the wavefront: lane 15 of a row ends
