@@ -305,11 +305,13 @@ __device__ void store_snapshot(const LDS uint64_t* col, int shift, int m, uint32
 // original pivots; P = lanes already pivots, k = pivots so far.
 //   h = lanes holding bit B; c = h & ~P; if c is empty the step is a no-op;
 //   else src = first lane of c becomes pivot k: every other lane of h gets
-//   w ^= w[src], L ^= L[src] | 1 << k, and lane src gets L = L[src] | 1 << k.
-// Written out by hand (eighteen instructions; a single wave issues about
-// one instruction per four cycles, so the count sets the cost): the XORs run
-// under an exec mask of h minus src, the pivot's own update under an exec
-// mask of src alone, and exec is restored before the block ends.
+//   w ^= w[src], L ^= L[src] | 1 << k.  Lane src keeps L[src]: its mask
+//   lacks its own bit k, which only ever changes by XOR afterwards, so the
+//   pivot's mask is its final L with bit k flipped, applied once at the end.
+// Written out by hand (sixteen instructions; a single wave issues about one
+// instruction per four cycles, so the count sets the cost): the XORs run
+// under an exec mask of h minus src, and exec is restored before the block
+// ends.
 template <int B>
 __device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint64_t& P, int& k) {
   uint64_t c, m, sv;
@@ -330,8 +332,6 @@ __device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint64_t& 
       "s_and_saveexec_b64 %[sv], vcc\n\t"
       "v_xor_b32 %[w], %[spw], %[w]\n\t"
       "v_xor_b32 %[L], %[spl], %[L]\n\t"
-      "s_and_b64 exec, %[sv], %[m]\n\t"
-      "v_mov_b32 %[L], %[spl]\n\t"
       "s_mov_b64 exec, %[sv]\n\t"
       "s_add_u32 %[k], %[k], 1\n"
       ".Lfactor_skip%=:"
@@ -374,7 +374,7 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LD
   const uint32_t pm = __hip_atomic_load(&N.pivmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   if (piv) {
     const int j = __popc(pm & ((1u << b) - 1u));
-    N.L[j] = L;
+    N.L[j] = L ^ (1u << j);
     N.rows[j] = S.cand[lane];
     N.bits[j] = b;
   }
