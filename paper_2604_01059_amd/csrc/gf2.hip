@@ -70,7 +70,7 @@ constexpr int EARLY_MIN = 48;     // wave-0 candidates that allow reducing the n
 // record's tag, so that the record itself is the publication:
 //   bits 0-13 pivot row, 14-18 its strip bit, 19 last (the strip is finished
 //   with this record), 20 valid (t < k), 21-31 tag (record index mod 2048),
-//   32-63 L_t.
+//   32-63 L_t (the original pivots that combine into pivot t, by strip bit).
 // A record with no valid slot ends a strip without pivots.
 struct PassRec {
   uint64_t e[SW];
@@ -177,8 +177,9 @@ __global__ void rref_init(Ctl* ctl, PassRec* recs, int32_t* status, uint64_t* pr
 }
 
 // One pass in LDS: its pivot rows, their strip bits and masks of original
-// pivots.  Two are kept: the pass being applied and the pass a wavefront
-// reduces meanwhile.
+// pivots (bit q of L[t]: the original word of the pivot of strip bit q takes
+// part in pivot t).  Two are kept: the pass being applied and the pass a
+// wavefront reduces meanwhile.
 struct Pass {
   int32_t k, last;
   uint32_t pivmask;
@@ -302,19 +303,20 @@ __device__ void store_snapshot(const LDS uint64_t* col, int shift, int m, uint32
 
 // One elimination step of the candidate reduction, for strip bit B, in
 // wavefront registers: w = the lane's candidate strip word, L = its mask of
-// original pivots; P = lanes already pivots, k = pivots so far.
+// original pivots, indexed by their strip bits; P = lanes already pivots.
 //   h = lanes holding bit B; c = h & ~P; if c is empty the step is a no-op;
-//   else src = first lane of c becomes pivot k: every other lane of h gets
-//   w ^= w[src], L ^= L[src] | 1 << k.  Lane src keeps L[src]: its mask
-//   lacks its own bit k, which only ever changes by XOR afterwards, so the
-//   pivot's mask is its final L with bit k flipped, applied once at the end.
-// Written out by hand (sixteen instructions; a single wave issues about one
+//   else src = first lane of c becomes the pivot of bit B: every other lane
+//   of h gets w ^= w[src], L ^= L[src] | 1 << B.  Lane src keeps L[src]: its
+//   mask lacks its own bit B, which only ever changes by XOR afterwards, so
+//   the pivot's mask is its final L with bit B flipped, applied once at the
+//   end.
+// Written out by hand (thirteen instructions; a single wave issues about one
 // instruction per four cycles, so the count sets the cost): the XORs run
 // under an exec mask of h minus src, and exec is restored before the block
 // ends.
 template <int B>
-__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint64_t& P, int& k) {
-  uint64_t c, m, sv;
+__device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint64_t& P) {
+  uint64_t c, sv;
   uint32_t t, spw, spl;
   int src;
   asm volatile(
@@ -323,28 +325,26 @@ __device__ __forceinline__ void factor_step(uint32_t& w, uint32_t& L, uint64_t& 
       "s_andn2_b64 %[c], vcc, %[P]\n\t"  // SCC = (c != 0)
       "s_cbranch_scc0 .Lfactor_skip%=\n\t"
       "s_ff1_i32_b64 %[src], %[c]\n\t"
-      "s_lshl_b64 %[m], 1, %[src]\n\t"
-      "s_or_b64 %[P], %[P], %[m]\n\t"
-      "s_andn2_b64 vcc, vcc, %[m]\n\t"
+      "s_bitset1_b64 %[P], %[src]\n\t"
+      "s_bitset0_b64 vcc, %[src]\n\t"
       "v_readlane_b32 %[spw], %[w], %[src]\n\t"
       "v_readlane_b32 %[spl], %[L], %[src]\n\t"
-      "s_bitset1_b32 %[spl], %[k]\n\t"
+      "s_or_b32 %[spl], %[spl], %[bit]\n\t"
       "s_and_saveexec_b64 %[sv], vcc\n\t"
       "v_xor_b32 %[w], %[spw], %[w]\n\t"
       "v_xor_b32 %[L], %[spl], %[L]\n\t"
-      "s_mov_b64 exec, %[sv]\n\t"
-      "s_add_u32 %[k], %[k], 1\n"
+      "s_mov_b64 exec, %[sv]\n"
       ".Lfactor_skip%=:"
-      : [w] "+v"(w), [L] "+v"(L), [P] "+s"(P), [k] "+s"(k), [t] "=&v"(t), [c] "=&s"(c), [m] "=&s"(m),
-        [sv] "=&s"(sv), [spw] "=&s"(spw), [spl] "=&s"(spl), [src] "=&s"(src)
+      : [w] "+v"(w), [L] "+v"(L), [P] "+s"(P), [t] "=&v"(t), [c] "=&s"(c), [sv] "=&s"(sv), [spw] "=&s"(spw),
+        [spl] "=&s"(spl), [src] "=&s"(src)
       : [bit] "s"(1u << B)
       : "vcc", "scc");
 }
 
 template <int B>
-__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint64_t& P, int& k) {
-  factor_step<B>(w, L, P, k);
-  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, P, k);
+__device__ __forceinline__ void factor_steps(uint32_t& w, uint32_t& L, uint64_t& P) {
+  factor_step<B>(w, L, P);
+  if constexpr (B + 1 < SW) factor_steps<B + 1>(w, L, P);
 }
 
 // Wave 0 (all 64 lanes active): reduce the first nc candidates of S.cand,
@@ -355,8 +355,8 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LD
   uint32_t w = lane < nc ? (uint32_t)(col[S.cand[lane]] >> shift) : 0;
   uint32_t L = 0;
   uint64_t P = 0;
-  int k = 0;
-  factor_steps<0>(w, L, P, k);
+  factor_steps<0>(w, L, P);
+  const int k = __popcll(P);
   // A pivot lane's strip bit is the lowest set bit of its final word: bits
   // below it that hold pivots were cleared at their steps, bits below it
   // without a pivot are clear in every lane that was not yet a pivot at that
@@ -374,7 +374,7 @@ __device__ void factor_candidates(const LDS uint64_t* col, int shift, int nc, LD
   const uint32_t pm = __hip_atomic_load(&N.pivmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   if (piv) {
     const int j = __popc(pm & ((1u << b) - 1u));
-    N.L[j] = L ^ (1u << j);
+    N.L[j] = L ^ (1u << b);
     N.rows[j] = S.cand[lane];
     N.bits[j] = b;
   }
@@ -402,8 +402,9 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 // words into the columns.  The reduction takes strip bits in ascending
 // order, so the pivot at strip bit b is pivot t(b) = popcount(pivmask below
 // b), and its reduced word is P'_b = XOR of the original words of the pivots
-// in L_t(b).  Strip bit b = 4w + r is DPP row r of wave w: each of its 16
-// lanes XORs the original words of two pivots of L_t(b), a row XOR scan
+// whose strip bits are in L_t(b).  Strip bit b = 4w + r is DPP row r of wave
+// w: each of its 16 lanes XORs the original words of the pivots of two strip
+// bits of L_t(b), a row XOR scan
 // leaves P'_b in the row's last lane, and wave w, which then holds the four
 // strip bits of nibble table w, writes that table (entry e = XOR of the P'_b
 // selected by the bits of e) and keeps its P'_b in S.pp.  After a barrier
@@ -421,9 +422,12 @@ __device__ void make_tables(LDS uint64_t* const* cols, int nc, LDS uint64_t* new
   }
   const uint32_t pm = R.pivmask;
   const int w = tid >> 6, b = 4 * w + (lane >> 4), sub = lane & 15;
+  // L is indexed by strip bits: bit q names the pivot of strip bit q
   const uint32_t Lm = ((pm >> b) & 1) ? R.L[__popc(pm & ((1u << b) - 1u))] : 0u;
-  const bool u0 = (Lm >> (2 * sub)) & 1, u1 = (Lm >> (2 * sub + 1)) & 1;
-  const int r0 = u0 ? R.rows[2 * sub] : 0, r1 = u1 ? R.rows[2 * sub + 1] : 0;
+  const int q0 = 2 * sub, q1 = 2 * sub + 1;
+  const bool u0 = (Lm >> q0) & 1, u1 = (Lm >> q1) & 1;
+  const int r0 = u0 ? R.rows[__popc(pm & ((1u << q0) - 1u))] : 0;
+  const int r1 = u1 ? R.rows[__popc(pm & ((1u << q1) - 1u))] : 0;
   for (int j = 0; j < nc; ++j) {
     const LDS uint64_t* c = cols[j];
     const uint64_t x0 = c[r0], x1 = c[r1];
