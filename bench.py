@@ -446,8 +446,8 @@ def main():
         out["pauli"] = bench_pauli(zx, max(3, args.steps // 4))
         log("pauli: %s" % out["pauli"])
     # serving runs before the batched and learned legs: measured after the
-    # learned leg in the same process, its latency was several times higher
-    # (cause not found; a pause or an emptied allocator cache did not help)
+    # learned leg in the same process, its median latency was higher in every
+    # run (cause not found; a pause or an emptied allocator cache did not help)
     if args.only in ("all", "serve"):
         out["serve"] = bench_serve(zx, args, pool)
         log("serve: %s" % out["serve"])
