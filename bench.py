@@ -385,7 +385,7 @@ def main():
     if args.rref_strips:
         os.environ["ZX_RREF_PROFILE"] = "1"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the GF(2) "
+        print("bench.py measures one GPU: this library has no multi-GPU path (the GF(2) "
               "elimination would shard rows across GPUs with a per-strip pivot broadcast; "
               "see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

@@ -183,7 +183,7 @@ int or_pivot(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
  * Fixed point of the two rules (appendix, stabilizer decompositions: the
  * reduction stops when no interior pi/2 spider and no adjacent pair of
  * interior pi spiders remains).  The paper does not fix an order, so the
- * schedule is the canonical one of this build, in rounds:
+ * schedule is the canonical one of this library, in rounds:
  *
  *  LC rounds: scan spiders in ascending id; a spider joins the round if it
  *    is an LC candidate (interior, k in {2, 6}) and is not adjacent to a
