@@ -773,13 +773,24 @@ __device__ bool wait_slot(uint32_t idx, int G, const Args& a, LDS Smem& S) {
   return S.flag != 0;
 }
 
+// The column residue workgroup g owns: it holds word columns res, res + G,
+// ...  Workgroups are dispatched to the eight XCDs in turn (workgroup g on
+// XCD g mod 8), so consecutive residues go to workgroups of one XCD, G / 8 at
+// a time: the owner of the next word column, which takes over the strip
+// chain, then mostly sits on the same XCD.
+__device__ __forceinline__ int col_residue(int g, int G) {
+  if (G % 8 != 0) return g;
+  const int per = G / 8;
+  return (g % 8) * per + g / 8;
+}
+
 __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   extern __shared__ __align__(16) uint64_t smem[];
   const int tid = threadIdx.x;
-  const int g = blockIdx.x, G = gridDim.x;
+  const int g = blockIdx.x, G = gridDim.x, res = col_residue(g, G);
   const int m = a.m;
   const int nsl = (m + BS - 1) / BS;
-  const int nown = (a.nw - g + G - 1) / G;  // word columns owned: g, g+G, ...
+  const int nown = (a.nw - res + G - 1) / G;  // word columns owned: res, res+G, ...
   const int ms = nsl * BS;                  // column stride: rows padded with zeros
   const int pw = ms / 64;
   // the pass tables first, at a fixed LDS address (immediate offsets)
@@ -790,7 +801,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   LDS uint64_t* newpiv = pivflag + pw;                           // [pw]
 
   for (int j = 0; j < nown; ++j) {
-    const int c = g + j * G;
+    const int c = res + j * G;
     if (c < a.nw_a) {
       const int tail = a.n_cols - 64 * c;
       const uint64_t cm = tail >= 64 ? ~0ull : ((1ull << tail) - 1);
@@ -826,8 +837,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   int pend_ack = -1;
   for (int t = 0; t < a.nstrips && rank < m && ok; ++t) {
     const int wc = t >> 1, shift = SW * (t & 1);
-    const int owner = wc % G;
-    if (owner == g) {
+    if (wc % G == res) {
       // ---------------- produce strip t ----------------
       const int js = wc / G;
       LDS uint64_t* col = cols + (size_t)js * ms;
@@ -976,7 +986,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
       // ---------------- consume strip t ----------------
       // my next strip follows directly when t is the high half of the word
       // column just before one of mine
-      const bool own_next = (t + 1 < a.nstrips) && (((t + 1) >> 1) % G) == g && ((t + 1) & 1) == 0;
+      const bool own_next = (t + 1 < a.nstrips) && (((t + 1) >> 1) % G) == res && ((t + 1) & 1) == 0;
       for (;;) {
         const int slot = seq % RING;
         const PassRec* rec = a.recs + slot;
@@ -1017,8 +1027,8 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
           // owned word columns after wc
           LDS uint64_t* list[MAX_CW];
           int nc = 0, fuse = -1;
-          for (int j = (wc - g) >= 0 ? (wc - g) / G + 1 : 0; j < nown; ++j) {
-            if (fused && g + j * G == ((t + 1) >> 1)) fuse = nc;
+          for (int j = (wc - res) >= 0 ? (wc - res) / G + 1 : 0; j < nown; ++j) {
+            if (fused && res + j * G == ((t + 1) >> 1)) fuse = nc;
             list[nc++] = cols + (size_t)j * ms;
           }
           if (nc > 0) {
@@ -1097,7 +1107,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
   // T: rows in pivot order, then the rows that are no pivot, ascending (their
   // transform rows span the left null space); piv_base[w] = non-pivot rows in
   // flag words before w
-  const bool has_t = a.T && nown > 0 && g + (nown - 1) * G >= a.nw_a;
+  const bool has_t = a.T && nown > 0 && res + (nown - 1) * G >= a.nw_a;
   if (has_t) {
     if (tid == 0) {
       int acc = 0;
@@ -1111,7 +1121,7 @@ __global__ __launch_bounds__(BS) void rref_kernel(Args a) {
     __syncthreads();
   }
   for (int j = 0; j < nown; ++j) {
-    const int c = g + j * G;
+    const int c = res + j * G;
     const LDS uint64_t* col = cols + (size_t)j * ms;
     if (c < a.nw_a) {
       for (int i = tid; i < m; i += BS) {
