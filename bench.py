@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # (KiB, already scaled by the copy-kernel calibration), valid only for the
 # gf2.hip source they were measured on (sha256 prefix); see profiles/.
 RREF_TRAFFIC = {
-    "57f0d1d3bebf2964": {"fetch_kib": 25727.4, "write_kib": 11388.3},
+    "33a1b390f0dd9346": {"fetch_kib": 25724.2, "write_kib": 11388.3},
 }
 METRIC = "GF(2) elim GB/s (% HBM peak); diagrams simplified/sec batched vs plain, bit-exact"
 
