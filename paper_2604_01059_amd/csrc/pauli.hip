@@ -80,18 +80,25 @@ __global__ __launch_bounds__(BS) void pauli_kernel(const uint64_t* __restrict__ 
       if (!one_chunk && active) load_j(X, Z, j, n, ldq, q0, nq, xj, zj);
       __syncthreads();
       if (!active) continue;
-      for (int r = 0; r < 64; ++r) {
-        uint32_t acc = 0;
+      // the 64 parities go into two 32-bit halves, one shift-or each
+      uint32_t ph[2] = {0u, 0u};
 #pragma unroll
-        for (int w = 0; w < QCH; ++w) {
-          const uint64_t xi = xi_s[r][w], zi = zi_s[r][w];
-          acc = xor_and(acc, (uint32_t)xi, zj[2 * w]);
-          acc = xor_and(acc, (uint32_t)zi, xj[2 * w]);
-          acc = xor_and(acc, (uint32_t)(xi >> 32), zj[2 * w + 1]);
-          acc = xor_and(acc, (uint32_t)(zi >> 32), xj[2 * w + 1]);
+      for (int h = 0; h < 2; ++h) {
+        for (int rr = 0; rr < 32; ++rr) {
+          const int r = 32 * h + rr;
+          uint32_t acc = 0;
+#pragma unroll
+          for (int w = 0; w < QCH; ++w) {
+            const uint64_t xi = xi_s[r][w], zi = zi_s[r][w];
+            acc = xor_and(acc, (uint32_t)xi, zj[2 * w]);
+            acc = xor_and(acc, (uint32_t)zi, xj[2 * w]);
+            acc = xor_and(acc, (uint32_t)(xi >> 32), zj[2 * w + 1]);
+            acc = xor_and(acc, (uint32_t)(zi >> 32), xj[2 * w + 1]);
+          }
+          ph[h] |= (__popc(acc) & 1u) << rr;
         }
-        pbits ^= (uint64_t)(__popc(acc) & 1) << r;
       }
+      pbits ^= ((uint64_t)ph[1] << 32) | ph[0];
     }
     if (!active) continue;
     // mirrored tile: row j, word it
