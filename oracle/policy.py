@@ -107,7 +107,8 @@ def replay(g: Graph, trace) -> Graph:
 
 def round_is_valid(before: Graph, entries, pivot: bool) -> bool:
     """One round of a schedule: LC spiders pairwise non-adjacent and maximal
-    among the candidates; pivot pairs disjoint, mutually non-adjacent."""
+    among the candidates; pivot pairs disjoint, mutually non-adjacent, and
+    maximal among the candidate edges."""
     if not pivot:
         sel = [u for u, _ in entries]
         for i, a in enumerate(sel):
@@ -125,4 +126,14 @@ def round_is_valid(before: Graph, entries, pivot: bool) -> bool:
             if w in (u, v) or before.edge(u, w) or before.edge(v, w):
                 return False
         ends += [u, v]
+    # maximal: every candidate edge left out shares an end with, or is
+    # adjacent to, an end already taken
+    P = pauli_candidates(before)
+    taken = set((min(u, v), max(u, v)) for u, v in entries)
+    for i, u in enumerate(P):
+        for v in P[i + 1:]:
+            if not before.edge(u, v) or (u, v) in taken:
+                continue
+            if not any(w in (u, v) or before.edge(u, w) or before.edge(v, w) for w in ends):
+                return False
     return True
