@@ -27,7 +27,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no vector intrinsics)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -56,6 +56,9 @@ def lib():
         _lib.or_frontier.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, P, C.POINTER(i32), C.POINTER(i64)]
         _lib.or_pauli_commute.argtypes = [i64, C.c_int, P, P, i64, i64, i64, P, i64]
         _lib.or_pauli_commute.restype = None
+        _lib.or_gf2_matmul.argtypes = [i64, i64, C.c_int, P, i64, P, i64, P, i64]
+        _lib.or_gf2_matmul.restype = None
+        _lib.or_detector_sample.argtypes = [C.c_int, C.c_int, P, P, P, C.c_uint64, i64, i64, P, i64]
     return _lib
 
 
@@ -189,4 +192,29 @@ def pauli_commute(X: np.ndarray, Z: np.ndarray, rows=None, n_paulis: int | None 
     ldc = words_for(n)
     out = np.zeros((i1 - i0, ldc), np.uint64)
     lib().or_pauli_commute(n, w, _p(X), _p(Z), w, i0, i1, _p(out), ldc)
+    return out
+
+
+def gf2_matmul(U: np.ndarray, F: np.ndarray, k_bits: int):
+    """C[k][l] = parity of the first k_bits bits of U[k] & F[l] (m x ceil(n/64) words)."""
+    U = np.ascontiguousarray(U, dtype=np.uint64)
+    F = np.ascontiguousarray(F, dtype=np.uint64)
+    m, n = U.shape[0], F.shape[0]
+    ldc = max(1, words_for(n))
+    out = np.zeros((m, ldc), np.uint64)
+    lib().or_gf2_matmul(m, n, int(k_bits), _p(U), U.shape[1], _p(F), F.shape[1], _p(out), ldc)
+    return out
+
+
+def detector_sample(col_ptr, col_idx, prob, n_f: int, seed: int, shot0: int, n_shots: int):
+    """Shots shot0 .. shot0 + n_shots - 1 of f = T e (rows of ceil(n_f/64) words)."""
+    col_ptr = np.ascontiguousarray(col_ptr, np.int32)
+    col_idx = np.ascontiguousarray(col_idx, np.int32)
+    prob = np.ascontiguousarray(prob, np.float64)
+    ldf = max(1, words_for(n_f))
+    out = np.zeros((n_shots, ldf), np.uint64)
+    rc = lib().or_detector_sample(len(prob), n_f, _p(col_ptr), _p(col_idx), _p(prob), int(seed) & (2**64 - 1),
+                                  int(shot0), int(n_shots), _p(out), ldf)
+    if rc != OK:
+        raise ValueError("detector_sample failed %d" % rc)
     return out

@@ -23,6 +23,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -386,4 +387,98 @@ void or_pauli_commute(int64_t n_paulis, int n_words, const uint64_t* X,
       if (parity) crow[j / 64] |= (uint64_t)1 << (j % 64);
     }
   }
+}
+
+/* ------------------------------------------------ batched parities -- */
+/*
+ * Parities of many parameter subsets for many parameter settings at once
+ * (appendix "Parameterized evaluation of Clifford ZX diagrams", equation
+ * parities: a_k = XOR_i u_ki f_i, batched over settings l).  Row k of U
+ * selects the parameters of parity k, row l of F is setting l, and
+ *   C[k][l] = (sum_i U[k][i] F[l][i]) mod 2
+ * for rows k = 0..m-1 and settings l = 0..n-1, over the first k_bits bits.
+ */
+void or_gf2_matmul(int64_t m, int64_t n, int k_bits, const uint64_t* U, int64_t ldu,
+                   const uint64_t* F, int64_t ldf, uint64_t* C, int64_t ldc) {
+  for (int64_t k = 0; k < m; ++k) {
+    uint64_t* crow = C + (size_t)k * ldc;
+    memset(crow, 0, sizeof(uint64_t) * (size_t)ldc);
+    for (int64_t l = 0; l < n; ++l) {
+      int parity = 0;
+      for (int i = 0; i < k_bits; ++i)
+        parity ^= bit_get(U + (size_t)k * ldu, i) & bit_get(F + (size_t)l * ldf, i);
+      if (parity) crow[l / 64] |= (uint64_t)1 << (l % 64);
+    }
+  }
+}
+
+/* ------------------------------------------------- detector sampling -- */
+/*
+ * Shots of the detector/observable bits f = T e mod 2 (section on the
+ * repetition-code example, equation detector_sampling; paragraph on
+ * sampling detectors, equation dets-only and the text after it).  Column j
+ * of T lists the f bits that error mechanism j flips (col_ptr / col_idx);
+ * mechanism j fires independently with probability prob[j].
+ *
+ * As the paper describes (following Stim), firing mechanisms are found by
+ * sampling the gap to the next one from a geometric distribution instead of
+ * testing every mechanism.  Probabilities that differ per mechanism are
+ * handled by thinning: gaps are drawn for the largest probability pmax, and
+ * a mechanism so reached fires with probability prob[j] / pmax.
+ *
+ * Random numbers: SplitMix64 (Steele, Lea, Flood 2014), counter based.  The
+ * t-th draw of shot s is mix64(seed + (s * 2^32 + t + 1) * GAMMA).  Per
+ * candidate: one draw u for the gap, G = floor(ln(U) / ln(1 - pmax)) with
+ * U = ((u >> 11) + 1) 2^-53 in (0, 1] (no gap draw when pmax = 1: G = 0);
+ * then one draw v for the thinning: the mechanism fires iff
+ * (v >> 11) < floor(prob[j] / pmax * 2^53).
+ * Output: row s - shot0 of F holds the n_f bits of shot s.
+ */
+static uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+static uint64_t sm_draw(uint64_t seed, uint64_t t) {
+  return sm_mix(seed + (t + 1) * 0x9E3779B97F4A7C15ull);
+}
+
+int or_detector_sample(int n_err, int n_f, const int32_t* col_ptr, const int32_t* col_idx,
+                       const double* prob, uint64_t seed, int64_t shot0, int64_t n_shots,
+                       uint64_t* F, int64_t ldf) {
+  double pmax = 0.0;
+  for (int j = 0; j < n_err; ++j) {
+    if (!(prob[j] >= 0.0 && prob[j] <= 1.0)) return OR_EINVAL;
+    if (prob[j] > pmax) pmax = prob[j];
+  }
+  const double two53 = 9007199254740992.0;
+  const double log1m = log(1.0 - pmax);  /* -inf when pmax = 1 */
+  for (int64_t i = 0; i < n_shots; ++i) {
+    uint64_t* row = F + (size_t)i * ldf;
+    memset(row, 0, sizeof(uint64_t) * (size_t)ldf);
+    if (pmax == 0.0) continue;
+    const uint64_t base = (uint64_t)(shot0 + i) << 32;
+    uint64_t t = 0;
+    int64_t pos = 0;
+    for (;;) {
+      int64_t gap = 0;
+      if (pmax < 1.0) {
+        const double U = (double)((sm_draw(seed, base + t++) >> 11) + 1) / two53;
+        const double g = floor(log(U) / log1m);
+        if (g >= (double)(n_err - pos)) break;
+        gap = (int64_t)g;
+      }
+      pos += gap;
+      if (pos >= n_err) break;
+      const uint64_t thr = (uint64_t)(prob[pos] / pmax * two53);
+      if ((sm_draw(seed, base + t++) >> 11) < thr)
+        for (int q = col_ptr[pos]; q < col_ptr[pos + 1]; ++q) {
+          const int b = col_idx[q];
+          row[b / 64] ^= (uint64_t)1 << (b % 64);
+        }
+      pos += 1;
+    }
+  }
+  (void)n_f;
+  return OR_OK;
 }

@@ -38,6 +38,8 @@ P_PAULI = 4
 P_ARRIVAL = 5
 P_WEIGHTS = 6
 P_SERVE = 7
+P_PARITY = 8
+P_DEM = 9
 
 
 @dataclass
@@ -223,3 +225,106 @@ def serve_params(seed: int, item: int, q_lo: int = 8, q_hi: int = 512, m_lo: int
 def serve_diagram(seed: int, item: int, **kw) -> Diagram:
     q, n, p = serve_params(seed, item, **kw)
     return make_diagram(seed, item, q, n, p)
+
+
+@dataclass
+class ParityProblem:
+    """Inputs of the batched phase-pair evaluation: term selectors U, V
+    (n_terms x n_params bits), parameter settings F (n_settings x n_params
+    bits, one row per setting) and the terms' phase codes (multiples of pi/4)."""
+
+    n_params: int
+    U: np.ndarray
+    V: np.ndarray
+    F: np.ndarray
+    k_alpha: np.ndarray
+    k_beta: np.ndarray
+
+
+def _bits(seed: int, purpose_item: int, rows: int, cols: int, p: float) -> np.ndarray:
+    """rows x ceil(cols/64) words of Bernoulli(p) bits (bit = draw < p 2^53)."""
+    s = stream_seed(seed, purpose_item, P_PARITY)
+    w = words_for(cols)
+    out = np.zeros((rows, w), np.uint64)
+    thr = bernoulli_threshold(p)
+    step = max(1, (1 << 22) // max(1, cols))
+    for r0 in range(0, rows, step):
+        r1 = min(rows, r0 + step)
+        t = (np.arange(r0, r1, dtype=np.uint64)[:, None] * np.uint64(cols)
+             + np.arange(cols, dtype=np.uint64)[None, :])
+        b = ((draw(s, t) >> np.uint64(11)) < thr).astype(np.uint8)
+        out[r0:r1] = pack_rows(b)
+    return out
+
+
+def parity_problem(seed: int, n_terms: int, n_settings: int, n_params: int,
+                   p_select: float = 1.0 / 16, p_setting: float = 0.5) -> ParityProblem:
+    """Selectors Bernoulli(p_select) (a parity touches n_params * p_select
+    parameters on average), settings Bernoulli(p_setting), phase codes
+    uniform in 0..7."""
+    U = _bits(seed, 0, n_terms, n_params, p_select)
+    V = _bits(seed, 1, n_terms, n_params, p_select)
+    F = _bits(seed, 2, n_settings, n_params, p_setting)
+    s = stream_seed(seed, 3, P_PARITY)
+    h = draw(s, np.arange(2 * n_terms, dtype=np.uint64))
+    ka = (h[:n_terms] & np.uint64(7)).astype(np.int8)
+    kb = (h[n_terms:] & np.uint64(7)).astype(np.int8)
+    return ParityProblem(n_params, U, V, F, ka, kb)
+
+
+@dataclass
+class DetectorModel:
+    """Binary matrix T of the sampling step (f = T e): column j lists the f
+    bits (detectors, then the observable) flipped by error mechanism j,
+    CSC arrays; prob[j] is the mechanism's firing probability."""
+
+    n_f: int
+    n_det: int
+    col_ptr: np.ndarray  # int32 [n_err + 1]
+    col_idx: np.ndarray  # int32 [nnz]
+    prob: np.ndarray     # float64 [n_err]
+
+    @property
+    def n_err(self) -> int:
+        return len(self.prob)
+
+
+def surface_dem(seed: int, d: int, rounds: int, p: float = 1e-3) -> DetectorModel:
+    """Detector error model shaped like a distance-d rotated surface code
+    memory experiment with ``rounds`` rounds: checks on an a x b grid,
+    a = (d+1)/2, b = d-1 (a b = (d^2-1)/2 checks), detectors for rounds
+    0..rounds (the last from the final data readout), one observable.
+    Mechanisms per round r, in this order: horizontal neighbour pairs,
+    vertical neighbour pairs, single checks on the two boundary columns
+    (those on column 0 also flip the observable), then, for r < rounds,
+    time-like pairs (check c in rounds r and r + 1) and diagonal pairs
+    ((x, y, r), (x + 1, y + 1, r + 1)).  prob = p * U[0.5, 1.5] each."""
+    a, b = (d + 1) // 2, d - 1
+    K = a * b
+    n_det = K * (rounds + 1)
+    obs = n_det
+    det = lambda x, y, r: r * K + x * b + y
+    cols = []
+    for r in range(rounds + 1):
+        for x in range(a):
+            for y in range(b - 1):
+                cols.append([det(x, y, r), det(x, y + 1, r)])
+        for x in range(a - 1):
+            for y in range(b):
+                cols.append([det(x, y, r), det(x + 1, y, r)])
+        for x in range(a):
+            cols.append([det(x, 0, r), obs])
+            cols.append([det(x, b - 1, r)])
+        if r < rounds:
+            for c in range(K):
+                cols.append([r * K + c, (r + 1) * K + c])
+            for x in range(a - 1):
+                for y in range(b - 1):
+                    cols.append([det(x, y, r), det(x + 1, y + 1, r + 1)])
+    col_ptr = np.zeros(len(cols) + 1, np.int32)
+    col_ptr[1:] = np.cumsum([len(c) for c in cols])
+    col_idx = np.array([i for c in cols for i in c], np.int32)
+    s = stream_seed(seed, d * 1000 + rounds, P_DEM)
+    u = unit(draw(s, np.arange(len(cols), dtype=np.uint64)))
+    prob = p * (0.5 + u)
+    return DetectorModel(n_det + 1, n_det, col_ptr, col_idx, prob.astype(np.float64))
