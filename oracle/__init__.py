@@ -37,6 +37,11 @@ class Scalar(C.Structure):
                 ("fill_in", C.c_int64)]
 
 
+class Params(C.Structure):
+    _fields_ = [("pw", C.c_int), ("rows", C.c_void_p), ("term_k", C.c_void_p), ("term_u", C.c_void_p),
+                ("term_v", C.c_void_p), ("cap", C.c_int32), ("n_terms", C.c_int32)]
+
+
 _lib = None
 
 
@@ -46,12 +51,14 @@ def lib():
         _lib = C.CDLL(build())
         P = C.c_void_p
         i32, i64 = C.c_int32, C.c_int64
-        _lib.or_local_comp.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, C.POINTER(Scalar)]
-        _lib.or_pivot.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, C.c_int, C.POINTER(Scalar)]
+        PP = C.POINTER(Params)
+        _lib.or_local_comp.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, C.POINTER(Scalar), PP]
+        _lib.or_pivot.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, C.c_int, C.POINTER(Scalar),
+                                  PP]
         _lib.or_simplify.argtypes = [C.c_int, C.c_int, P, P, P, P, C.POINTER(Scalar), P, C.c_int,
                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
         _lib.or_simplify_rounds.argtypes = [C.c_int, C.c_int, P, P, P, P, C.POINTER(Scalar), P, C.c_int,
-                                            C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
+                                            C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int, PP]
         _lib.or_gf2_rref.argtypes = [C.c_int, C.c_int, i64, P, P, C.POINTER(i32), C.POINTER(i64), P, i64]
         _lib.or_frontier.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, P, C.POINTER(i32), C.POINTER(i64)]
         _lib.or_pauli_commute.argtypes = [i64, C.c_int, P, P, i64, i64, i64, P, i64]
@@ -73,7 +80,10 @@ def words_for(n: int) -> int:
 class Graph:
     """Mutable graph-like diagram state held by the oracle (host numpy arrays)."""
 
-    def __init__(self, n, adj, phase, inputs=(), outputs=(), bnd_is_h=None):
+    def __init__(self, n, adj, phase, inputs=(), outputs=(), bnd_is_h=None, params=None):
+        """params: optional n x pw uint64 parameter rows (spider v's phase is
+        k_v pi/4 + (params[v] . f) pi); terms recorded by rewrites are kept
+        in term_k (m x 2: k_alpha, k_beta), term_u, term_v (m x pw)."""
         self.n = int(n)
         self.W = words_for(self.n)
         self.adj = np.ascontiguousarray(np.array(adj, dtype=np.uint64).reshape(self.n, self.W))
@@ -91,6 +101,33 @@ class Graph:
         self.scalar = Scalar(0, 0, 0, 0)
         self.trace = np.zeros((0, 4), np.int32)
         self.rounds = 0
+        if params is None:
+            self.pw = 0
+            self.params = np.zeros((self.n, 0), np.uint64)
+        else:
+            self.params = np.ascontiguousarray(np.array(params, dtype=np.uint64).reshape(self.n, -1))
+            self.pw = self.params.shape[1]
+        cap = self.n + 1
+        self.term_k = np.zeros((cap, 2), np.int32)
+        self.term_u = np.zeros((cap, max(self.pw, 1)), np.uint64)
+        self.term_v = np.zeros((cap, max(self.pw, 1)), np.uint64)
+        self.n_terms = 0
+
+    def _par(self):
+        if self.pw == 0:
+            return None
+        self._pstruct = Params(self.pw, self.params.ctypes.data, self.term_k.ctypes.data, self.term_u.ctypes.data,
+                               self.term_v.ctypes.data, self.term_k.shape[0], self.n_terms)
+        return C.byref(self._pstruct)
+
+    def _par_done(self):
+        if self.pw:
+            self.n_terms = self._pstruct.n_terms
+
+    def terms(self):
+        """(k (m x 2), u (m x pw), v (m x pw)) of the terms recorded so far."""
+        m = self.n_terms
+        return self.term_k[:m].copy(), self.term_u[:m, : self.pw].copy(), self.term_v[:m, : self.pw].copy()
 
     @classmethod
     def from_diagram(cls, d):
@@ -104,6 +141,9 @@ class Graph:
         g.alive, g.bnd = self.alive.copy(), self.bnd.copy()
         g.scalar = Scalar(self.scalar.pow_sqrt2, self.scalar.phase8, 0, self.scalar.fill_in)
         g.trace, g.rounds = self.trace.copy(), self.rounds
+        g.pw, g.params = self.pw, self.params.copy()
+        g.term_k, g.term_u, g.term_v = self.term_k.copy(), self.term_u.copy(), self.term_v.copy()
+        g.n_terms = self.n_terms
         return g
 
     # -- queries --------------------------------------------------------
@@ -128,12 +168,18 @@ class Graph:
 
     # -- rules ------------------------------------------------------------
     def local_comp(self, u, graph_only=False) -> int:
-        return lib().or_local_comp(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive),
-                                   _p(self.bnd), int(u), int(graph_only), C.byref(self.scalar))
+        par = self._par()
+        rc = lib().or_local_comp(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive),
+                                 _p(self.bnd), int(u), int(graph_only), C.byref(self.scalar), par)
+        self._par_done()
+        return rc
 
     def pivot(self, u, v, graph_only=False) -> int:
-        return lib().or_pivot(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive),
-                              _p(self.bnd), int(u), int(v), int(graph_only), C.byref(self.scalar))
+        par = self._par()
+        rc = lib().or_pivot(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive),
+                            _p(self.bnd), int(u), int(v), int(graph_only), C.byref(self.scalar), par)
+        self._par_done()
+        return rc
 
     def simplify(self, max_rounds: int = 0) -> int:
         """Canonical greedy schedule to the fixed point, or for max_rounds
@@ -142,9 +188,11 @@ class Graph:
         cap = 2 * self.n + 2
         tr = np.zeros((cap, 4), np.int32)
         nt, nr = C.c_int(0), C.c_int(0)
+        par = self._par()
         rc = lib().or_simplify_rounds(self.n, self.W, _p(self.adj), _p(self.k), _p(self.alive), _p(self.bnd),
                                       C.byref(self.scalar), _p(tr), cap, C.byref(nt), C.byref(nr),
-                                      int(max_rounds))
+                                      int(max_rounds), par)
+        self._par_done()
         self.trace = tr[: nt.value].copy()
         self.rounds = nr.value
         return rc

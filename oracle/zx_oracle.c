@@ -36,6 +36,48 @@ typedef struct {
   int64_t fill_in;    /* Hadamard edges toggled on by rewrites */
 } or_scalar;
 
+/*
+ * Parameterized Pauli spiders (the paper's Pauli boxes: a spider whose phase
+ * carries an extra a*pi with a a parity of binary parameters; section on ZX
+ * representation, and appendix "Rewrite rules", where the rules take phases
+ * pi/2 + b*pi and a*pi with binary a, b).  Spider v's phase is
+ *   k_v pi/4 + (p_v . f) pi,
+ * p_v a row of pw 64-bit words over the parameters f.  A rewrite whose
+ * scalar depends on the parameters records a phase-pair term
+ * (k_alpha, k_beta, u, v): the factor h(k_alpha pi/4, k_beta pi/4; u.f, v.f)
+ * of the parameterized evaluation appendix (equation phase_pair), so that
+ * the diagram equals  omega^phase8 sqrt(2)^pow_sqrt2 prod_terms h * rest.
+ */
+typedef struct {
+  int pw;            /* words per parameter row; 0 = no parameters */
+  uint64_t* rows;    /* n x pw */
+  int32_t* term_k;   /* cap x 2: k_alpha, k_beta */
+  uint64_t* term_u;  /* cap x pw */
+  uint64_t* term_v;  /* cap x pw */
+  int32_t cap, n_terms;
+} or_params;
+
+static int prow_zero(const or_params* par, int v) {
+  for (int q = 0; q < par->pw; ++q)
+    if (par->rows[(size_t)v * par->pw + q]) return 0;
+  return 1;
+}
+/* p_dst ^= p_src */
+static void prow_xor(or_params* par, int dst, int src) {
+  for (int q = 0; q < par->pw; ++q) par->rows[(size_t)dst * par->pw + q] ^= par->rows[(size_t)src * par->pw + q];
+}
+static int add_term(or_params* par, int ka, int kb, int su, int sv) {
+  if (par->n_terms >= par->cap) return OR_EINVAL;
+  const int t = par->n_terms++;
+  par->term_k[2 * t] = ka;
+  par->term_k[2 * t + 1] = kb;
+  for (int q = 0; q < par->pw; ++q) {
+    par->term_u[(size_t)t * par->pw + q] = su >= 0 ? par->rows[(size_t)su * par->pw + q] : 0;
+    par->term_v[(size_t)t * par->pw + q] = sv >= 0 ? par->rows[(size_t)sv * par->pw + q] : 0;
+  }
+  return OR_OK;
+}
+
 /* ---------------------------------------------------------------- bits -- */
 
 static int bit_get(const uint64_t* row, int c) {
@@ -99,7 +141,7 @@ static void delete_spider(uint64_t* adj, int n, int W, int8_t* k, uint64_t* aliv
  * phases and scalar untouched.
  */
 int or_local_comp(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
-                  const uint64_t* bnd, int u, int graph_only, or_scalar* sc) {
+                  const uint64_t* bnd, int u, int graph_only, or_scalar* sc, or_params* par) {
   if (u < 0 || u >= n) return OR_EINVAL;
   if (!bit_get(alive, u)) return OR_ENOMATCH;
   if (!graph_only && (!is_interior(alive, bnd, u) || (k[u] != 2 && k[u] != 6)))
@@ -115,9 +157,25 @@ int or_local_comp(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
   if (!graph_only) {
     int bpar = (k[u] - 2) / 4; /* b of the rule: 0 for pi/2, 1 for 3pi/2 */
     for (int a = 0; a < deg; ++a) k[nb[a]] = (int8_t)mod8(k[nb[a]] - k[u]);
-    sc->phase8 = mod8(sc->phase8 + 1 - 2 * bpar);
+    const int has_par = par && par->pw && !prow_zero(par, u);
+    if (!has_par) {
+      sc->phase8 = mod8(sc->phase8 + 1 - 2 * bpar);
+    } else {
+      /* u's phase is pi/2 + (bpar + p_u.f) pi: neighbours lose p_u.f pi too
+       * (-x pi = x pi mod 2 pi), and the factor e^{-i b pi/2} with
+       * b = bpar XOR (p_u.f) becomes a term: for bpar = 0 it is
+       * h(pi, pi/2; p_u.f, 0) / (2i), for bpar = 1 it is
+       * -i h(0, pi/2; p_u.f, 0) / 2 (h(pi, pi/2; a, 0) = 2i e^{-i a pi/2},
+       * h(0, pi/2; a, 0) = 2 e^{i a pi/2}); both constants are
+       * omega^{-2} / 2, so with e^{i pi/4}: phase8 - 1, pow_sqrt2 - 2. */
+      for (int a = 0; a < deg; ++a) prow_xor(par, nb[a], u);
+      if (add_term(par, bpar ? 0 : 4, 2, u, -1) != OR_OK) { free(nb); return OR_EINVAL; }
+      sc->phase8 = mod8(sc->phase8 - 1);
+      sc->pow_sqrt2 -= 2;
+    }
     sc->pow_sqrt2 += (int64_t)(deg - 1) * (deg - 2) / 2 - 2 * toggled_off;
     sc->fill_in += pairs - toggled_off;
+    if (par && par->pw) for (int q = 0; q < par->pw; ++q) par->rows[(size_t)u * par->pw + q] = 0;
     delete_spider(adj, n, W, k, alive, u);
   }
   free(nb);
@@ -139,7 +197,7 @@ int or_local_comp(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
  * graph_only: only the tripartite toggle; u, v, phases and scalar are kept.
  */
 int or_pivot(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
-             const uint64_t* bnd, int u, int v, int graph_only, or_scalar* sc) {
+             const uint64_t* bnd, int u, int v, int graph_only, or_scalar* sc, or_params* par) {
   if (u < 0 || u >= n || v < 0 || v >= n || u == v) return OR_EINVAL;
   if (!bit_get(alive, u) || !bit_get(alive, v) || !is_edge(adj, W, u, v)) return OR_ENOMATCH;
   if (!graph_only) {
@@ -169,9 +227,23 @@ int or_pivot(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
     for (int i = 0; i < na; ++i) k[A[i]] = (int8_t)mod8(k[A[i]] + 4 * b);
     for (int j = 0; j < nc; ++j) k[C[j]] = (int8_t)mod8(k[C[j]] + 4 * a);
     for (int i = 0; i < nbb; ++i) k[B[i]] = (int8_t)mod8(k[B[i]] + 4 * a + 4 * b + 4);
-    sc->phase8 = mod8(sc->phase8 + 4 * a * b);
+    const int has_par = par && par->pw && (!prow_zero(par, u) || !prow_zero(par, v));
+    if (!has_par) {
+      sc->phase8 = mod8(sc->phase8 + 4 * a * b);
+    } else {
+      /* u = (a + p_u.f) pi, v = (b + p_v.f) pi: A gains p_v, C gains p_u,
+       * B gains both; the factor (-1)^{(a + p_u.f)(b + p_v.f)} is the term
+       * h(a pi, b pi; p_u.f, p_v.f) / 2 (h(0, 0; x, y) = 2 (-1)^{xy}). */
+      for (int i = 0; i < na; ++i) prow_xor(par, A[i], v);
+      for (int j = 0; j < nc; ++j) prow_xor(par, C[j], u);
+      for (int i = 0; i < nbb; ++i) { prow_xor(par, B[i], u); prow_xor(par, B[i], v); }
+      if (add_term(par, 4 * a, 4 * b, u, v) != OR_OK) { free(A); free(B); free(C); return OR_EINVAL; }
+      sc->pow_sqrt2 -= 2;
+    }
     sc->pow_sqrt2 += (int64_t)(na - 1) * (nc - 1) + (int64_t)nbb * (na + nc - 2) - 2 * toggled_off;
     sc->fill_in += pairs - toggled_off;
+    if (par && par->pw)
+      for (int q = 0; q < par->pw; ++q) par->rows[(size_t)u * par->pw + q] = par->rows[(size_t)v * par->pw + q] = 0;
     delete_spider(adj, n, W, k, alive, u);
     delete_spider(adj, n, W, k, alive, v);
   }
@@ -212,7 +284,7 @@ static int pauli_candidate(const uint64_t* alive, const uint64_t* bnd, const int
  * used to reach the intermediate states of a greedy run. */
 int or_simplify_rounds(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
                        const uint64_t* bnd, or_scalar* sc, or_trace* trace, int trace_cap,
-                       int* n_trace, int* n_rounds, int max_rounds) {
+                       int* n_trace, int* n_rounds, int max_rounds, or_params* par) {
   int* sel = (int*)malloc(sizeof(int) * (size_t)(2 * n + 2));
   int nt = 0, round = 0;
   /* LC rounds */
@@ -228,7 +300,7 @@ int or_simplify_rounds(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
     }
     if (ns == 0) break;
     for (int i = 0; i < ns; ++i) {
-      int rc = or_local_comp(n, W, adj, k, alive, bnd, sel[i], 0, sc);
+      int rc = or_local_comp(n, W, adj, k, alive, bnd, sel[i], 0, sc, par);
       if (rc != OR_OK) { free(sel); return rc; }
       if (nt < trace_cap) { trace[nt].round = round; trace[nt].rule = 0; trace[nt].u = sel[i]; trace[nt].v = -1; }
       nt++;
@@ -253,7 +325,7 @@ int or_simplify_rounds(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
     }
     if (np == 0) break;
     for (int i = 0; i < np; ++i) {
-      int rc = or_pivot(n, W, adj, k, alive, bnd, sel[2 * i], sel[2 * i + 1], 0, sc);
+      int rc = or_pivot(n, W, adj, k, alive, bnd, sel[2 * i], sel[2 * i + 1], 0, sc, par);
       if (rc != OR_OK) { free(sel); return rc; }
       if (nt < trace_cap) { trace[nt].round = round; trace[nt].rule = 1; trace[nt].u = sel[2 * i]; trace[nt].v = sel[2 * i + 1]; }
       nt++;
@@ -269,7 +341,7 @@ int or_simplify_rounds(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
 int or_simplify(int n, int W, uint64_t* adj, int8_t* k, uint64_t* alive,
                 const uint64_t* bnd, or_scalar* sc, or_trace* trace, int trace_cap,
                 int* n_trace, int* n_rounds) {
-  return or_simplify_rounds(n, W, adj, k, alive, bnd, sc, trace, trace_cap, n_trace, n_rounds, 0);
+  return or_simplify_rounds(n, W, adj, k, alive, bnd, sc, trace, trace_cap, n_trace, n_rounds, 0, NULL);
 }
 
 /* ----------------------------------------------------- GF(2) elimination -- */
