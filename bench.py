@@ -122,53 +122,332 @@ def bench_rref(zx, args):
                 last_strip=last_strip, m=m, n=n, timeline=timeline)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads the all-core baselines use: this process's CPU share (at most 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline_rref(res, budget_s):
+    """The oracle on the whole matrix: single-threaded, median of 3 runs; the
+    same loops with row additions over all host threads, median of 3."""
     import oracle
     A = res["A"]
-    runs, t_total = 0, 0.0
-    Ro = None
-    while t_total < budget_s or runs == 0:
+    one = []
+    Ro = pivo = ranko = None
+    for _ in range(3):
         t0 = time.perf_counter()
         Ro, pivo, ranko, ops = oracle.gf2_rref(A, res["n"])
-        t_total += time.perf_counter() - t0
-        runs += 1
-    sec = t_total / runs
+        one.append(time.perf_counter() - t0)
     exact = bool(np.array_equal(Ro, res["R"]) and ranko == res["rank"] and np.array_equal(pivo, res["piv"]))
-    return dict(value=round(res["bytes"] / sec / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
-                sample="whole 4096x16384 matrix, %d run(s), %.2f s each, plain single-threaded C "
-                       "Gauss-Jordan" % (runs, sec),
-                seconds_per_run=round(sec, 3)), exact
+    th = host_threads()
+    os.environ["OMP_NUM_THREADS"] = str(th)
+    allc = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        R2, p2, r2 = oracle.gf2_rref_threads(A, res["n"])
+        allc.append(time.perf_counter() - t0)
+    exact = exact and bool(np.array_equal(R2, res["R"]))
+    s1, sa = float(np.median(one)), float(np.median(allc))
+    return dict(value=round(res["bytes"] / s1 / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                sample="whole 4096x16384 matrix, median of 3 runs (%.2f s each), plain single-threaded C "
+                       "Gauss-Jordan" % s1,
+                seconds_per_run=round(s1, 3),
+                all_cores={"value": round(res["bytes"] / sa / 1e9, 4), "unit": "GB/s", "cores": th,
+                           "seconds_per_run": round(sa, 3),
+                           "sample": "same matrix, row additions over %d OpenMP threads, median of 3" % th},
+                cpu_model=cpu_model()), exact
 
 
-def bench_pauli(zx, steps):
+def _time_launches(fn, steps):
+    """Average ms of fn() over steps launches, HIP events on the current stream."""
     import torch
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+_PAULI = {}
+
+
+def _oracle_pauli_block(args):
+    """sha256 of rows i0..i1-1 of the oracle's table (worker process)."""
+    import hashlib
     import oracle
+    from workloads import pauli_strings
+    i0, i1 = args
+    if "XZ" not in _PAULI:
+        _PAULI["XZ"] = pauli_strings(22, 65536, 1024)
+    X, Z = _PAULI["XZ"]
+    blk = oracle.pauli_commute(X, Z, rows=(i0, i1))
+    return hashlib.sha256(np.ascontiguousarray(blk).tobytes()).hexdigest()
+
+
+def bench_pauli(zx, steps, pool):
+    import hashlib
+    import torch
     from workloads import pauli_strings
     n, q = 65536, 1024
     X, Z = pauli_strings(22, n, q)
     dX, dZ = zx.to_device_words(X), zx.to_device_words(Z)
     C = torch.empty((n, n // 64), dtype=torch.int64, device="cuda")
+    pairs = float(n) * n
+    out = {"workload": "65536 Pauli strings x 1024 qubits (seed 22), 65536^2-bit table"}
+    for name, flag in (("valu", zx.ZX_PAULI_FORCE_VALU), ("mfma", zx.ZX_PAULI_FORCE_MFMA)):
+        ms = _time_launches(lambda: zx.pauli_commute(dX, dZ, q, C_out=C, flags=flag), steps)
+        out[name] = {"ms": round(ms, 4), "pairs_per_s": pairs / (ms * 1e-3),
+                     "out_GBps": round(n * n / 8 / (ms * 1e-3) / 1e9, 2)}
+    # VALU work: 64x64 tiles on and above the diagonal, AND + XOR per qubit per term
+    tiles = (n // 64) * (n // 64 + 1) / 2
+    out["valu"]["bitop_Tops"] = round(tiles * 4096 * 2 * q * 2 / (out["valu"]["ms"] * 1e-3) / 1e12, 2)
+    # matrix cores: 256x256 tiles on and above the diagonal, K = 2q, 2 flops per product
+    t256 = (n // 256) * (n // 256 + 1) / 2
+    mflops = t256 * 256 * 256 * 2 * q * 2
+    out["mfma"]["TFLOPs"] = round(mflops / (out["mfma"]["ms"] * 1e-3) / 1e12, 1)
+    out["mfma"]["frac_of_fp4_peak"] = round(mflops / (out["mfma"]["ms"] * 1e-3) / 10.1e15, 4)
+    best = min(("valu", "mfma"), key=lambda k: out[k]["ms"])
+    out["auto_picks"] = "mfma"
+    out["faster"] = best
+    out["ms"] = out["mfma"]["ms"]
+    # the table of the variant AUTO runs, compared in full with the oracle
     zx.pauli_commute(dX, dZ, q, C_out=C)
     torch.cuda.synchronize()
+    if pool is not None:
+        blocks = [(i, min(n, i + 1024)) for i in range(0, n, 1024)]
+        t0 = time.perf_counter()
+        digests = list(pool.map(_oracle_pauli_block, blocks, chunksize=1))
+        cpu_s = time.perf_counter() - t0
+        Ch = C.cpu().numpy().view(np.uint64)
+        same = sum(hashlib.sha256(np.ascontiguousarray(Ch[i0:i1]).tobytes()).hexdigest() == d
+                   for (i0, i1), d in zip(blocks, digests))
+        out["full_exact"] = "%d/%d row blocks" % (same, len(blocks))
+        out["cpu_baseline"] = {"value": round(pairs / cpu_s, 1), "unit": "pairs/s", "cores": pool._processes,
+                               "kind": "oracle", "sample": "the whole 65536^2 table, 64 blocks of 1024 rows "
+                               "over %d worker processes (%.1f s)" % (pool._processes, cpu_s)}
+    return out
+
+
+def bench_parity(zx, steps):
+    """Batched phase-pair evaluation: parities a = U F^T, b = V F^T on the
+    matrix cores, then the phase-pair product per setting."""
+    import torch
+    import oracle
+    from oracle import phase as oph
+    from workloads import parity_problem
+    m, L, P = 4096, 65536, 1024
+    prob = parity_problem(61, m, L, P)
+    dU, dV, dF = (zx.to_device_words(x) for x in (prob.U, prob.V, prob.F))
+    ka = torch.from_numpy(prob.k_alpha).cuda()
+    kb = torch.from_numpy(prob.k_beta).cuda()
+    A = torch.empty((m, L // 64), dtype=torch.int64, device="cuda")
+    B = torch.empty_like(A)
+    mant = torch.empty((L, 2), dtype=torch.float32, device="cuda")
+    expo = torch.empty(L, dtype=torch.int32, device="cuda")
+    ms_mm = _time_launches(lambda: zx.gf2_matmul(dU, dF, P, C_out=A), steps)
+    zx.gf2_matmul(dV, dF, P, C_out=B)
+    ms_pp = _time_launches(lambda: zx.phase_pair_product(A, B, ka, kb, L, 3, -5, mant=mant, expo=expo), steps)
+    torch.cuda.synchronize()
+    flops = 2.0 * m * L * P
+    Ah = zx.to_host_words(A)
+    rows = (0, 1, 2047, 4095)
+    rows_ok = all(np.array_equal(Ah[r:r + 1], oracle.gf2_matmul(prob.U[r:r + 1], prob.F, P)) for r in rows)
+    # product on 64 settings, against the fp64 oracle (its tolerance: tests)
+    S = 64
+    Bh = zx.to_host_words(B)
+    t0 = time.perf_counter()
+    Ao = oracle.gf2_matmul(prob.U, prob.F[:S], P)
+    Bo = oracle.gf2_matmul(prob.V, prob.F[:S], P)
+    mo, eo = oph.phase_pair_product(Ao, Bo, prob.k_alpha, prob.k_beta, S, 3, -5)
+    cpu_s = time.perf_counter() - t0
+    mg, eg = mant.cpu().numpy()[:S], expo.cpu().numpy()[:S]
+    zg = mg[:, 0].astype(np.float64) + 1j * mg[:, 1]
+    errs = [abs(zg[l] * 2.0 ** float(int(eg[l]) - int(eo[l])) - mo[l]) / abs(mo[l]) for l in range(S) if mo[l] != 0]
+    rel = max(errs) if errs else 0.0
+    zeros_agree = all((mo[l] == 0) == (zg[l] == 0) for l in range(S))
+    total = 2 * ms_mm + ms_pp
+    return {"workload": "4096 terms x 65536 settings x 1024 parameters (seed 61): a = U F^T, b = V F^T, "
+                        "then prod_k h(alpha_k, beta_k; a_k, b_k)",
+            "ms_matmul": round(ms_mm, 4), "ms_product": round(ms_pp, 4), "ms_total": round(total, 4),
+            "settings_per_s": round(L / (total * 1e-3), 1),
+            "matmul_TFLOPs": round(flops / (ms_mm * 1e-3) / 1e12, 1),
+            "matmul_frac_of_fp4_peak": round(flops / (ms_mm * 1e-3) / 10.1e15, 4),
+            "parity_rows_exact": rows_ok, "a_b_bits_equal_oracle_on_64_settings":
+                bool(np.array_equal(Ah[:, :1], Ao[:, :1]) and np.array_equal(Bh[:, :1], Bo[:, :1])),
+            "product_max_rel_err_64_settings": float(rel), "product_zeros_agree": zeros_agree,
+            "product_rel_tolerance": (21 * m + 4) * 2.0 ** -24,
+            "cpu_baseline": {"value": round(S / cpu_s, 2), "unit": "settings/s", "cores": 1, "kind": "oracle",
+                             "sample": "parities of all 4096 terms (two products) and the fp64 product for "
+                                       "64 settings, %.1f s" % cpu_s}}
+
+
+def bench_sample(zx, steps):
+    """Detector sampling f = T e, surface-code-shaped model d = 7, 7 rounds."""
+    import torch
+    import oracle
+    from workloads import surface_dem
+    M = surface_dem(7, 7, 7, 1e-3)
+    S = zx.DetectorSampler(M.col_ptr, M.col_idx, M.prob, M.n_f)
+    shots = 1 << 24
+    fw = (M.n_f + 63) // 64
+    out = torch.empty((shots, fw), dtype=torch.int64, device="cuda")
+    ms = _time_launches(lambda: S.sample(2024, 0, shots, out=out), steps)
+    assert S.status() == 0
+    n_chk = 100000
+    got = zx.to_host_words(out[:n_chk])
+    ref = oracle.detector_sample(M.col_ptr, M.col_idx, M.prob, M.n_f, 2024, 0, n_chk)
+    tail0 = shots - 20000
+    got_t = zx.to_host_words(out[tail0:])
+    t0 = time.perf_counter()
+    ref_t = oracle.detector_sample(M.col_ptr, M.col_idx, M.prob, M.n_f, 2024, tail0, 20000)
+    cpu_s = time.perf_counter() - t0
+    written = shots * fw * 8
+    gbs = written / (ms * 1e-3) / 1e9
+    return {"workload": "detector error model shaped like a d=7 surface-code memory experiment, 7 rounds "
+                        "(%d detectors + 1 observable, %d mechanisms, p ~ 1e-3 U[0.5,1.5]); %d shots per "
+                        "launch" % (M.n_det, M.n_err, shots),
+            "ms": round(ms, 4), "shots_per_s": round(shots / (ms * 1e-3), 1),
+            "out_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "exact_first_100k": bool(np.array_equal(got, ref)),
+            "exact_last_20k": bool(np.array_equal(got_t, ref_t)),
+            "cpu_baseline": {"value": round(20000 / cpu_s, 1), "unit": "shots/s", "cores": 1, "kind": "oracle",
+                             "sample": "20000 shots (the last of the launch), %.2f s" % cpu_s}}
+
+
+def _oracle_param_diag(args):
+    import oracle
+    from workloads import batch_diagram, param_rows
+    i, P = args
+    d = batch_diagram(3, i)
+    g = oracle.Graph(d.n, d.adj, d.phase, d.inputs, d.outputs, d.bnd_is_h, params=param_rows(3, i, d.n, P))
+    g.simplify()
+    tk, tu, tv = g.terms()
+    import hashlib
+    hsh = hashlib.sha256()
+    for a in (g.adj, g.k, g.params, tk, tu, tv):
+        hsh.update(np.ascontiguousarray(a).tobytes())
+    hsh.update(np.array([g.scalar.pow_sqrt2, g.scalar.phase8 % 8], np.int64).tobytes())
+    return hsh.hexdigest()
+
+
+def bench_params(zx, pool):
+    """Batched simplification of the 4096 batched-workload diagrams with
+    parameterized Pauli spiders (1024 parameters), against the same batch
+    without parameters; bit-exact against the oracle."""
+    import hashlib
+    import torch
+    from workloads import batch_diagram, param_rows
+    P = 1024
+    ds = list(pool.map(_gen_diag, range(4096), chunksize=32)) if pool is not None else \
+        [_gen_diag(i) for i in range(4096)]
+    prs = [param_rows(3, i, d.n, P) for i, d in enumerate(ds)]
+    gs = [zx.Graph.create(d.adj, d.phase, d.inputs, d.outputs, d.bnd_is_h, n_params=P, params=pr)
+          for d, pr in zip(ds, prs)]
+    plain = [zx.Graph.from_diagram(d) for d in ds]
+    res = {}
+    for name, graphs in (("with_params", gs), ("without_params", plain)):
+        b = zx.Batch(graphs)
+        ms = _time_launches(lambda: b.run(extract=True), 3)
+        assert b.status() == 0
+        res[name + "_ms"] = round(ms, 3)
+    out = {"workload": "4096 diagrams of the batched workload (seed 3), ~30% of spiders carrying 2 of "
+                       "1024 parameters", **res,
+           "diagrams_per_s": round(4096 / (res["with_params_ms"] * 1e-3), 1)}
+    if pool is not None:
+        t0 = time.perf_counter()
+        digests = list(pool.map(_oracle_param_diag, [(i, P) for i in range(4096)], chunksize=16))
+        cpu_s = time.perf_counter() - t0
+        same = 0
+        for g, dg in zip(gs, digests):
+            adj, ph, al, info = g.read()
+            rows, kab, u, v = g.params()
+            hsh = hashlib.sha256()
+            for a in (adj, ph, rows, kab, u, v):
+                hsh.update(np.ascontiguousarray(a).tobytes())
+            hsh.update(np.array([info.pow_sqrt2, info.phase8], np.int64).tobytes())
+            same += hsh.hexdigest() == dg
+        out["bit_exact_vs_oracle"] = "%d/4096" % same
+        out["cpu_baseline"] = {"value": round(4096 / cpu_s, 1), "unit": "diagrams/s", "cores": pool._processes,
+                               "kind": "oracle", "sample": "all 4096 diagrams, one per worker process"}
+    return out
+
+
+def _oracle_c1(seed):
+    import oracle
+    from workloads import single_diagram
+    d = single_diagram(seed)
+    t0 = time.perf_counter()
+    g = oracle.Graph.from_diagram(d)
+    g.simplify()
+    M, piv, rank, ops = g.frontier()
+    dt = time.perf_counter() - t0
+    return dt, (g.adj.tobytes(), g.k.tobytes(), int(g.scalar.pow_sqrt2), int(g.scalar.phase8 % 8), M.tobytes(),
+                int(rank), int(ops))
+
+
+def bench_c1(zx):
+    """One diagram (8 qubits, 64 spiders, p = 0.1), seeds 1..1000: latency of
+    one launch per diagram, kernel only (HIP events) and end to end (host
+    clock around launch and result read), against the oracle on one core."""
+    import torch
+    from workloads import single_diagram
+    ds = [single_diagram(s) for s in range(1, 1001)]
+    gs = [zx.Graph.from_diagram(d) for d in ds]
+    bs = [zx.Batch([g]) for g in gs]
+    for b in bs[:20]:
+        b.run(extract=True)
+    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    kern, e2e = [], []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        zx.pauli_commute(dX, dZ, q, C_out=C)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    rows = [0, 777, 32768, 65535]
-    Ch = C[rows].cpu().numpy().view(np.uint64)
-    ok = all(np.array_equal(Ch[i], oracle.pauli_commute(X, Z, rows=(r, r + 1))[0]) for i, r in enumerate(rows))
-    pairs = float(n) * n
-    # VALU work: the kernel computes the 64x64 tiles on and above the diagonal
-    tiles = (n // 64) * (n // 64 + 1) / 2
-    bitops = tiles * 4096 * 2 * q * 2  # AND + XOR per qubit per term, per computed pair
-    return dict(ms=round(ms, 4), pairs_per_s=pairs / (ms * 1e-3), out_GBps=round(n * n / 8 / (ms * 1e-3) / 1e9, 2),
-                bitop_Tops=round(bitops / (ms * 1e-3) / 1e12, 2), sampled_rows_exact=ok,
-                workload="65536 Pauli strings x 1024 qubits (seed 22), 65536^2-bit table")
+    for g, b in zip(gs, bs):
+        t0 = time.perf_counter()
+        e0.record(stream)
+        b.run(extract=True)
+        e1.record(stream)
+        info = g.info()  # synchronises
+        e2e.append(time.perf_counter() - t0)
+        kern.append(e0.elapsed_time(e1) * 1e-3)
+        assert info.status == 0
+    exact = 0
+    cpu = []
+    for s, g in zip(range(1, 1001), gs):
+        dt, ref = _oracle_c1(s)
+        cpu.append(dt)
+        adj, ph, al, info = g.read()
+        M, piv = g.frontier()
+        got = (adj.tobytes(), ph.tobytes(), int(info.pow_sqrt2), int(info.phase8), M.tobytes(), int(info.rank),
+               int(info.rowops))
+        exact += got == ref
+    us = lambda a, q: round(float(np.percentile(np.array(a), q)) * 1e6, 2)
+    return {"workload": "one diagram per launch: 8 qubits, 64 spiders, ER p=0.1, seeds 1..1000; simplify + "
+                        "8x64 frontier RREF",
+            "kernel_us_p50": us(kern, 50), "kernel_us_p99": us(kern, 99),
+            "end_to_end_us_p50": us(e2e, 50), "end_to_end_us_p99": us(e2e, 99),
+            "bit_exact_vs_oracle": "%d/1000" % exact,
+            "cpu_baseline": {"value": us(cpu, 50), "unit": "us per diagram (p50)", "p99": us(cpu, 99), "cores": 1,
+                             "kind": "oracle", "sample": "the same 1000 diagrams, one at a time"}}
 
 
 def _gen_diag(i):
@@ -370,7 +649,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy"])
+    ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy",
+                                                      "parity", "sample", "params", "c1"])
     ap.add_argument("--learned-states", type=int, default=20000)
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -390,7 +670,7 @@ def main():
               "see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     pool = None
-    if args.only in ("all", "batched", "learned", "serve"):
+    if args.only in ("all", "batched", "learned", "serve", "pauli", "params"):
         # worker processes (generation, oracle checks) are forked before any
         # GPU call, so they never inherit an initialised device
         import multiprocessing as mp
@@ -443,8 +723,17 @@ def main():
         out["bit_exact_rref_vs_oracle"] = exact
         log("cpu baseline: %s GB/s (%s)" % (cb["value"], cb["sample"]))
     if args.only in ("all", "pauli"):
-        out["pauli"] = bench_pauli(zx, max(3, args.steps // 4))
+        out["pauli"] = bench_pauli(zx, max(3, args.steps // 4), pool)
         log("pauli: %s" % out["pauli"])
+    if args.only in ("all", "parity"):
+        out["parity"] = bench_parity(zx, max(3, args.steps // 4))
+        log("parity: %s" % out["parity"])
+    if args.only in ("all", "sample"):
+        out["sample"] = bench_sample(zx, max(3, args.steps // 4))
+        log("sample: %s" % out["sample"])
+    if args.only in ("all", "c1"):
+        out["c1"] = bench_c1(zx)
+        log("c1: %s" % out["c1"])
     # serving runs before the batched and learned legs: measured after the
     # learned leg in the same process, its median latency was higher in every
     # run (cause not found; a pause or an emptied allocator cache did not help)
@@ -454,6 +743,9 @@ def main():
     if args.only in ("all", "batched"):
         out["batched"] = bench_batched(zx, args, pool)
         log("batched: %s" % out["batched"])
+    if args.only in ("all", "params"):
+        out["params"] = bench_params(zx, pool)
+        log("params: %s" % out["params"])
     if args.only in ("all", "learned"):
         out["learned"] = bench_learned(zx, args, pool)
         log("learned: %s" % out["learned"])

@@ -110,6 +110,39 @@ zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena_bytes, int
                           const int32_t* in_spider, int32_t n_in,
                           const int32_t* out_spider, int32_t n_out,
                           const uint8_t* bnd_is_hadamard, hipStream_t s);
+/* Parameterized Pauli spiders (Pauli boxes).  The paper models Pauli noise
+ * as spiders whose phase carries a binary parameter times pi (section on the
+ * ZX representation; the rewrite rules of appendix "Rewrite rules" are
+ * stated for phases pi/2 + b pi and a pi with binary a, b).  Here spider v's
+ * phase is k_v pi/4 + (p_v . f) pi, p_v its parameter row: n_params bits in
+ * pw = ceil(n_params/64) words, param_rows n x pw words (host), bits at or
+ * beyond n_params zero.  n_params <= 4096.  Rewrites never look at the
+ * parameters to decide (the schedule is that of the constant phases); they
+ * update the rows (local complementation at u XORs p_u into every neighbour;
+ * a pivot u-v XORs p_v into N(u) only, p_u into N(v) only, both into common
+ * neighbours) and, when a rewrite's scalar depends on the parameters, record
+ * a phase-pair term (k_alpha, k_beta, u, v): the factor
+ * h(k_alpha pi/4, k_beta pi/4; u.f, v.f) of the parameterized evaluation
+ * appendix (equation phase_pair).  For every f the CURRENT diagram then
+ * satisfies  D_source(f) = omega^phase8 sqrt(2)^pow_sqrt2 prod_terms h * D(f).
+ * Local complementation with p_u != 0 gives (4, 2, p_u, 0) if k_u = 2,
+ * (0, 2, p_u, 0) if k_u = 6; a pivot with p_u or p_v != 0 gives
+ * (k_u, k_v, p_u, p_v).  zx_graph_bytes_ex / zx_graph_create_ex take the
+ * parameters; with n_params = 0 they equal zx_graph_bytes / zx_graph_create.
+ * Serving requests carry no parameters. */
+size_t zx_graph_bytes_ex(int32_t n, int32_t n_in, int32_t n_out, int32_t n_params);
+zx_status zx_graph_create_ex(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
+                             const uint64_t* adj_host, const int8_t* phase_host,
+                             const int32_t* in_spider, int32_t n_in,
+                             const int32_t* out_spider, int32_t n_out,
+                             const uint8_t* bnd_is_hadamard, int32_t n_params,
+                             const uint64_t* param_rows, hipStream_t s);
+/* CURRENT parameter rows (n x pw words) and the terms recorded since the
+ * SOURCE diagram (count to *n_terms; the first min(count, cap) to k_ab
+ * (2 int32 each: k_alpha, k_beta), u and v (pw words each)), in the order of
+ * the rewrites that made them.  Any output may be NULL.  Synchronises s. */
+zx_status zx_graph_read_params(const zx_graph* g, uint64_t* rows, int32_t* n_terms, int32_t* k_ab,
+                               uint64_t* u, uint64_t* v, int32_t cap, hipStream_t s);
 /* Attach a handle to an arena already initialised by zx_graph_create. */
 zx_status zx_graph_attach(zx_graph** g, void* dev_arena, size_t arena_bytes);
 void zx_graph_destroy(zx_graph* g);   /* host handle only */
@@ -246,14 +279,103 @@ zx_status zx_gf2_profile_read(const void* ws, int32_t m, int64_t* ticks, int32_t
  * Symplectic commutation table of Pauli strings
  *
  * X, Z: n_paulis x ld_q words (device); qubit b of string i is bit b of the
- * X and Z rows.  C: n_paulis x ld_c words (device, ld_c >= ceil(n/64)),
- * C[i][j] = parity of sum_b x_i[b] z_j[b] + z_i[b] x_j[b], i.e. 1 when
- * strings i and j anticommute.  Bits beyond n_paulis in a row are zero.
+ * X and Z rows (bits at or beyond n_qubits are ignored).  C: n_paulis x ld_c
+ * words (device, ld_c >= ceil(n/64)), C[i][j] = parity of
+ * sum_b x_i[b] z_j[b] + z_i[b] x_j[b], i.e. 1 when strings i and j
+ * anticommute.  Bits beyond n_paulis in a row are zero; words at or beyond
+ * ceil(n/64) are not written.
+ * Variants: ZX_PAULI_FORCE_VALU, bitwise AND/XOR on the vector units;
+ * ZX_PAULI_FORCE_MFMA, the same product on the matrix cores (bits as FP4
+ * values, exact fp32 counts, see zx_gf2_matmul).  ZX_PAULI_AUTO takes the
+ * matrix cores from 1024 strings up.  Both give identical bits.
  * ==================================================================== */
 #define ZX_PAULI_AUTO 0u
+#define ZX_PAULI_FORCE_VALU 0x1u
+#define ZX_PAULI_FORCE_MFMA 0x2u
 zx_status zx_pauli_commute(const uint64_t* X, const uint64_t* Z, int64_t n_paulis,
                            int32_t n_qubits, int64_t ld_q, uint64_t* C, int64_t ld_c,
                            uint32_t flags, hipStream_t s);
+
+/* ======================================================================
+ * Parameterized evaluation: batched parities and the phase-pair product
+ *
+ * After reduction, a diagram with parameterized Pauli spiders evaluates to
+ * c * prod_k h(alpha_k, beta_k; a_k, b_k), where a_k and b_k are parities of
+ * the binary parameters f (appendix "Parameterized evaluation of Clifford
+ * ZX diagrams", equations parities, phase_pair and scalar_product).
+ * ==================================================================== */
+/* C[i][j] = (sum_{b < k_bits} A[i][b] B[j][b]) mod 2: row i of A selects
+ * parameters (u_i), row j of B is one parameter setting (f_j), so C holds
+ * a_i for every setting j (equation parities batched over settings).
+ * A: m x lda words, B: n x ldb words, C: m x ldc words (ldc >= ceil(n/64);
+ * words at or beyond ceil(n/64) are not written), all device memory.  Bits at
+ * or beyond k_bits are ignored; bits beyond n in a row of C are zero.  Runs
+ * on the matrix cores: bits enter as FP4 values 0 and 1 and every sum is an
+ * exact fp32 count.  flags: ZX_SYNC only.  Asynchronous on s. */
+zx_status zx_gf2_matmul(const uint64_t* A, int64_t m, int64_t lda, const uint64_t* B, int64_t n,
+                        int64_t ldb, int32_t k_bits, uint64_t* C, int64_t ldc, uint32_t flags,
+                        hipStream_t s);
+/* Minimal parameter basis (section on the repetition-code example: after
+ * equation detector_sampling, a minimal set of f is chosen by Gaussian
+ * elimination over F2 of the parameter dependencies, keeping a linearly
+ * independent basis).  D: m x ld words, one dependency vector per row
+ * (n_cols bits: the parameter rows left after reduction and the terms'
+ * u and v).  R (m x ld, must not overlap D) receives RREF(D); its first
+ * *rank_dev rows are the basis T, f = T e.  coeff (m x ldc words, ldc >=
+ * ceil(min(m, n_cols)/64)) receives each vector's coordinates in that basis:
+ * bit j of row i = D[i][pivot_j] for j < rank (zero beyond), so that
+ * D = coeff . T.  ws: zx_gf2_workspace_bytes(m, n_cols) bytes.  Device
+ * memory; asynchronous on s.  m <= 16384 (zx_gf2_eliminate's limit). */
+zx_status zx_gf2_basis(const uint64_t* D, int32_t m, int32_t n_cols, int64_t ld, uint64_t* R,
+                       int32_t* rank_dev, int32_t* pivot_cols_dev, uint64_t* coeff, int64_t ldc,
+                       void* ws, size_t ws_bytes, hipStream_t s);
+/* Per setting l (0 <= l < n_settings):
+ *   omega^phase8 * sqrt(2)^pow_sqrt2 * prod_k h(k_alpha[k] pi/4, k_beta[k] pi/4; a_kl, b_kl)
+ * with h(alpha, beta; a, b) = 1 + e^{i(alpha + a pi)} + e^{i(beta + b pi)}
+ * - e^{i(alpha + beta + a pi + b pi)} (equation phase_pair) and a_kl, b_kl
+ * bit l of row k of A and of B (n_terms x ld words, ld >= ceil(n_settings/64),
+ * as written by zx_gf2_matmul).  Phases are multiples of pi/4 (integer codes,
+ * as everywhere in this library).  Output per setting: mant[2l], mant[2l+1]
+ * (real, imaginary; the larger magnitude in [0.5, 1), or both 0) and expo[l],
+ * value = mant * 2^expo.  fp32 complex products, renormalised every 8 terms.
+ * All arrays device memory.  Asynchronous on s. */
+zx_status zx_phase_pair_product(const uint64_t* A, const uint64_t* B, int64_t ld, int32_t n_terms,
+                                int64_t n_settings, const int8_t* k_alpha, const int8_t* k_beta,
+                                int32_t phase8, int64_t pow_sqrt2, float* mant, int32_t* expo,
+                                hipStream_t s);
+
+/* ======================================================================
+ * Detector sampling: f = T e mod 2
+ *
+ * Section on the repetition-code example (equation detector_sampling) and
+ * the detector paragraph after equation dets-only: column j of the binary
+ * matrix T lists the detector/observable bits that error mechanism j flips;
+ * mechanism j fires independently with probability prob[j].  As the paper
+ * describes, the firing mechanisms of a shot are found by sampling the gap
+ * to the next one from a geometric distribution (here for the largest
+ * probability pmax, each mechanism so reached then firing with probability
+ * prob[j] / pmax), so a shot costs O(pmax * n_err + 1).
+ *
+ * T as CSC: col_ptr[n_err + 1] (col_ptr[0] = 0, non-decreasing, col_ptr[n_err]
+ * = nnz), col_idx[nnz] in [0, n_f).  Random numbers: SplitMix64, draw t of
+ * shot s = mix64(seed + (s * 2^32 + t + 1) * 0x9E3779B97F4A7C15); per
+ * candidate one draw u for the gap G = floor(ln U / ln(1 - pmax)),
+ * U = ((u >> 11) + 1) * 2^-53 (none when pmax = 1), then one draw v: fires
+ * iff (v >> 11) < floor(prob[j] / pmax * 2^53), all in fp64.  Shot s
+ * depends only on (seed, s), so ranges of shots can be sampled separately.
+ * out: n_shots x ld_out words (ld_out >= ceil(n_f/64)); row i = shot
+ * shot0 + i.  n_f <= 2048, shot0 + n_shots <= 2^31.  ws: device workspace of
+ * zx_detector_workspace_bytes(n_err), 256-byte aligned.  A model that fails
+ * validation on the device (probabilities outside [0, 1], bad col_ptr or
+ * col_idx) sets the workspace status to ZX_EINVAL (zx_detector_status) and
+ * the output rows are all zero.  Device arrays; asynchronous on s.
+ * ==================================================================== */
+size_t zx_detector_workspace_bytes(int32_t n_err);
+zx_status zx_detector_sample(const int32_t* col_ptr, const int32_t* col_idx, int64_t nnz, const double* prob,
+                             int32_t n_err, int32_t n_f, uint64_t seed, int64_t shot0, int64_t n_shots,
+                             uint64_t* out, int64_t ld_out, void* ws, size_t ws_bytes, hipStream_t s);
+/* Status of the last sampling call that used ws (synchronises s). */
+zx_status zx_detector_status(const void* ws, hipStream_t s);
 
 /* ======================================================================
  * Learned rewrite proposal: scoring network, training kernels, rollouts

@@ -27,7 +27,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no vector intrinsics)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-fopenmp", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +65,7 @@ def lib():
         _lib.or_pauli_commute.restype = None
         _lib.or_gf2_matmul.argtypes = [i64, i64, C.c_int, P, i64, P, i64, P, i64]
         _lib.or_gf2_matmul.restype = None
+        _lib.or_gf2_rref_omp.argtypes = [C.c_int, C.c_int, i64, P, P, C.POINTER(i32)]
         _lib.or_detector_sample.argtypes = [C.c_int, C.c_int, P, P, P, C.c_uint64, i64, i64, P, i64]
     return _lib
 
@@ -266,3 +267,16 @@ def detector_sample(col_ptr, col_idx, prob, n_f: int, seed: int, shot0: int, n_s
     if rc != OK:
         raise ValueError("detector_sample failed %d" % rc)
     return out
+
+
+def gf2_rref_threads(A: np.ndarray, n_cols: int):
+    """The elimination with row additions spread over OpenMP threads (timing
+    only).  Returns (R, pivots, rank)."""
+    A = np.array(A, dtype=np.uint64, copy=True, order="C")
+    m, ld = A.shape
+    piv = np.zeros(max(m, 1), np.int32)
+    rank = C.c_int32(0)
+    rc = lib().or_gf2_rref_omp(m, n_cols, ld, _p(A), _p(piv), C.byref(rank))
+    if rc != OK:
+        raise ValueError("rref failed %d" % rc)
+    return A, piv[:m].copy(), rank.value

@@ -408,6 +408,42 @@ int or_gf2_rref(int m, int n_cols, int64_t ld, uint64_t* A, int32_t* piv,
   return OR_OK;
 }
 
+/*
+ * The same elimination with the row additions of each column spread over
+ * host threads (OpenMP); used only to time the oracle on all host cores.
+ * Identical results: rows are independent within one column step.
+ */
+int or_gf2_rref_omp(int m, int n_cols, int64_t ld, uint64_t* A, int32_t* piv, int32_t* rank) {
+  int nw = (n_cols + 63) / 64;
+  if (m < 0 || n_cols < 0 || ld < nw) return OR_EINVAL;
+  uint64_t* tmp = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)ld + 8);
+  int cur = 0;
+  for (int c = 0; c < n_cols && cur < m; ++c) {
+    int r = -1;
+    for (int i = cur; i < m; ++i)
+      if (bit_get(A + (size_t)i * ld, c)) { r = i; break; }
+    if (r < 0) continue;
+    if (r != cur) {
+      memcpy(tmp, A + (size_t)r * ld, sizeof(uint64_t) * (size_t)nw);
+      memcpy(A + (size_t)r * ld, A + (size_t)cur * ld, sizeof(uint64_t) * (size_t)nw);
+      memcpy(A + (size_t)cur * ld, tmp, sizeof(uint64_t) * (size_t)nw);
+    }
+    const uint64_t* prow = A + (size_t)cur * ld;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < m; ++i) {
+      if (i == cur || !bit_get(A + (size_t)i * ld, c)) continue;
+      uint64_t* row = A + (size_t)i * ld;
+      for (int w = 0; w < nw; ++w) row[w] ^= prow[w];
+    }
+    piv[cur] = c;
+    cur++;
+  }
+  for (int i = cur; i < m; ++i) piv[i] = -1;
+  *rank = cur;
+  free(tmp);
+  return OR_OK;
+}
+
 /* ---------------------------------------------------- frontier extraction -- */
 /*
  * Biadjacency between the output-attached spiders and the rest, the matrix a

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzx.so")
 ROOT = os.path.dirname(HERE)
-SOURCES = ["runtime.hip", "gf2.hip", "pauli.hip", "graph.hip", "mlp.hip", "serve.hip"]
+SOURCES = ["runtime.hip", "gf2.hip", "gf2mm.hip", "pauli.hip", "graph.hip", "mlp.hip", "serve.hip", "sample.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -37,7 +37,7 @@ def _compile(src: str, build_dir: str) -> str:
 def build(verbose: bool = True) -> str:
     build_dir = os.path.join(ROOT, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]

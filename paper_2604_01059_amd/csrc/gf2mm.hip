@@ -1,0 +1,447 @@
+// Dense products over GF(2) on the matrix cores, and the phase-pair product.
+//
+// 1. C[i][j] = (sum_k A[i][k] B[j][k]) mod 2 for bit-packed rows A_i, B_j.
+//    This is the batched parity contraction a_k = XOR_i u_ki f_i of the
+//    paper's parameterized evaluation (appendix "Parameterized evaluation of
+//    Clifford ZX diagrams", equation parities), with A = U and B = the
+//    parameter settings, and it is the symplectic commutation table of Pauli
+//    strings with A_i = [x_i | z_i], B_j = [z_j | x_j] (appendix "Pauli
+//    channels" for the encoding).  The paper contracts in floating point on
+//    BLAS; here the bits enter v_mfma_scale_f32_32x32x64_f8f6f4 as FP4
+//    (E2M1) values: a set bit is the code 0b0001 (0.5), the block scale 2^1
+//    makes it 1.0, so every product is 0 or 1 and the fp32 sums (at most the
+//    row length, far below 2^24) are exact counts; bit 0 of the count is the
+//    parity.  Unpacking a 32-bit word of bits costs seven VALU operations:
+//    nibble r of dword t of the operand holds bit 4r + t of the word, i.e.
+//    operand dword t = (word >> t) & 0x11111111.  The order in which bits
+//    reach the k positions of the instruction does not matter, since A and
+//    B fragments are unpacked the same way and the sum runs over all k.
+//
+//    Workgroup: 256 threads, a 256 x 256 output tile, each wavefront a
+//    128 x 128 quarter (4 x 4 blocks of 32 x 32, 256 fp32 accumulators per
+//    lane).  The rows' bits go through LDS in chunks of 256 bits (4 words,
+//    double buffered): 16 KiB per chunk for the 512 rows of the tile.  For
+//    each 64-bit step of a chunk, lane half h of a fragment takes dword
+//    4h + s of its row's chunk.  Parities leave through wave ballots (row
+//    words) and, for the symmetric table, through per-lane packing (the
+//    mirrored tile's row words).  Tiles are dealt to the eight XCDs in
+//    contiguous runs of the tile order, so one XCD's tiles share rows in its
+//    L2.
+//
+// 2. Per setting l: omega^phase8 sqrt(2)^pow * prod_k h(alpha_k, beta_k;
+//    a_kl, b_kl), h of equation phase_pair, phases multiples of pi/4.  One
+//    lane per setting, fp32 complex products, renormalised to a power of two
+//    every 8 factors.
+#include "zx_internal.h"
+
+namespace {
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+#define LDS __attribute__((address_space(3)))
+
+constexpr int MM_BS = 256;    // threads per workgroup
+constexpr int MM_T = 256;     // output tile edge
+constexpr int MM_CW = 4;      // words per chunk
+constexpr int SCALE_ONE = 128;  // E8M0 2^1: FP4 code 0b0001 (0.5) scaled to 1.0
+
+struct MmArgs {
+  const uint64_t* a0;  // row i of A = a0 row i (kw0 words) then a1 row i (kw1 words)
+  const uint64_t* a1;
+  const uint64_t* b0;  // row j of B = b0 row j (kw0 words) then b1 row j (kw1 words)
+  const uint64_t* b1;
+  int64_t lda, ldb;    // words per row of a0/a1 and of b0/b1
+  int64_t m, n;        // rows of A, rows of B
+  int32_t kw0, kw1;
+  uint64_t mask0, mask1;  // valid bits of the last word of each part
+  uint64_t* C;
+  int64_t ldc;
+  int64_t cw;          // words of C written per row: ceil(n / 64)
+  int32_t tm, tn;      // tiles along m and n
+  int32_t sym;         // symmetric table: tiles ti <= tj, mirror written too
+  int64_t n_tiles;
+  int64_t per_xcd;     // tiles per XCD run
+};
+
+__device__ __forceinline__ uint64_t row_word(const uint64_t* p0, const uint64_t* p1, int64_t ld, int64_t r,
+                                             int64_t nrows, int w, int kw0, int kw1, uint64_t m0,
+                                             uint64_t m1) {
+  if (r >= nrows) return 0;
+  if (w < kw0) {
+    const uint64_t v = p0[r * ld + w];
+    return w == kw0 - 1 ? v & m0 : v;
+  }
+  w -= kw0;
+  if (w < kw1) {
+    const uint64_t v = p1[r * ld + w];
+    return w == kw1 - 1 ? v & m1 : v;
+  }
+  return 0;
+}
+
+__device__ __forceinline__ v8i unpack_fp4(uint32_t d) {
+  v8i o;
+  o[0] = (int)(d & 0x11111111u);
+  o[1] = (int)((d >> 1) & 0x11111111u);
+  o[2] = (int)((d >> 2) & 0x11111111u);
+  o[3] = (int)((d >> 3) & 0x11111111u);
+  o[4] = 0;
+  o[5] = 0;
+  o[6] = 0;
+  o[7] = 0;
+  return o;
+}
+
+// tile t of the grid order -> (ti, tj)
+__device__ __forceinline__ void tile_of(const MmArgs& a, int64_t t, int& ti, int& tj) {
+  if (!a.sym) {
+    ti = (int)(t / a.tn);
+    tj = (int)(t % a.tn);
+    return;
+  }
+  // upper triangle, row by row: row i holds tn - i tiles
+  int i = 0;
+  int64_t start = 0;
+  while (start + (a.tn - i) <= t) {
+    start += a.tn - i;
+    ++i;
+  }
+  ti = i;
+  tj = i + (int)(t - start);
+}
+
+__global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
+  // two chunk buffers: [buf][row 0..255 A, 256..511 B][4 words]
+  __shared__ __attribute__((aligned(16))) uint64_t sbuf[2][2 * MM_T][MM_CW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+  if (t >= a.n_tiles) return;
+  int ti, tj;
+  tile_of(a, t, ti, tj);
+  const int64_t m0 = (int64_t)ti * MM_T, n0 = (int64_t)tj * MM_T;
+  const int kw = a.kw0 + a.kw1;
+  const int nch = (kw + MM_CW - 1) / MM_CW;
+
+  // staging: thread tid fetches A row m0 + tid and B row n0 + tid
+  uint64_t ra[MM_CW], rb[MM_CW];
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int w = 0; w < MM_CW; ++w) {
+      ra[w] = row_word(a.a0, a.a1, a.lda, m0 + tid, a.m, c * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);
+      rb[w] = row_word(a.b0, a.b1, a.ldb, n0 + tid, a.n, c * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int w = 0; w < MM_CW; ++w) {
+      sbuf[buf][tid][w] = ra[w];
+      sbuf[buf][MM_T + tid][w] = rb[w];
+    }
+  };
+
+  v16f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  const int wr = (wv >> 1) * 128, wc = (wv & 1) * 128;  // this wave's quarter
+  const int h = lane >> 5, l32 = lane & 31;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) fetch(c + 1);
+    // this lane's fragments: 16 bytes (dwords 4h .. 4h+3) of each row's chunk
+    uint32_t fa[4][4], fb[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t* pa = (const uint32_t*)&sbuf[buf][wr + 32 * i + l32][2 * h];
+      const uint32_t* pb = (const uint32_t*)&sbuf[buf][MM_T + wc + 32 * i + l32][2 * h];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        fa[i][d] = pa[d];
+        fb[i][d] = pb[d];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      v8i oa[4], ob[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        oa[i] = unpack_fp4(fa[i][s]);
+        ob[i] = unpack_fp4(fb[i][s]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(oa[i], ob[j], acc[i][j], 4, 4, 0,
+                                                                       SCALE_ONE, 0, SCALE_ONE);
+    }
+    if (c + 1 < nch) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- parities out.  Accumulator r of block (i, j) in lane (h, l32) is
+  // row 32 i + 8 (r / 4) + 4 h + (r % 4), column 32 j + l32 of the quarter.
+  LDS uint32_t* rows = (LDS uint32_t*)&sbuf[0][0][0] + wv * (128 * 4);  // [128 rows][4 dwords]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t bit = (uint32_t)(int)acc[i][j][r] & 1u;
+        const uint64_t bal = __ballot(bit);
+        const int row = 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (l32 == 0) rows[row * 4 + j] = (uint32_t)(bal >> (32 * h));
+      }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  // row words: lane -> rows lane, lane + 64 of the quarter, two words each
+  const int64_t cword = (n0 + wc) / 64;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int row = lane + 64 * p;
+    const int64_t gi = m0 + wr + row;
+    if (gi < a.m) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int64_t wcol = cword + q;
+        if (wcol < a.cw) {
+          const uint64_t v = (uint64_t)rows[row * 4 + 2 * q] | ((uint64_t)rows[row * 4 + 2 * q + 1] << 32);
+          a.C[gi * a.ldc + wcol] = v;
+        }
+      }
+    }
+  }
+  if (!a.sym || ti == tj) return;
+  // mirrored tile: row (column 32 j + l32 of the quarter), words over the
+  // quarter's rows; this lane holds rows 32 i + 8 q + 4 h + s (r = 4 q + s)
+  const int64_t rword = (m0 + wr) / 64;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint64_t w0 = 0, w1 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint64_t bit = (uint64_t)((uint32_t)(int)acc[i][j][r] & 1u);
+        const int pos = 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (pos < 64)
+          w0 |= bit << pos;
+        else
+          w1 |= bit << (pos - 64);
+      }
+    w0 |= (uint64_t)__shfl_xor((long long)w0, 32);
+    w1 |= (uint64_t)__shfl_xor((long long)w1, 32);
+    const int64_t gj = n0 + wc + 32 * j + l32;
+    const int64_t wcol = rword + h;
+    if (gj < a.n && wcol < a.cw) a.C[gj * a.ldc + wcol] = h ? w1 : w0;
+  }
+}
+
+// ------------------------------------------------------ phase-pair product --
+
+constexpr int PP_BS = 256;
+constexpr int PP_CHUNK = 256;   // terms whose h tables sit in LDS at a time
+constexpr float RH = 0.70710678118654752440f;
+
+// cos(k pi/4): exact 0 and +-1 where they occur
+__device__ __forceinline__ float cos_q(int k) {
+  k &= 7;
+  const float mag = (k & 1) ? RH : ((k & 2) ? 0.0f : 1.0f);
+  return (k >= 3 && k <= 5) ? -mag : mag;
+}
+
+// e^{i k pi/4} = (cos(k pi/4), sin(k pi/4)), sin(x) = cos(x - pi/2)
+__device__ __forceinline__ float2 omega_pow(int k) { return make_float2(cos_q(k), cos_q(k + 6)); }
+
+__device__ __forceinline__ float2 cmul(float2 x, float2 y) {
+  return make_float2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
+
+// scale z by a power of two so that max(|re|, |im|) is in [0.5, 1)
+__device__ __forceinline__ void renorm(float2& z, int& e) {
+  const float mx = fmaxf(fabsf(z.x), fabsf(z.y));
+  if (mx == 0.0f) return;
+  const int ex = __builtin_amdgcn_frexp_expf(mx);
+  z.x = ldexpf(z.x, -ex);
+  z.y = ldexpf(z.y, -ex);
+  e += ex;
+}
+
+__global__ __launch_bounds__(PP_BS) void phase_pair_kernel(const uint64_t* __restrict__ A,
+                                                           const uint64_t* __restrict__ B, int64_t ld,
+                                                           int32_t m, int64_t n_set,
+                                                           const int8_t* __restrict__ ka,
+                                                           const int8_t* __restrict__ kb, int32_t phase8,
+                                                           int64_t pow_sqrt2, float2* __restrict__ mant,
+                                                           int32_t* __restrict__ expo) {
+  __shared__ float2 tab[PP_CHUNK][4];  // h(k; a, b) at index a + 2 b
+  const int64_t l = (int64_t)blockIdx.x * PP_BS + threadIdx.x;
+  // uniform over the wave: the term words are scalar loads
+  const int64_t wcol = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * PP_BS + (threadIdx.x & ~63)) >> 6));
+  const int bitpos = (int)(l & 63);
+  // c = omega^phase8 sqrt(2)^pow
+  const bool odd = (pow_sqrt2 & 1) != 0;
+  int e = (int)((pow_sqrt2 - (odd ? 1 : 0)) / 2);
+  float2 z = omega_pow(phase8);
+  if (odd) {
+    z.x *= 1.41421356237309504880f;
+    z.y *= 1.41421356237309504880f;
+  }
+  renorm(z, e);
+  for (int k0 = 0; k0 < m; k0 += PP_CHUNK) {
+    const int nk = m - k0 < PP_CHUNK ? m - k0 : PP_CHUNK;
+    __syncthreads();
+    for (int x = threadIdx.x; x < nk * 4; x += PP_BS) {
+      const int k = x >> 2, ab = x & 3, av = ab & 1, bv = ab >> 1;
+      const int ak = ka[k0 + k], bk = kb[k0 + k];
+      const float2 p = omega_pow(ak + 4 * av), q = omega_pow(bk + 4 * bv), r = omega_pow(ak + bk + 4 * av + 4 * bv);
+      tab[k][ab] = make_float2(1.0f + p.x + q.x - r.x, p.y + q.y - r.y);
+    }
+    __syncthreads();
+    if (l < n_set) {
+      for (int k = 0; k < nk; ++k) {
+        const uint64_t aw = A[(int64_t)(k0 + k) * ld + wcol];
+        const uint64_t bw = B[(int64_t)(k0 + k) * ld + wcol];
+        const int idx = (int)((aw >> bitpos) & 1) + 2 * (int)((bw >> bitpos) & 1);
+        z = cmul(z, tab[k][idx]);
+        if ((k & 7) == 7) renorm(z, e);
+      }
+      renorm(z, e);
+    }
+  }
+  if (l < n_set) {
+    if (z.x == 0.0f && z.y == 0.0f) e = 0;
+    mant[l] = z;
+    expo[l] = e;
+  }
+}
+
+// coeff[i] bit j = D[i][piv[j]] for j < rank (zero beyond), words < cwords
+__global__ void basis_coeff_kernel(const uint64_t* __restrict__ D, int32_t m, int64_t ld,
+                                   const int32_t* __restrict__ rank_dev, const int32_t* __restrict__ piv,
+                                   uint64_t* __restrict__ coeff, int64_t ldc, int32_t cwords) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= (int64_t)m * cwords) return;
+  const int i = (int)(it / cwords), jw = (int)(it - (int64_t)i * cwords);
+  const int rank = *rank_dev;
+  uint64_t w = 0;
+  for (int b = 0; b < 64; ++b) {
+    const int j = 64 * jw + b;
+    if (j >= rank) break;
+    const int c = piv[j];
+    w |= ((D[(int64_t)i * ld + (c >> 6)] >> (c & 63)) & 1ull) << b;
+  }
+  coeff[(int64_t)i * ldc + jw] = w;
+}
+
+zx_status launch_gf2mm(MmArgs a, hipStream_t s) {
+  a.tm = (int32_t)((a.m + MM_T - 1) / MM_T);
+  a.tn = (int32_t)((a.n + MM_T - 1) / MM_T);
+  a.n_tiles = a.sym ? (int64_t)a.tn * (a.tn + 1) / 2 : (int64_t)a.tm * a.tn;
+  a.per_xcd = (a.n_tiles + 7) / 8;
+  const int64_t blocks = 8 * a.per_xcd;
+  if (blocks > 0x7fffffff) {
+    zx_set_error("product of %lld x %lld rows has too many tiles", (long long)a.m, (long long)a.n);
+    return ZX_ECAPACITY;
+  }
+  hipLaunchKernelGGL(gf2mm_kernel, dim3((unsigned)blocks), dim3(MM_BS), 0, s, a);
+  ZX_HIP(hipGetLastError());
+  return ZX_OK;
+}
+
+}  // namespace
+
+// Symmetric commutation table on the matrix cores (called by zx_pauli_commute).
+zx_status zx_pauli_commute_mfma(const uint64_t* X, const uint64_t* Z, int64_t n, int32_t n_qubits, int64_t ldq,
+                                uint64_t* C, int64_t ldc, hipStream_t s) {
+  MmArgs a{};
+  const int qw = (n_qubits + 63) / 64;
+  a.a0 = X;
+  a.a1 = Z;
+  a.b0 = Z;
+  a.b1 = X;
+  a.lda = a.ldb = ldq;
+  a.m = a.n = n;
+  a.kw0 = a.kw1 = qw;
+  a.mask0 = a.mask1 = (n_qubits % 64) ? ((1ull << (n_qubits % 64)) - 1) : ~0ull;
+  a.C = C;
+  a.ldc = ldc;
+  a.cw = (n + 63) / 64;
+  a.sym = 1;
+  return launch_gf2mm(a, s);
+}
+
+extern "C" zx_status zx_gf2_matmul(const uint64_t* A, int64_t m, int64_t lda, const uint64_t* B, int64_t n,
+                                   int64_t ldb, int32_t k_bits, uint64_t* C, int64_t ldc, uint32_t flags,
+                                   hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(A && B && C, "null argument");
+  ZX_CHECK_ARG(m > 0 && n > 0 && k_bits > 0, "empty product: m=%lld n=%lld k_bits=%d", (long long)m,
+               (long long)n, k_bits);
+  const int kw = (k_bits + 63) / 64;
+  ZX_CHECK_ARG(lda >= kw && ldb >= kw, "lda/ldb below %d words", kw);
+  ZX_CHECK_ARG(ldc >= (n + 63) / 64, "ldc below %lld words", (long long)((n + 63) / 64));
+  MmArgs a{};
+  a.a0 = A;
+  a.b0 = B;
+  a.lda = lda;
+  a.ldb = ldb;
+  a.m = m;
+  a.n = n;
+  a.kw0 = kw;
+  a.kw1 = 0;
+  a.mask0 = (k_bits % 64) ? ((1ull << (k_bits % 64)) - 1) : ~0ull;
+  a.mask1 = ~0ull;
+  a.C = C;
+  a.ldc = ldc;
+  a.cw = (n + 63) / 64;
+  a.sym = 0;
+  zx_status rc = launch_gf2mm(a, s);
+  if (rc == ZX_OK && (flags & ZX_SYNC)) ZX_HIP(hipStreamSynchronize(s));
+  return rc;
+}
+
+extern "C" zx_status zx_phase_pair_product(const uint64_t* A, const uint64_t* B, int64_t ld, int32_t n_terms,
+                                           int64_t n_settings, const int8_t* k_alpha, const int8_t* k_beta,
+                                           int32_t phase8, int64_t pow_sqrt2, float* mant, int32_t* expo,
+                                           hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(mant && expo, "null output");
+  ZX_CHECK_ARG(n_terms >= 0 && n_settings > 0, "bad sizes: n_terms=%d n_settings=%lld", n_terms,
+               (long long)n_settings);
+  ZX_CHECK_ARG(n_terms == 0 || (A && B && k_alpha && k_beta), "null term input");
+  ZX_CHECK_ARG(n_terms == 0 || ld >= (n_settings + 63) / 64, "ld below %lld words",
+               (long long)((n_settings + 63) / 64));
+  const int64_t blocks = (n_settings + PP_BS - 1) / PP_BS;
+  ZX_CHECK_ARG(blocks <= 0x7fffffff, "too many settings");
+  hipLaunchKernelGGL(phase_pair_kernel, dim3((unsigned)blocks), dim3(PP_BS), 0, s, A, B, ld, n_terms,
+                     n_settings, k_alpha, k_beta, phase8 & 7, pow_sqrt2, (float2*)mant, expo);
+  ZX_HIP(hipGetLastError());
+  return ZX_OK;
+}
+
+extern "C" zx_status zx_gf2_basis(const uint64_t* D, int32_t m, int32_t n_cols, int64_t ld, uint64_t* R,
+                                  int32_t* rank_dev, int32_t* pivot_cols_dev, uint64_t* coeff, int64_t ldc,
+                                  void* ws, size_t ws_bytes, hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(D && R && coeff && D != R, "null argument or D == R");
+  ZX_CHECK_ARG(m > 0 && n_cols > 0, "empty matrix");
+  const int cwords = ((m < n_cols ? m : n_cols) + 63) / 64;
+  ZX_CHECK_ARG(ldc >= cwords, "ldc %lld < %d", (long long)ldc, cwords);
+  zx_status rc = zx_gf2_eliminate(D, R, m, n_cols, ld, rank_dev, pivot_cols_dev, nullptr, 0, ws, ws_bytes, s);
+  if (rc != ZX_OK) return rc;
+  const int64_t total = (int64_t)m * cwords;
+  hipLaunchKernelGGL(basis_coeff_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, D, m, ld,
+                     rank_dev, pivot_cols_dev, coeff, ldc, cwords);
+  ZX_HIP(hipGetLastError());
+  return ZX_OK;
+}

@@ -72,6 +72,8 @@ struct Shared {
   int32_t nsw;         // words of the selected set (list in Ctx::blocked)
   int32_t ns;          // selected spiders (list in Ctx::slist)
   int64_t rowops;
+  int32_t n_terms;     // phase-pair terms recorded (parameterized spiders)
+  int32_t pad_terms;
 };
 
 // LDS pointers are typed as such so that the compiler emits ds_* accesses.
@@ -101,6 +103,9 @@ struct Ctx {
   int T, nteams, team, tl;
   LDSP uint64_t* scr;      // arena mode: free LDS for the round update
   int scr_words;
+  int pw;                  // words per parameter row (0: no parameters)
+  uint64_t* par;           // CURRENT parameter rows, n x pw (global)
+  uint8_t* terms;          // recorded terms (global)
 };
 
 template <class P>
@@ -167,6 +172,9 @@ __device__ void setup_ctx(Ctx<LA>& c, uint8_t* arena, uint8_t* lds) {
   c.scr = nullptr;
   c.scr_words = 0;
   c.trace = (int32_t*)(arena + c.h->off_trace);
+  c.pw = uni(c.h->pw);
+  c.par = c.pw ? (uint64_t*)(arena + c.h->off_par) : nullptr;
+  c.terms = c.pw ? arena + c.h->off_terms : nullptr;
   c.T = team_size(W);
   c.nteams = BS / c.T;
   c.team = threadIdx.x / c.T;
@@ -218,6 +226,10 @@ __device__ void load_state(Ctx<LA>& c, Shared& sh, bool from_source) {
     c.kc[v] = 0;
     c.partner[v] = -1;
   }
+  if (c.pw && from_source) {
+    const uint64_t* sp = (const uint64_t*)(c.base + c.h->off_src_par);
+    for (int64_t i = tid; i < (int64_t)n * c.pw; i += BS) c.par[i] = sp[i];
+  }
   const uint64_t* bm = (const uint64_t*)(c.base + c.h->off_bndmask);
   const uint64_t* al = (const uint64_t*)(c.base + c.h->off_alive);
   for (int j = tid; j < W; j += BS) {
@@ -245,6 +257,7 @@ __device__ void load_state(Ctx<LA>& c, Shared& sh, bool from_source) {
     sh.n_trace = 0;
     sh.round = 0;
     sh.status = 0;
+    sh.n_terms = (from_source || !c.pw) ? 0 : c.h->n_terms;
   }
   __syncthreads();
   const int64_t e = count_edges<BS, LA>(c, sh);
@@ -281,6 +294,7 @@ __device__ void store_state(Ctx<LA>& c, Shared& sh) {
     c.h->fill_in = sh.fill_in;
     c.h->n_edges = sh.E;
     c.h->n_alive = sh.cnt;
+    if (c.pw) c.h->n_terms = sh.n_terms;
   }
   __syncthreads();
 }
@@ -745,6 +759,7 @@ __device__ void delete_selected(Ctx<LA>& c, Shared& sh, bool cols_done) {
     auto rx = row_ptr(c, x);
     for (int j = c.tl; j < W; j += c.T) rx[j] = 0;
     if (c.tl == 0) c.k[x] = 0;
+    for (int q = c.tl; q < c.pw; q += c.T) c.par[(int64_t)x * c.pw + q] = 0;
   }
   __syncthreads();
   for (int j = threadIdx.x; j < W; j += BS) c.alive[j] &= ~c.sel[j];
@@ -802,6 +817,117 @@ __device__ void trace_lc_round(Ctx<LA>& c, Shared& sh) {
   __syncthreads();
 }
 
+// ------------------------------------------------ parameterized spiders --
+// A spider's phase is k pi/4 + (p . f) pi, p its parameter row (the paper's
+// parameterized Pauli vertices; the rules of appendix "Rewrite rules" take
+// phases pi/2 + b pi and a pi with binary a, b).
+
+__device__ __forceinline__ bool par_nonzero(const uint64_t* par, int pw, int v) {
+  uint64_t o = 0;
+  for (int q = 0; q < pw; ++q) o |= par[(int64_t)v * pw + q];
+  return o != 0;
+}
+
+// Terms of the round's rewrites whose scalar depends on the parameters, in
+// trace order (ascending spider for local complementation, ascending lower
+// end for pivots; slist is ascending).  Local complementation at u with
+// p_u != 0: the factor e^{-i b pi/2}, b = (k_u - 2)/4 XOR p_u.f, is
+// h(pi, pi/2; p_u.f, 0)/(2i) for k_u = 2 and -i h(0, pi/2; p_u.f, 0)/2 for
+// k_u = 6: term (k_alpha, k_beta) = (4 or 0, 2), constant omega^-2 / 2 in
+// place of the rule's e^{-i b0 pi/2}.  Pivot (u, v) with p_u or p_v != 0:
+// (-1)^{ab} = h(a0 pi, b0 pi; p_u.f, p_v.f)/2: term (k_u, k_v), constant 1/2
+// in place of (-1)^{a0 b0}.  The constants go straight into the scalar.
+// Reads only phases, partners and parameter rows of the selected spiders,
+// none of which the round has changed yet.
+template <int BS, bool LA>
+__device__ void terms_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+  if (!c.pw) return;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, pw = c.pw, ns = uni(sh.ns);
+    const int64_t tb = zx_term_bytes(pw);
+    int nt = sh.n_terms, dphase = 0, cnt = 0;
+    for (int i0 = 0; i0 < ns; i0 += 64) {
+      const int i = i0 + lane;
+      bool has = false;
+      int x = -1, p = -1;
+      if (i < ns) {
+        x = c.slist[i];
+        p = pivot ? c.partner[x] : -1;
+        if (!pivot || p > x)
+          has = par_nonzero(c.par, pw, x) || (pivot && par_nonzero(c.par, pw, p));
+      }
+      const uint64_t b = __ballot(has);
+      const int pos = nt + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
+      if (has && pos <= c.n) {
+        uint8_t* e = c.terms + (int64_t)pos * tb;
+        ZxTermHead* hd = (ZxTermHead*)e;
+        uint64_t* u = (uint64_t*)(e + 16);
+        uint64_t* v = u + pw;
+        if (!pivot) {
+          hd->k_alpha = c.k[x] == 2 ? 4 : 0;
+          hd->k_beta = 2;
+          for (int q = 0; q < pw; ++q) {
+            u[q] = c.par[(int64_t)x * pw + q];
+            v[q] = 0;
+          }
+          dphase += c.k[x] == 2 ? -2 : 0;  // -1 in place of 1 - 2 b0
+        } else {
+          hd->k_alpha = c.k[x];
+          hd->k_beta = c.k[p];
+          for (int q = 0; q < pw; ++q) {
+            u[q] = c.par[(int64_t)x * pw + q];
+            v[q] = c.par[(int64_t)p * pw + q];
+          }
+          dphase -= 4 * ((c.k[x] / 4) * (c.k[p] / 4));  // 0 in place of 4 a0 b0
+        }
+        hd->pad0 = hd->pad1 = 0;
+      }
+      nt += __popcll(b);
+      cnt += __popcll(b);
+    }
+    for (int o = 32; o > 0; o >>= 1) dphase += __shfl_xor(dphase, o);
+    if (lane == 0) {
+      if (nt > c.n + 1) sh.status = ZX_ECAPACITY;
+      sh.n_terms = nt;
+      sh.phase8 = (sh.phase8 + dphase) & 7;
+      sh.pow_sqrt2 -= 2 * (int64_t)cnt;
+    }
+  }
+  __syncthreads();
+}
+
+// Parameter rows after the round: local complementation at u gives every
+// neighbour p_u; a pivot (u, v) gives N(u) p_v and N(v) p_u (common
+// neighbours both).  So p_w ^= XOR over selected x adjacent to w of
+// p_src(x), src(x) = x (local complementation) or x's partner (pivot).  One
+// thread per (present unselected row, parameter word); runs before the
+// round changes any unselected row (selected columns are still set).
+template <int BS, bool LA>
+__device__ void param_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+  if (!c.pw) return;
+  const int pw = c.pw, n = c.n, nsw = uni(sh.nsw);
+  const LDSP int32_t* sw = (const LDSP int32_t*)c.blocked;
+  for (int64_t it = threadIdx.x; it < (int64_t)n * pw; it += BS) {
+    const int w = (int)(it / pw), q = (int)(it - (int64_t)w * pw);
+    if (!bit_of(c.alive, w) || bit_of(c.sel, w)) continue;
+    const auto row = row_ptr(c, w);
+    uint64_t d = 0;
+    for (int s = 0; s < nsw; ++s) {
+      const int kw = sw[s];
+      uint64_t msk = row[kw] & c.sel[kw];
+      while (msk) {
+        const int b = __ffsll((long long)msk) - 1;
+        msk &= msk - 1;
+        const int x = 64 * kw + b;
+        const int src = pivot ? c.partner[x] : x;
+        d ^= c.par[(int64_t)src * pw + q];
+      }
+    }
+    if (d) c.par[it] ^= d;
+  }
+  __syncthreads();
+}
+
 #include "policy_dev.h"
 
 // ----------------------------------------------------------- simplify --
@@ -841,6 +967,8 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     trace_lc_round<BS, LA>(c, sh);
     prepare_round<BS, LA>(c, sh, false, false);
     collect_swords<BS, LA>(c, sh);
+    terms_round<BS, LA>(c, sh, false);
+    param_round<BS, LA>(c, sh, false);
     const bool cc = apply_round<BS, LA>(c, sh, false);
     delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, removed);
@@ -860,6 +988,8 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     if (npairs == 0) break;
     prepare_round<BS, LA>(c, sh, true, false);
     collect_swords<BS, LA>(c, sh);
+    terms_round<BS, LA>(c, sh, true);
+    param_round<BS, LA>(c, sh, true);
     const bool cc = apply_round<BS, LA>(c, sh, true);
     delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, 2 * npairs);
@@ -1099,6 +1229,9 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
     if (fits) {
       setup_ctx<BS, true>(c, arena, smem_dyn);
       c.trace = nullptr;
+      c.pw = 0;  // the state is only read: parameter rows play no part in a rollout's cost
+      c.par = nullptr;
+      c.terms = nullptr;
       pol.wbf = nullptr;
       pol.param = nullptr;
       pol.cap = pol_cap(n);
@@ -1185,6 +1318,9 @@ __global__ __launch_bounds__(BS) void features_kernel(FeatArgs a) {
   Ctx<true> c;
   setup_ctx<BS, true>(c, a.arena, smem_dyn);
   c.trace = nullptr;
+  c.pw = 0;
+  c.par = nullptr;
+  c.terms = nullptr;
   Pol pol;
   pol.wbf = nullptr;
   pol.param = nullptr;
@@ -1366,6 +1502,8 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
   } else {
     prepare_round<BS, LA>(c, sh, pivot != 0, false);
     collect_swords<BS, LA>(c, sh);
+    terms_round<BS, LA>(c, sh, pivot != 0);
+    param_round<BS, LA>(c, sh, pivot != 0);
     const bool cc = apply_round<BS, LA>(c, sh, pivot != 0);
     delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, pivot ? 2 : 1);
@@ -1387,6 +1525,11 @@ __global__ void reset_kernel(uint8_t* arena) {
   for (int64_t v = tid; v < n; v += nth) dp[v] = sp[v];
   for (int64_t j = tid; j < W; j += nth)
     al[j] = (j < W - 1 || (n & 63) == 0) ? ~0ull : ((1ull << (n & 63)) - 1);
+  if (h->pw) {
+    const uint64_t* spar = (const uint64_t*)(arena + h->off_src_par);
+    uint64_t* dpar = (uint64_t*)(arena + h->off_par);
+    for (int64_t i = tid; i < (int64_t)n * h->pw; i += nth) dpar[i] = spar[i];
+  }
   if (tid == 0) {
     int64_t e = 0;
     (void)e;
@@ -1399,6 +1542,7 @@ __global__ void reset_kernel(uint8_t* arena) {
     h->rank = -1;
     h->rowops = 0;
     h->n_alive = n;
+    h->n_terms = 0;
   }
 }
 

@@ -31,13 +31,15 @@ __device__ __forceinline__ uint32_t xor_and(uint32_t acc, uint32_t a, uint32_t b
 
 // This lane's string j, qubit words [q0, q0 + nq) of the chunk, as halves.
 __device__ __forceinline__ void load_j(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z, int64_t j,
-                                       int64_t n, int64_t ldq, int q0, int nq, uint32_t* xj, uint32_t* zj) {
+                                       int64_t n, int64_t ldq, int q0, int nq, int qw, uint64_t qmask,
+                                       uint32_t* xj, uint32_t* zj) {
 #pragma unroll
   for (int w = 0; w < QCH; ++w) {
     uint64_t xv = 0, zv = 0;
     if (w < nq && j < n) {
-      xv = X[j * ldq + q0 + w];
-      zv = Z[j * ldq + q0 + w];
+      const uint64_t mk = q0 + w == qw - 1 ? qmask : ~0ull;
+      xv = X[j * ldq + q0 + w] & mk;
+      zv = Z[j * ldq + q0 + w] & mk;
     }
     xj[2 * w] = (uint32_t)xv;
     xj[2 * w + 1] = (uint32_t)(xv >> 32);
@@ -48,8 +50,8 @@ __device__ __forceinline__ void load_j(const uint64_t* __restrict__ X, const uin
 
 __global__ __launch_bounds__(BS) void pauli_kernel(const uint64_t* __restrict__ X,
                                                    const uint64_t* __restrict__ Z, int64_t n,
-                                                   int qw, int64_t ldq, uint64_t* __restrict__ C,
-                                                   int64_t ldc) {
+                                                   int qw, uint64_t qmask, int64_t ldq,
+                                                   uint64_t* __restrict__ C, int64_t ldc) {
   __shared__ uint64_t xi_s[64][QCH];
   __shared__ uint64_t zi_s[64][QCH];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(BS) void pauli_kernel(const uint64_t* __restrict__ 
   const int64_t j = jw * 64 + lane;
   const bool one_chunk = qw <= QCH;
   uint32_t xj[2 * QCH], zj[2 * QCH];
-  if (one_chunk) load_j(X, Z, j, n, ldq, 0, qw, xj, zj);
+  if (one_chunk) load_j(X, Z, j, n, ldq, 0, qw, qw, qmask, xj, zj);
   // every wave runs the same iterations (barriers inside); the bounds are
   // uniform over the workgroup
   for (int t = 0; t < IT && it0 + t < nwj; ++t) {
@@ -74,10 +76,11 @@ __global__ __launch_bounds__(BS) void pauli_kernel(const uint64_t* __restrict__ 
         const int r = x / QCH, w = x % QCH;
         const int64_t i = i0 + r;
         const bool in = i < n && w < nq;
-        xi_s[r][w] = in ? X[i * ldq + q0 + w] : 0;
-        zi_s[r][w] = in ? Z[i * ldq + q0 + w] : 0;
+        const uint64_t mk = q0 + w == qw - 1 ? qmask : ~0ull;
+        xi_s[r][w] = in ? X[i * ldq + q0 + w] & mk : 0;
+        zi_s[r][w] = in ? Z[i * ldq + q0 + w] & mk : 0;
       }
-      if (!one_chunk && active) load_j(X, Z, j, n, ldq, q0, nq, xj, zj);
+      if (!one_chunk && active) load_j(X, Z, j, n, ldq, q0, nq, qw, qmask, xj, zj);
       __syncthreads();
       if (!active) continue;
       // the 64 parities go into two 32-bit halves, one shift-or each
@@ -115,11 +118,6 @@ __global__ __launch_bounds__(BS) void pauli_kernel(const uint64_t* __restrict__ 
   }
 }
 
-__global__ void clear_tail(uint64_t* C, int64_t n, int64_t ldc) {
-  // words beyond ceil(n/64) in each row are left untouched; nothing to do
-  (void)C; (void)n; (void)ldc;
-}
-
 }  // namespace
 
 extern "C" zx_status zx_pauli_commute(const uint64_t* X, const uint64_t* Z, int64_t n_paulis,
@@ -133,9 +131,20 @@ extern "C" zx_status zx_pauli_commute(const uint64_t* X, const uint64_t* Z, int6
   const int64_t nwj = (n_paulis + 63) / 64;
   ZX_CHECK_ARG(ld_c >= nwj, "ld_c too small");
   ZX_CHECK_ARG(nwj <= 65535 * (int64_t)NJW && (nwj + IT - 1) / IT <= 65535, "too many strings");
-  dim3 grid((unsigned)((nwj + NJW - 1) / NJW), (unsigned)((nwj + IT - 1) / IT));
-  hipLaunchKernelGGL(pauli_kernel, grid, dim3(BS), 0, s, X, Z, n_paulis, qw, ld_q, C, ld_c);
-  ZX_HIP(hipGetLastError());
+  ZX_CHECK_ARG((flags & (ZX_PAULI_FORCE_VALU | ZX_PAULI_FORCE_MFMA)) !=
+                   (ZX_PAULI_FORCE_VALU | ZX_PAULI_FORCE_MFMA),
+               "ZX_PAULI_FORCE_VALU and ZX_PAULI_FORCE_MFMA together");
+  const bool mfma = (flags & ZX_PAULI_FORCE_MFMA) ||
+                    (!(flags & ZX_PAULI_FORCE_VALU) && n_paulis >= ZX_PAULI_MFMA_MIN);
+  if (mfma) {
+    zx_status rc = zx_pauli_commute_mfma(X, Z, n_paulis, n_qubits, ld_q, C, ld_c, s);
+    if (rc != ZX_OK) return rc;
+  } else {
+    const uint64_t qmask = (n_qubits % 64) ? ((1ull << (n_qubits % 64)) - 1) : ~0ull;
+    dim3 grid((unsigned)((nwj + NJW - 1) / NJW), (unsigned)((nwj + IT - 1) / IT));
+    hipLaunchKernelGGL(pauli_kernel, grid, dim3(BS), 0, s, X, Z, n_paulis, qw, qmask, ld_q, C, ld_c);
+    ZX_HIP(hipGetLastError());
+  }
   if (flags & ZX_SYNC) ZX_HIP(hipStreamSynchronize(s));
   return ZX_OK;
 }

@@ -63,12 +63,19 @@ extern "C" size_t zx_graph_bytes(int32_t n, int32_t n_in, int32_t n_out) {
 zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
                          const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
                          int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
-                         std::vector<uint8_t>& img) {
+                         std::vector<uint8_t>& img, int32_t n_params, const uint64_t* param_rows) {
   ZX_CHECK_ARG(adj_host && phase_host, "null argument");
   ZX_CHECK_ARG(n > 0 && n <= (1 << 20), "n out of range: %d", n);
   ZX_CHECK_ARG(n_in >= 0 && n_out >= 0 && n_in + n_out <= n, "bad boundary counts");
   ZX_CHECK_ARG((n_in == 0 || in_spider) && (n_out == 0 || out_spider), "null boundary list");
-  ZxLayout L = zx_layout(n, n_in, n_out);
+  ZX_CHECK_ARG(n_params >= 0 && n_params <= ZX_MAX_PARAMS, "n_params %d not in 0..%d", n_params, ZX_MAX_PARAMS);
+  ZX_CHECK_ARG(n_params == 0 || param_rows, "null parameter rows");
+  ZxLayout L = zx_layout(n, n_in, n_out, n_params);
+  const int pw = (n_params + 63) / 64;
+  if (n_params % 64)
+    for (int r = 0; r < n; ++r)
+      ZX_CHECK_ARG((param_rows[(size_t)r * pw + pw - 1] >> (n_params % 64)) == 0,
+                   "parameter bits beyond n_params in row %d", r);
   const int W = (n + 63) / 64;
   // validate on the host: symmetric, zero diagonal, no bits >= n, phases
   for (int r = 0; r < n; ++r) {
@@ -114,6 +121,12 @@ zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phas
   h.off_trace = L.off_trace;
   h.off_front = L.off_front;
   h.off_fpiv = L.off_fpiv;
+  h.n_params = n_params;
+  h.pw = pw;
+  h.off_src_par = L.off_src_par;
+  h.off_par = L.off_par;
+  h.off_terms = L.off_terms;
+  h.n_terms = 0;
   h.bytes = L.bytes;
   int64_t edges = 0;
   for (size_t i = 0; i < (size_t)n * W; ++i) edges += __builtin_popcountll(adj_host[i]);
@@ -126,6 +139,10 @@ zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phas
   if (n_in) memcpy(img.data() + L.off_in, in_spider, 4 * (size_t)n_in);
   if (n_out) memcpy(img.data() + L.off_out, out_spider, 4 * (size_t)n_out);
   if (bnd_is_h) memcpy(img.data() + L.off_is_h, bnd_is_h, (size_t)(n_in + n_out));
+  if (pw) {
+    memcpy(img.data() + L.off_src_par, param_rows, (size_t)n * pw * 8);
+    memcpy(img.data() + L.off_par, param_rows, (size_t)n * pw * 8);
+  }
   uint64_t* bm = (uint64_t*)(img.data() + L.off_bndmask);
   for (int v = 0; v < n; ++v)
     if (seen[v]) bm[v / 64] |= (uint64_t)1 << (v % 64);
@@ -136,23 +153,30 @@ zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phas
   return ZX_OK;
 }
 
-extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
-                                     const uint64_t* adj_host, const int8_t* phase_host,
-                                     const int32_t* in_spider, int32_t n_in,
-                                     const int32_t* out_spider, int32_t n_out,
-                                     const uint8_t* bnd_is_h, hipStream_t s) {
+extern "C" size_t zx_graph_bytes_ex(int32_t n, int32_t n_in, int32_t n_out, int32_t n_params) {
+  if (n <= 0 || n_in < 0 || n_out < 0 || n_params < 0 || n_params > ZX_MAX_PARAMS) return 0;
+  return (size_t)zx_layout(n, n_in, n_out, n_params).bytes;
+}
+
+extern "C" zx_status zx_graph_create_ex(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
+                                        const uint64_t* adj_host, const int8_t* phase_host,
+                                        const int32_t* in_spider, int32_t n_in,
+                                        const int32_t* out_spider, int32_t n_out,
+                                        const uint8_t* bnd_is_h, int32_t n_params,
+                                        const uint64_t* param_rows, hipStream_t s) {
   zx_clear_error();
   ZX_CHECK_ARG(g && dev_arena && adj_host && phase_host, "null argument");
   ZX_CHECK_ARG(n > 0 && n <= (1 << 20), "n out of range: %d", n);
   ZX_CHECK_ARG(n_in >= 0 && n_out >= 0 && n_in + n_out <= n, "bad boundary counts");
   ZX_CHECK_ARG((n_in == 0 || in_spider) && (n_out == 0 || out_spider), "null boundary list");
   ZX_CHECK_ARG(((uintptr_t)dev_arena & 255) == 0, "arena must be 256-byte aligned");
-  ZxLayout L = zx_layout(n, n_in, n_out);
+  ZX_CHECK_ARG(n_params >= 0 && n_params <= ZX_MAX_PARAMS, "n_params %d not in 0..%d", n_params, ZX_MAX_PARAMS);
+  ZxLayout L = zx_layout(n, n_in, n_out, n_params);
   ZX_CHECK_ARG(arena_bytes >= (size_t)L.bytes, "arena too small: %zu < %lld", arena_bytes,
                (long long)L.bytes);
   std::vector<uint8_t> img;
   zx_status st = zx_build_image(n, adj_host, phase_host, in_spider, n_in, out_spider, n_out, bnd_is_h,
-                                true, img);
+                                true, img, n_params, param_rows);
   if (st != ZX_OK) return st;
   const int W = (n + 63) / 64;
   ZX_HIP(hipMemcpyAsync(dev_arena, img.data(), img.size(), hipMemcpyHostToDevice, s));
@@ -168,9 +192,20 @@ extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena
   G->n_in = n_in;
   G->n_out = n_out;
   G->W = W;
+  G->n_params = n_params;
+  G->pw = (n_params + 63) / 64;
   G->L = L;
   *g = G;
   return ZX_OK;
+}
+
+extern "C" zx_status zx_graph_create(zx_graph** g, void* dev_arena, size_t arena_bytes, int32_t n,
+                                     const uint64_t* adj_host, const int8_t* phase_host,
+                                     const int32_t* in_spider, int32_t n_in,
+                                     const int32_t* out_spider, int32_t n_out,
+                                     const uint8_t* bnd_is_h, hipStream_t s) {
+  return zx_graph_create_ex(g, dev_arena, arena_bytes, n, adj_host, phase_host, in_spider, n_in, out_spider,
+                            n_out, bnd_is_h, 0, nullptr, s);
 }
 
 extern "C" zx_status zx_graph_attach(zx_graph** g, void* dev_arena, size_t arena_bytes) {
@@ -179,7 +214,7 @@ extern "C" zx_status zx_graph_attach(zx_graph** g, void* dev_arena, size_t arena
   ZxHeader h;
   ZX_HIP(hipMemcpy(&h, dev_arena, sizeof(h), hipMemcpyDeviceToHost));
   ZX_CHECK_ARG(h.magic == ZX_MAGIC, "arena not initialised by zx_graph_create");
-  ZxLayout L = zx_layout(h.n, h.n_in, h.n_out);
+  ZxLayout L = zx_layout(h.n, h.n_in, h.n_out, h.n_params);
   ZX_CHECK_ARG(arena_bytes >= (size_t)L.bytes, "arena too small");
   zx_graph* G = (zx_graph*)calloc(1, sizeof(zx_graph));
   if (!G) return ZX_ECAPACITY;
@@ -189,6 +224,8 @@ extern "C" zx_status zx_graph_attach(zx_graph** g, void* dev_arena, size_t arena
   G->n_in = h.n_in;
   G->n_out = h.n_out;
   G->W = h.W;
+  G->n_params = h.n_params;
+  G->pw = h.pw;
   G->L = L;
   *g = G;
   return ZX_OK;
@@ -249,6 +286,36 @@ extern "C" zx_status zx_graph_read_frontier(const zx_graph* g, uint64_t* rows, i
                      hipMemcpyDeviceToHost));
   if (pivots && g->n_out)
     ZX_HIP(hipMemcpy(pivots, g->arena + g->L.off_fpiv, (size_t)g->n_out * 4, hipMemcpyDeviceToHost));
+  return ZX_OK;
+}
+
+extern "C" zx_status zx_graph_read_params(const zx_graph* g, uint64_t* rows, int32_t* n_terms, int32_t* k_ab,
+                                          uint64_t* u, uint64_t* v, int32_t cap, hipStream_t s) {
+  zx_clear_error();
+  ZX_CHECK_ARG(g, "null graph");
+  ZX_HIP(hipStreamSynchronize(s));
+  const int pw = g->pw;
+  if (rows && pw)
+    ZX_HIP(hipMemcpy(rows, g->arena + g->L.off_par, (size_t)g->n * pw * 8, hipMemcpyDeviceToHost));
+  int32_t nt = 0;
+  if (pw) ZX_HIP(hipMemcpy(&nt, g->arena + offsetof(ZxHeader, n_terms), 4, hipMemcpyDeviceToHost));
+  if (n_terms) *n_terms = nt;
+  const int cnt = nt < cap ? nt : cap;
+  if (cnt > 0 && (k_ab || u || v)) {
+    const int64_t tb = zx_term_bytes(pw);
+    std::vector<uint8_t> buf((size_t)cnt * tb);
+    ZX_HIP(hipMemcpy(buf.data(), g->arena + g->L.off_terms, buf.size(), hipMemcpyDeviceToHost));
+    for (int t = 0; t < cnt; ++t) {
+      const uint8_t* e = buf.data() + (size_t)t * tb;
+      const ZxTermHead* hd = (const ZxTermHead*)e;
+      if (k_ab) {
+        k_ab[2 * t] = hd->k_alpha;
+        k_ab[2 * t + 1] = hd->k_beta;
+      }
+      if (u) memcpy(u + (size_t)t * pw, e + 16, (size_t)pw * 8);
+      if (v) memcpy(v + (size_t)t * pw, e + 16 + 8 * pw, (size_t)pw * 8);
+    }
+  }
   return ZX_OK;
 }
 

@@ -35,18 +35,32 @@ struct ZxHeader {
   int64_t off_src_adj, off_src_phase, off_in, off_out, off_is_h, off_bndmask;
   int64_t off_adj, off_phase, off_alive, off_trace, off_front, off_fpiv;
   int64_t bytes;
-  int64_t reserved[7];
+  // parameterized Pauli spiders (0 parameters: sections of size 0)
+  int32_t n_params, pw;  // parameters, 64-bit words per parameter row
+  int64_t off_src_par, off_par, off_terms;
+  int32_t n_terms;       // phase-pair terms recorded
+  int32_t pad1;
+  int64_t reserved[2];
 };
 static_assert(sizeof(ZxHeader) <= 256, "header fits 256 bytes");
+
+// A recorded phase-pair term: head, then u[pw], v[pw] words.
+struct ZxTermHead {
+  int32_t k_alpha, k_beta, pad0, pad1;
+};
+static inline __host__ __device__ int64_t zx_term_bytes(int pw) { return 16 + 16 * (int64_t)pw; }
+constexpr int32_t ZX_MAX_PARAMS = 4096;
 
 static inline __host__ __device__ int64_t zx_align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 struct ZxLayout {
   int64_t off_src_adj, off_src_phase, off_in, off_out, off_is_h, off_bndmask;
-  int64_t off_adj, off_phase, off_alive, off_trace, off_front, off_fpiv, bytes;
+  int64_t off_adj, off_phase, off_alive, off_trace, off_front, off_fpiv;
+  int64_t off_src_par, off_par, off_terms, bytes;
 };
 
-static inline __host__ __device__ ZxLayout zx_layout(int32_t n, int32_t n_in, int32_t n_out) {
+static inline __host__ __device__ ZxLayout zx_layout(int32_t n, int32_t n_in, int32_t n_out,
+                                                     int32_t n_params = 0) {
   ZxLayout L;
   int64_t W = (n + 63) / 64;
   int64_t o = 256;
@@ -62,6 +76,12 @@ static inline __host__ __device__ ZxLayout zx_layout(int32_t n, int32_t n_in, in
   L.off_trace = o;     o = zx_align256(o + 16 * (int64_t)(n + 1));
   L.off_front = o;     o = zx_align256(o + (int64_t)n_out * W * 8);
   L.off_fpiv = o;      o = zx_align256(o + 4 * (int64_t)(n_out + 1));
+  // parameter sections last, so that a diagram without parameters keeps the
+  // layout (and size) it had before they existed
+  const int64_t pw = (n_params + 63) / 64;
+  L.off_src_par = o;   o = zx_align256(o + (int64_t)n * pw * 8);
+  L.off_par = o;       o = zx_align256(o + (int64_t)n * pw * 8);
+  L.off_terms = o;     o = zx_align256(o + (pw ? (int64_t)(n + 1) * zx_term_bytes((int)pw) : 0));
   L.bytes = o;
   return L;
 }
@@ -71,6 +91,7 @@ struct zx_graph {
   uint8_t* arena;  // device
   size_t bytes;
   int32_t n, n_in, n_out, W;
+  int32_t n_params, pw;
   ZxLayout L;
 };
 
@@ -81,7 +102,8 @@ void zx_set_error(const char* fmt, ...);
 zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
                          const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
                          int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
-                         std::vector<uint8_t>& img);
+                         std::vector<uint8_t>& img, int32_t n_params = 0,
+                         const uint64_t* param_rows = nullptr);
 
 // Largest diagram the simplify kernels take with this policy (graph.hip).
 int32_t zx_max_spiders(int32_t policy);
@@ -139,6 +161,12 @@ struct ZxDevice {
   char name[128];
 };
 const ZxDevice* zx_device();
+
+// Commutation table on the matrix cores (gf2mm.hip); zx_pauli_commute picks
+// it from this many strings up unless a flag forces a variant.
+constexpr int64_t ZX_PAULI_MFMA_MIN = 1024;
+zx_status zx_pauli_commute_mfma(const uint64_t* X, const uint64_t* Z, int64_t n, int32_t n_qubits, int64_t ldq,
+                                uint64_t* C, int64_t ldc, hipStream_t s);
 
 // ---------------------------------------------------- device helpers --
 // Device-side status update: keep the first error.

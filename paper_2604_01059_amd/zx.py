@@ -89,6 +89,10 @@ def load():
         "zx_graph_bytes": ([i32, i32, i32], sz),
         "zx_graph_create": ([C.POINTER(P), P, sz, i32, P, P, P, i32, P, i32, P, P], i32),
         "zx_graph_attach": ([C.POINTER(P), P, sz], i32),
+        "zx_graph_bytes_ex": ([i32, i32, i32, i32], sz),
+        "zx_graph_create_ex": ([C.POINTER(P), P, sz, i32, P, P, P, i32, P, i32, P, i32, P, P], i32),
+        "zx_graph_read_params": ([P, P, C.POINTER(i32), P, P, P, i32, P], i32),
+        "zx_gf2_basis": ([P, i32, i32, i64, P, P, P, P, i64, P, sz, P], i32),
         "zx_graph_destroy": ([P], None),
         "zx_graph_arena": ([P], P),
         "zx_graph_read": ([P, P, P, P, C.POINTER(GraphInfo), P], i32),
@@ -112,6 +116,11 @@ def load():
         "zx_gf2_status": ([P, P], i32),
         "zx_gf2_profile_read": ([P, i32, P, i32, P], i32),
         "zx_pauli_commute": ([P, P, i64, i32, i64, P, i64, u32, P], i32),
+        "zx_gf2_matmul": ([P, i64, i64, P, i64, i64, i32, P, i64, u32, P], i32),
+        "zx_phase_pair_product": ([P, P, i64, i32, i64, P, P, i32, i64, P, P, P], i32),
+        "zx_detector_workspace_bytes": ([i32], sz),
+        "zx_detector_sample": ([P, P, i64, P, i32, i32, C.c_uint64, i64, i64, P, i64, P, sz, P], i32),
+        "zx_detector_status": ([P, P], i32),
         "zx_mlp_sync": ([C.POINTER(MlpHandle), P], i32),
         "zx_mlp_forward": ([C.POINTER(MlpHandle), P, i64, P, P], i32),
         "zx_mlp_loss": ([P, P, P, i32, P, P, P], i32),
@@ -138,12 +147,15 @@ def load():
 
 def exported_symbols():
     return ["zx_version", "zx_last_error", "zx_device_info", "zx_graph_bytes", "zx_graph_create",
-            "zx_graph_attach", "zx_graph_destroy", "zx_graph_arena", "zx_graph_read",
+            "zx_graph_attach", "zx_graph_bytes_ex", "zx_graph_create_ex", "zx_graph_read_params",
+            "zx_gf2_basis", "zx_graph_destroy", "zx_graph_arena", "zx_graph_read",
             "zx_graph_read_trace", "zx_graph_read_frontier", "zx_graph_status", "zx_graph_reset",
             "zx_local_comp", "zx_pivot", "zx_simplify_variants", "zx_simplify_variant_name",
             "zx_simplify_workspace_bytes", "zx_simplify", "zx_batch_prepare", "zx_batch_simplify",
             "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
             "zx_gf2_eliminate", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
+            "zx_gf2_matmul", "zx_phase_pair_product", "zx_detector_workspace_bytes",
+            "zx_detector_sample", "zx_detector_status",
             "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
             "zx_mlp_adam", "zx_rollout_workspace_bytes", "zx_rollout", "zx_policy_features", "zx_server_create",
             "zx_server_submit", "zx_server_poll", "zx_server_stats_read", "zx_server_destroy"]
@@ -185,11 +197,13 @@ def device_info():
 class Graph:
     """Host handle of a diagram arena (torch uint8 device tensor)."""
 
-    def __init__(self, handle, arena, n, n_in, n_out):
+    def __init__(self, handle, arena, n, n_in, n_out, n_params=0):
         self.h = handle
         self.arena = arena
         self.n, self.n_in, self.n_out = n, n_in, n_out
         self.W = (n + 63) // 64
+        self.n_params = int(n_params)
+        self.pw = (self.n_params + 63) // 64
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -200,23 +214,45 @@ class Graph:
     def bytes_for(n, n_in, n_out):
         return load().zx_graph_bytes(n, n_in, n_out)
 
+    @staticmethod
+    def bytes_for_params(n, n_in, n_out, n_params):
+        return load().zx_graph_bytes_ex(n, n_in, n_out, n_params)
+
     @classmethod
-    def create(cls, adj, phase, inputs, outputs, bnd_is_h=None, arena=None, stream=None):
+    def create(cls, adj, phase, inputs, outputs, bnd_is_h=None, arena=None, stream=None, n_params=0,
+               params=None):
+        """params: n x ceil(n_params/64) uint64 parameter rows (with n_params > 0)."""
         import torch
         adj = np.ascontiguousarray(adj, dtype=np.uint64)
         phase = np.ascontiguousarray(phase, dtype=np.int8)
         inputs = np.ascontiguousarray(inputs, dtype=np.int32)
         outputs = np.ascontiguousarray(outputs, dtype=np.int32)
         n = int(adj.shape[0])
-        nb = cls.bytes_for(n, len(inputs), len(outputs))
+        nb = cls.bytes_for_params(n, len(inputs), len(outputs), n_params)
         if arena is None:
             arena = torch.empty(nb, dtype=torch.uint8, device="cuda")
         bh = None if bnd_is_h is None else np.ascontiguousarray(bnd_is_h, dtype=np.uint8)
+        prm = None if not n_params else np.ascontiguousarray(params, dtype=np.uint64)
         h = C.c_void_p()
-        _check(load().zx_graph_create(C.byref(h), _ptr(arena), arena.numel(), n, _np(adj), _np(phase),
-                                      _np(inputs), len(inputs), _np(outputs), len(outputs), _np(bh),
-                                      _stream(stream)))
-        return cls(h, arena, n, len(inputs), len(outputs))
+        _check(load().zx_graph_create_ex(C.byref(h), _ptr(arena), arena.numel(), n, _np(adj), _np(phase),
+                                         _np(inputs), len(inputs), _np(outputs), len(outputs), _np(bh),
+                                         int(n_params), _np(prm), _stream(stream)))
+        return cls(h, arena, n, len(inputs), len(outputs), n_params)
+
+    def params(self, stream=None):
+        """(rows (n x pw), k_ab (m x 2), u (m x pw), v (m x pw)): CURRENT
+        parameter rows and the recorded phase-pair terms."""
+        pw = max(self.pw, 1)
+        rows = np.zeros((self.n, pw), np.uint64)
+        cap = self.n + 1
+        kab = np.zeros((cap, 2), np.int32)
+        u = np.zeros((cap, pw), np.uint64)
+        v = np.zeros((cap, pw), np.uint64)
+        nt = C.c_int32(0)
+        _check(load().zx_graph_read_params(self.h, _np(rows), C.byref(nt), _np(kab), _np(u), _np(v), cap,
+                                           _stream(stream)))
+        m = nt.value
+        return rows[:, : self.pw], kab[:m].copy(), u[:m, : self.pw].copy(), v[:m, : self.pw].copy()
 
     @classmethod
     def from_diagram(cls, d, arena=None, stream=None):
@@ -228,8 +264,8 @@ class Graph:
         h = C.c_void_p()
         _check(load().zx_graph_attach(C.byref(h), _ptr(arena), arena.numel()))
         import torch
-        hdr = arena[:16].cpu().numpy().view(np.int32)
-        return cls(h, arena, int(hdr[1]), int(hdr[2]), int(hdr[3]))
+        hdr = arena[:192].cpu().numpy().view(np.int32)
+        return cls(h, arena, int(hdr[1]), int(hdr[2]), int(hdr[3]), int(hdr[46]))
 
     def snapshot(self):
         """Independent copy of the arena (SOURCE, CURRENT, trace, header)."""
@@ -510,6 +546,23 @@ def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, strea
     return R, rank, pivots, ws
 
 
+def gf2_basis(D, n_cols, stream=None):
+    """Minimal basis of the rows of D (device word tensor m x ld): returns
+    (R, rank tensor, pivots tensor, coeff) with the first rank rows of R the
+    basis and D = coeff . basis."""
+    import torch
+    m, ld = D.shape
+    R = torch.empty_like(D)
+    rank = torch.zeros(1, dtype=torch.int32, device=D.device)
+    piv = torch.zeros(m, dtype=torch.int32, device=D.device)
+    ldc = (min(m, n_cols) + 63) // 64
+    coeff = torch.empty((m, ldc), dtype=torch.int64, device=D.device)
+    ws = torch.empty(gf2_workspace_bytes(m, n_cols), dtype=torch.uint8, device=D.device)
+    _check(load().zx_gf2_basis(_ptr(D), m, n_cols, ld, _ptr(R), _ptr(rank), _ptr(piv), _ptr(coeff), ldc, _ptr(ws),
+                               ws.numel(), _stream(stream)))
+    return R, rank, piv, coeff
+
+
 def gf2_status(ws, stream=None):
     return load().zx_gf2_status(_ptr(ws), _stream(stream))
 
@@ -523,15 +576,53 @@ def gf2_profile(ws, m, max_strips=8192, stream=None):
 
 # ------------------------------------------------------------------ Pauli --
 
-def pauli_commute(X, Z, n_qubits, C_out=None, stream=None):
+ZX_PAULI_AUTO, ZX_PAULI_FORCE_VALU, ZX_PAULI_FORCE_MFMA = 0x0, 0x1, 0x2
+
+
+def pauli_commute(X, Z, n_qubits, C_out=None, stream=None, flags=ZX_PAULI_AUTO):
     import torch
     n, ldq = X.shape
     ldc = (n + 63) // 64
     if C_out is None:
         C_out = torch.empty((n, ldc), dtype=X.dtype, device=X.device)
-    _check(load().zx_pauli_commute(_ptr(X), _ptr(Z), n, n_qubits, ldq, _ptr(C_out), C_out.shape[1], 0,
+    _check(load().zx_pauli_commute(_ptr(X), _ptr(Z), n, n_qubits, ldq, _ptr(C_out), C_out.shape[1], flags,
                                    _stream(stream)))
     return C_out
+
+
+# ------------------------------------------------ parameterized evaluation --
+
+def gf2_matmul(A, B, k_bits, C_out=None, stream=None):
+    """C[i][j] = parity of A_i & B_j over the first k_bits bits (device tensors
+    of words, rows A: m, B: n).  Returns C (m x ceil(n/64) words)."""
+    import torch
+    m, lda = A.shape
+    n, ldb = B.shape
+    if C_out is None:
+        C_out = torch.empty((m, (n + 63) // 64), dtype=torch.int64, device=A.device)
+    _check(load().zx_gf2_matmul(_ptr(A), m, lda, _ptr(B), n, ldb, int(k_bits), _ptr(C_out), C_out.shape[1], 0,
+                                _stream(stream)))
+    return C_out
+
+
+def phase_pair_product(A, B, k_alpha, k_beta, n_settings, phase8=0, pow_sqrt2=0, mant=None, expo=None,
+                       stream=None):
+    """Per setting: omega^phase8 sqrt(2)^pow prod_k h(...).  A, B: n_terms x
+    ld word tensors; k_alpha, k_beta: int8 device tensors.  Returns (mant
+    float32 [n, 2], expo int32 [n])."""
+    import torch
+    n_terms = int(k_alpha.numel())
+    ld = A.shape[1] if n_terms else (n_settings + 63) // 64
+    dev = k_alpha.device
+    if mant is None:
+        mant = torch.empty((n_settings, 2), dtype=torch.float32, device=dev)
+    if expo is None:
+        expo = torch.empty(n_settings, dtype=torch.int32, device=dev)
+    _check(load().zx_phase_pair_product(_ptr(A) if n_terms else None, _ptr(B) if n_terms else None, ld,
+                                        n_terms, n_settings, _ptr(k_alpha) if n_terms else None,
+                                        _ptr(k_beta) if n_terms else None, int(phase8), int(pow_sqrt2),
+                                        _ptr(mant), _ptr(expo), _stream(stream)))
+    return mant, expo
 
 
 def to_device_words(a: np.ndarray):
@@ -542,3 +633,35 @@ def to_device_words(a: np.ndarray):
 
 def to_host_words(t) -> np.ndarray:
     return t.cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------- detector sampling --
+
+class DetectorSampler:
+    """Device copy of a detector error model (T as CSC, probabilities) and a
+    workspace; sample() fills rows of f bits for a range of shots."""
+
+    def __init__(self, col_ptr, col_idx, prob, n_f, device="cuda"):
+        import torch
+        self.n_err = int(len(prob))
+        self.n_f = int(n_f)
+        self.nnz = int(len(col_idx))
+        self.col_ptr = torch.from_numpy(np.ascontiguousarray(col_ptr, np.int32)).to(device)
+        self.col_idx = torch.from_numpy(np.ascontiguousarray(col_idx, np.int32)).to(device)
+        if self.nnz == 0:
+            self.col_idx = torch.zeros(1, dtype=torch.int32, device=device)
+        self.prob = torch.from_numpy(np.ascontiguousarray(prob, np.float64)).to(device)
+        self.ws = torch.empty(load().zx_detector_workspace_bytes(self.n_err), dtype=torch.uint8, device=device)
+
+    def sample(self, seed, shot0, n_shots, out=None, stream=None):
+        import torch
+        fw = (self.n_f + 63) // 64
+        if out is None:
+            out = torch.empty((n_shots, fw), dtype=torch.int64, device=self.ws.device)
+        _check(load().zx_detector_sample(_ptr(self.col_ptr), _ptr(self.col_idx), self.nnz, _ptr(self.prob),
+                                         self.n_err, self.n_f, int(seed) & (2 ** 64 - 1), int(shot0), int(n_shots),
+                                         _ptr(out), out.shape[1], _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        return out
+
+    def status(self, stream=None):
+        return load().zx_detector_status(_ptr(self.ws), _stream(stream))

@@ -40,6 +40,7 @@ P_WEIGHTS = 6
 P_SERVE = 7
 P_PARITY = 8
 P_DEM = 9
+P_PROWS = 10
 
 
 @dataclass
@@ -258,17 +259,27 @@ def _bits(seed: int, purpose_item: int, rows: int, cols: int, p: float) -> np.nd
 
 
 def parity_problem(seed: int, n_terms: int, n_settings: int, n_params: int,
-                   p_select: float = 1.0 / 16, p_setting: float = 0.5) -> ParityProblem:
+                   p_select: float = 1.0 / 16, p_setting: float = 0.5,
+                   any_phase: bool = False) -> ParityProblem:
     """Selectors Bernoulli(p_select) (a parity touches n_params * p_select
-    parameters on average), settings Bernoulli(p_setting), phase codes
-    uniform in 0..7."""
+    parameters on average), settings Bernoulli(p_setting).  Terms are of the
+    two kinds the rewrite rules produce, half each: half-pi terms
+    (k_alpha in {0, 4}, k_beta = 2, no second parity: V row zero) and pi-pair
+    terms (k_alpha, k_beta in {0, 4}); with any_phase, phase codes uniform in
+    0..7 instead."""
     U = _bits(seed, 0, n_terms, n_params, p_select)
     V = _bits(seed, 1, n_terms, n_params, p_select)
     F = _bits(seed, 2, n_settings, n_params, p_setting)
     s = stream_seed(seed, 3, P_PARITY)
-    h = draw(s, np.arange(2 * n_terms, dtype=np.uint64))
-    ka = (h[:n_terms] & np.uint64(7)).astype(np.int8)
-    kb = (h[n_terms:] & np.uint64(7)).astype(np.int8)
+    h = draw(s, np.arange(3 * n_terms, dtype=np.uint64))
+    if any_phase:
+        ka = (h[:n_terms] & np.uint64(7)).astype(np.int8)
+        kb = (h[n_terms:2 * n_terms] & np.uint64(7)).astype(np.int8)
+    else:
+        half = (h[2 * n_terms:] & np.uint64(1)).astype(bool)
+        ka = (4 * (h[:n_terms] & np.uint64(1))).astype(np.int8)
+        kb = np.where(half, 2, 4 * (h[n_terms:2 * n_terms] & np.uint64(1))).astype(np.int8)
+        V[half] = 0
     return ParityProblem(n_params, U, V, F, ka, kb)
 
 
@@ -328,3 +339,24 @@ def surface_dem(seed: int, d: int, rounds: int, p: float = 1e-3) -> DetectorMode
     u = unit(draw(s, np.arange(len(cols), dtype=np.uint64)))
     prob = p * (0.5 + u)
     return DetectorModel(n_det + 1, n_det, col_ptr, col_idx, prob.astype(np.float64))
+
+
+def param_rows(seed: int, item: int, n: int, n_params: int, frac: float = 0.3, per: int = 2) -> np.ndarray:
+    """Parameter rows of a diagram's spiders (n x ceil(n_params/64) words):
+    each spider carries parameters with probability ``frac``, then ``per``
+    parameter indices uniform in [0, n_params) (XORed, so a repeat cancels),
+    as a Pauli noise location flips the phase of the spiders it touches."""
+    pw = words_for(n_params)
+    out = np.zeros((n, pw), np.uint64)
+    if n_params == 0:
+        return out
+    s = stream_seed(seed, item, P_PROWS)
+    h = draw(s, np.arange(n * (per + 1), dtype=np.uint64)).reshape(n, per + 1)
+    thr = bernoulli_threshold(frac)
+    for v in range(n):
+        if (h[v, 0] >> np.uint64(11)) >= thr:
+            continue
+        for t in range(per):
+            b = int((h[v, 1 + t] >> np.uint64(11)) % np.uint64(n_params))
+            out[v, b // 64] ^= np.uint64(1) << np.uint64(b % 64)
+    return out
