@@ -263,6 +263,21 @@ size_t zx_gf2_workspace_bytes(int32_t m, int32_t n_cols);
 zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
                            int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
                            uint64_t* T, int64_t ld_t, void* ws, size_t ws_bytes, hipStream_t s);
+/* Allocation-free elimination, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as
+ * zx_gf2_eliminate, without ws: the workspace is a static device array of
+ * the library, sized for m <= 16384 (658,176 bytes on every GPU the library
+ * runs on, held until the process ends; larger m returns ZX_ECAPACITY).  The
+ * call itself allocates nothing; its first call on a device looks up that
+ * device's copy of the array.  Every call on one GPU shares the array, which
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  No
+ * per-strip profile.  *rank_dev is -1 after the stream completes if the
+ * kernel detected a failure (spin-wait time-out). */
+zx_status zx_gf2_eliminate_noalloc(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
+                                   int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
+                                   uint64_t* T, int64_t ld_t, hipStream_t s);
 /* Sticky status of the last elimination that used this workspace (syncs). */
 zx_status zx_gf2_status(const void* ws, hipStream_t s);
 /* Per-strip timestamps (100 MHz real-time counter) of the last elimination in

@@ -43,6 +43,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "zx_internal.h"
 
 namespace {
@@ -88,17 +90,26 @@ struct WsLayout {
   size_t ctl, recs, snaps, piv_row, piv_col, prof, bytes;
 };
 
+constexpr size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace sections; the profile slots come last, so the bytes before
+// them (ws_core_bytes) serve an elimination without profiling.
 WsLayout ws_layout(int m) {
   WsLayout L;
   size_t o = 256;  // ZxWsHeader
-  L.ctl = o;     o += (sizeof(Ctl) + 255) & ~size_t(255);
-  L.recs = o;    o += ((sizeof(PassRec) * RING) + 255) & ~size_t(255);
-  L.snaps = o;   o += (((size_t)m * 4 * RING) + 255) & ~size_t(255);
-  L.piv_row = o; o += (((size_t)m * 4) + 255) & ~size_t(255);
-  L.piv_col = o; o += (((size_t)m * 4) + 255) & ~size_t(255);
-  L.prof = o;    o += ((size_t)MAX_STRIPS * PROF_SLOTS * 8 + 255) & ~size_t(255);
+  L.ctl = o;     o += al256(sizeof(Ctl));
+  L.recs = o;    o += al256(sizeof(PassRec) * RING);
+  L.snaps = o;   o += al256((size_t)m * 4 * RING);
+  L.piv_row = o; o += al256((size_t)m * 4);
+  L.piv_col = o; o += al256((size_t)m * 4);
+  L.prof = o;    o += al256((size_t)MAX_STRIPS * PROF_SLOTS * 8);
   L.bytes = o;
   return L;
+}
+
+constexpr size_t ws_core_bytes(int m) {
+  return 256 + al256(sizeof(Ctl)) + al256(sizeof(PassRec) * RING) + al256((size_t)m * 4 * RING) +
+         2 * al256((size_t)m * 4);
 }
 
 struct Args {
@@ -162,12 +173,13 @@ __device__ bool spin_until(const uint32_t* p, uint32_t target, const Args& a) {
   }
 }
 
-// Before every elimination: control words zero, and every ring slot filled
+// Before every elimination: rank -1, control words zero, every ring slot filled
 // with all-ones words (tag 2047), which no record matches before its slot is
 // rewritten (slot s holds records s, s + RING, ...), so that records left in
 // a reused workspace by an earlier launch are never taken for this one's.
-__global__ void rref_init(Ctl* ctl, PassRec* recs, int32_t* status, uint64_t* prof) {
+__global__ void rref_init(Ctl* ctl, PassRec* recs, int32_t* status, uint64_t* prof, int32_t* rank_dev) {
   const int t = threadIdx.x;
+  if (t == 0) *rank_dev = -1;  // stays -1 if the elimination fails on the device
   uint32_t* c = (uint32_t*)ctl;
   for (int i = t; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
   for (int i = t; i < RING * SW; i += blockDim.x) recs[i / SW].e[i % SW] = ~0ull;
@@ -1165,6 +1177,97 @@ size_t smem_bytes(int m, int cw) {
   return (size_t)smem_head_words() * 8 + (size_t)cw * ms * 8 + 2 * (ms / 64) * 8;
 }
 
+// Host-side argument checks shared by both elimination entry points.
+zx_status check_rref_args(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols, int64_t ld_words,
+                          int32_t* rank_dev, int32_t* pivot_cols_dev, uint64_t* T, int64_t ld_t) {
+  ZX_CHECK_ARG(A && R && rank_dev && pivot_cols_dev, "null argument");
+  ZX_CHECK_ARG(m > 0 && n_cols > 0, "empty matrix: m=%d n_cols=%d", m, n_cols);
+  const int nw_a = (n_cols + 63) / 64;
+  ZX_CHECK_ARG(ld_words >= nw_a, "ld_words %lld < %d", (long long)ld_words, nw_a);
+  const int mw = (m + 63) / 64;
+  if (T) {
+    ZX_CHECK_ARG(ld_t >= mw, "ld_t %lld < %d", (long long)ld_t, mw);
+    const char* t0 = (const char*)T;
+    const char* t1 = t0 + (size_t)m * ld_t * 8;
+    const char* a0 = (const char*)A;
+    const char* a1 = a0 + (size_t)m * ld_words * 8;
+    const char* r0 = (const char*)R;
+    const char* r1 = r0 + (size_t)m * ld_words * 8;
+    ZX_CHECK_ARG((t1 <= a0 || a1 <= t0) && (t1 <= r0 || r1 <= t0), "T overlaps A or R");
+  }
+  if (A != R) {
+    const char* a0 = (const char*)A;
+    const char* a1 = a0 + (size_t)m * ld_words * 8;
+    const char* r0 = (const char*)R;
+    const char* r1 = r0 + (size_t)m * ld_words * 8;
+    ZX_CHECK_ARG(a1 <= r0 || r1 <= a0, "A and R overlap without being equal");
+  }
+  if (m > MAX_M) {
+    zx_set_error("m=%d exceeds %d rows per LDS column", m, MAX_M);
+    return ZX_ECAPACITY;
+  }
+  return ZX_OK;
+}
+
+// Launch rref_init and rref_kernel with the workspace sections of an m-row
+// elimination at base (prof: record per-strip timestamps in its profile
+// section, which must then exist).
+zx_status launch_rref(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols, int64_t ld_words,
+                      int32_t* rank_dev, int32_t* pivot_cols_dev, uint64_t* T, int64_t ld_t, uint8_t* base,
+                      bool prof, hipStream_t s) {
+  const ZxDevice* dev = zx_device();
+  if (!dev) {
+    zx_set_error("no HIP device");
+    return ZX_EDEVICE;
+  }
+  const int nw_a = (n_cols + 63) / 64;
+  const int mw = (m + 63) / 64;
+  const int nw = nw_a + (T ? mw : 0);
+  // word columns per workgroup: the smallest count whose grid is co-resident
+  int cw = 1, G = 0;
+  size_t lds = 0;
+  for (cw = 1; cw <= MAX_CW; ++cw) {
+    lds = smem_bytes(m, cw);
+    if (lds > dev->lds_per_block) break;
+    G = (nw + cw - 1) / cw;
+    ZX_HIP(hipFuncSetAttribute((const void*)rref_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (G <= co_resident_blocks(lds)) break;
+    G = 0;
+  }
+  if (G == 0) {
+    zx_set_error("matrix %d x %d does not fit the co-resident grid", m, n_cols);
+    return ZX_ECAPACITY;
+  }
+  const WsLayout W = ws_layout(m);
+  Args a;
+  a.A = A;
+  a.R = R;
+  a.T = T;
+  a.ldt = T ? ld_t : 0;
+  a.m = m;
+  a.n_cols = n_cols;
+  a.nw = nw;
+  a.nw_a = nw_a;
+  a.cw = cw;
+  a.nstrips = (n_cols + SW - 1) / SW;
+  a.ld = ld_words;
+  a.rank_dev = rank_dev;
+  a.piv_dev = pivot_cols_dev;
+  a.status = (int32_t*)base;
+  a.ctl = (Ctl*)(base + W.ctl);
+  a.recs = (PassRec*)(base + W.recs);
+  a.snaps = (uint32_t*)(base + W.snaps);
+  a.piv_row = (int32_t*)(base + W.piv_row);
+  a.piv_col = (int32_t*)(base + W.piv_col);
+  a.spin_ticks = 100000000ull * 5;  // 5 s at the 100 MHz real-time counter
+  a.prof = prof ? (uint64_t*)(base + W.prof) : nullptr;
+  hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.recs, a.status, a.prof, a.rank_dev);
+  ZX_HIP(hipGetLastError());
+  void* args[] = {&a};
+  ZX_HIP(hipLaunchCooperativeKernel((const void*)rref_kernel, dim3(G), dim3(BS), args, (unsigned)lds, s));
+  return ZX_OK;
+}
+
 }  // namespace
 
 extern "C" size_t zx_gf2_workspace_bytes(int32_t m, int32_t n_cols) {
@@ -1197,86 +1300,66 @@ extern "C" zx_status zx_gf2_eliminate(const uint64_t* A, uint64_t* R, int32_t m,
                                       int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
                                       uint64_t* T, int64_t ld_t, void* ws, size_t ws_bytes, hipStream_t s) {
   zx_clear_error();
-  ZX_CHECK_ARG(A && R && rank_dev && pivot_cols_dev && ws, "null argument");
-  ZX_CHECK_ARG(m > 0 && n_cols > 0, "empty matrix: m=%d n_cols=%d", m, n_cols);
-  const int nw_a = (n_cols + 63) / 64;
-  ZX_CHECK_ARG(ld_words >= nw_a, "ld_words %lld < %d", (long long)ld_words, nw_a);
-  const int mw = (m + 63) / 64;
-  if (T) {
-    ZX_CHECK_ARG(ld_t >= mw, "ld_t %lld < %d", (long long)ld_t, mw);
-    const char* t0 = (const char*)T;
-    const char* t1 = t0 + (size_t)m * ld_t * 8;
-    const char* a0 = (const char*)A;
-    const char* a1 = a0 + (size_t)m * ld_words * 8;
-    const char* r0 = (const char*)R;
-    const char* r1 = r0 + (size_t)m * ld_words * 8;
-    ZX_CHECK_ARG((t1 <= a0 || a1 <= t0) && (t1 <= r0 || r1 <= t0), "T overlaps A or R");
-  }
-  const int nw = nw_a + (T ? mw : 0);
+  ZX_CHECK_ARG(ws, "null workspace");
+  zx_status rc = check_rref_args(A, R, m, n_cols, ld_words, rank_dev, pivot_cols_dev, T, ld_t);
+  if (rc != ZX_OK) return rc;
   ZX_CHECK_ARG(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
-  if (A != R) {
-    const char* a0 = (const char*)A;
-    const char* a1 = a0 + (size_t)m * ld_words * 8;
-    const char* r0 = (const char*)R;
-    const char* r1 = r0 + (size_t)m * ld_words * 8;
-    ZX_CHECK_ARG(a1 <= r0 || r1 <= a0, "A and R overlap without being equal");
-  }
-  if (m > MAX_M) {
-    zx_set_error("m=%d exceeds %d rows per LDS column", m, MAX_M);
-    return ZX_ECAPACITY;
-  }
-  WsLayout W = ws_layout(m);
+  const WsLayout W = ws_layout(m);
   if (ws_bytes < W.bytes) {
     zx_set_error("workspace %zu < %zu bytes", ws_bytes, W.bytes);
     return ZX_ECAPACITY;
   }
-  const ZxDevice* dev = zx_device();
-  if (!dev) {
-    zx_set_error("no HIP device");
-    return ZX_EDEVICE;
+  static const bool prof_on = getenv("ZX_RREF_PROFILE") && getenv("ZX_RREF_PROFILE")[0] == '1';
+  return launch_rref(A, R, m, n_cols, ld_words, rank_dev, pivot_cols_dev, T, ld_t, (uint8_t*)ws, prof_on, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free elimination.  Its workspace is this static device array,
+// sized for the largest m the kernel takes, without profile slots.  Each GPU
+// holds its own copy at its own address.  In host code the array's name is
+// only a stand-in for the device symbol: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is ever passed
+// to a kernel.
+static __device__ __align__(256) uint8_t scratch[ws_core_bytes(MAX_M)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of scratch on the current device (nullptr and the error
+// message set on failure).
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    zx_set_error("no current HIP device");
+    return nullptr;
   }
-  // word columns per workgroup: the smallest count whose grid is co-resident
-  int cw = 1, G = 0;
-  size_t lds = 0;
-  for (cw = 1; cw <= MAX_CW; ++cw) {
-    lds = smem_bytes(m, cw);
-    if (lds > dev->lds_per_block) break;
-    G = (nw + cw - 1) / cw;
-    ZX_HIP(hipFuncSetAttribute((const void*)rref_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (G <= co_resident_blocks(lds)) break;
-    G = 0;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      zx_set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
   }
-  if (G == 0) {
-    zx_set_error("matrix %d x %d does not fit the co-resident grid", m, n_cols);
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" zx_status zx_gf2_eliminate_noalloc(const uint64_t* A, uint64_t* R, int32_t m, int32_t n_cols,
+                                              int64_t ld_words, int32_t* rank_dev, int32_t* pivot_cols_dev,
+                                              uint64_t* T, int64_t ld_t, hipStream_t s) {
+  zx_clear_error();
+  zx_status rc = check_rref_args(A, R, m, n_cols, ld_words, rank_dev, pivot_cols_dev, T, ld_t);
+  if (rc != ZX_OK) return rc;
+  if (ws_core_bytes(m) > sizeof(scratch)) {
+    zx_set_error("m=%d needs %zu scratch bytes > %zu", m, ws_core_bytes(m), sizeof(scratch));
     return ZX_ECAPACITY;
   }
-  uint8_t* base = (uint8_t*)ws;
-  Args a;
-  a.A = A;
-  a.R = R;
-  a.T = T;
-  a.ldt = T ? ld_t : 0;
-  a.m = m;
-  a.n_cols = n_cols;
-  a.nw = nw;
-  a.nw_a = nw_a;
-  a.cw = cw;
-  a.nstrips = (n_cols + SW - 1) / SW;
-  a.ld = ld_words;
-  a.rank_dev = rank_dev;
-  a.piv_dev = pivot_cols_dev;
-  a.status = (int32_t*)base;
-  a.ctl = (Ctl*)(base + W.ctl);
-  a.recs = (PassRec*)(base + W.recs);
-  a.snaps = (uint32_t*)(base + W.snaps);
-  a.piv_row = (int32_t*)(base + W.piv_row);
-  a.piv_col = (int32_t*)(base + W.piv_col);
-  a.spin_ticks = 100000000ull * 5;  // 5 s at the 100 MHz real-time counter
-  static const bool prof_on = getenv("ZX_RREF_PROFILE") && getenv("ZX_RREF_PROFILE")[0] == '1';
-  a.prof = prof_on ? (uint64_t*)(base + W.prof) : nullptr;
-  hipLaunchKernelGGL(rref_init, dim3(1), dim3(256), 0, s, a.ctl, a.recs, a.status, a.prof);
-  ZX_HIP(hipGetLastError());
-  void* args[] = {&a};
-  ZX_HIP(hipLaunchCooperativeKernel((const void*)rref_kernel, dim3(G), dim3(BS), args, (unsigned)lds, s));
-  return ZX_OK;
+  uint8_t* base = (uint8_t*)scratch_address();
+  if (!base) return ZX_EDEVICE;
+  return launch_rref(A, R, m, n_cols, ld_words, rank_dev, pivot_cols_dev, T, ld_t, base, false, s);
 }

@@ -113,6 +113,7 @@ def load():
         "zx_batch_destroy": ([P], None),
         "zx_gf2_workspace_bytes": ([i32, i32], sz),
         "zx_gf2_eliminate": ([P, P, i32, i32, i64, P, P, P, i64, P, sz, P], i32),
+        "zx_gf2_eliminate_noalloc": ([P, P, i32, i32, i64, P, P, P, i64, P], i32),
         "zx_gf2_status": ([P, P], i32),
         "zx_gf2_profile_read": ([P, i32, P, i32, P], i32),
         "zx_pauli_commute": ([P, P, i64, i32, i64, P, i64, u32, P], i32),
@@ -153,7 +154,7 @@ def exported_symbols():
             "zx_local_comp", "zx_pivot", "zx_simplify_variants", "zx_simplify_variant_name",
             "zx_simplify_workspace_bytes", "zx_simplify", "zx_batch_prepare", "zx_batch_simplify",
             "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
-            "zx_gf2_eliminate", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
+            "zx_gf2_eliminate", "zx_gf2_eliminate_noalloc", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
             "zx_gf2_matmul", "zx_phase_pair_product", "zx_detector_workspace_bytes",
             "zx_detector_sample", "zx_detector_status",
             "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
@@ -544,6 +545,18 @@ def gf2_eliminate(A, R=None, n_cols=None, rank=None, pivots=None, ws=None, strea
                                    _ptr(T) if T is not None else None, ldt, _ptr(ws), ws.numel(),
                                    _stream(stream)))
     return R, rank, pivots, ws
+
+
+def gf2_eliminate_noalloc(A, R, rank, pivots, n_cols=None, stream=None, T=None):
+    """RREF of A into the caller's R, rank and pivots tensors through the
+    allocation-free entry point (workspace: the library's static device
+    array).  Returns R."""
+    m, ld = A.shape
+    n_cols = 64 * ld if n_cols is None else n_cols
+    ldt = T.shape[1] if T is not None else 0
+    _check(load().zx_gf2_eliminate_noalloc(_ptr(A), _ptr(R), m, n_cols, ld, _ptr(rank), _ptr(pivots),
+                                           _ptr(T) if T is not None else None, ldt, _stream(stream)))
+    return R
 
 
 def gf2_basis(D, n_cols, stream=None):

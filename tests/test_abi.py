@@ -53,6 +53,12 @@ def test_host_argument_errors(lib):
                                 None) == zx.ZX_EINVAL
     assert lib.zx_gf2_eliminate(P(4096), P(4096), 4, 64, 1, dummy, dummy, P(4096), 1, dummy, 1 << 20,
                                 None) == zx.ZX_EINVAL
+    # the allocation-free elimination: same checks, and m beyond its static scratch
+    assert lib.zx_gf2_eliminate_noalloc(None, None, 4, 64, 1, None, None, None, 0, None) == zx.ZX_EINVAL
+    assert lib.zx_gf2_eliminate_noalloc(dummy, dummy, 0, 64, 1, dummy, dummy, None, 0, None) == zx.ZX_EINVAL
+    assert lib.zx_gf2_eliminate_noalloc(dummy, dummy, 16385, 64, 1, dummy, dummy, None, 0,
+                                        None) == zx.ZX_ECAPACITY
+    assert b"16385" in lib.zx_last_error()
     assert lib.zx_pauli_commute(None, None, 10, 10, 1, None, 1, 0, None) == zx.ZX_EINVAL
     assert lib.zx_local_comp(None, 0, 0, None) == zx.ZX_EINVAL
     assert lib.zx_batch_simplify(None, None, None) == zx.ZX_EINVAL
