@@ -560,7 +560,9 @@ int or_detector_sample(int n_err, int n_f, const int32_t* col_ptr, const int32_t
     if (prob[j] > pmax) pmax = prob[j];
   }
   const double two53 = 9007199254740992.0;
-  const double log1m = log(1.0 - pmax);  /* -inf when pmax = 1 */
+  /* ln(1 - pmax) through log1p: log(1.0 - pmax) rounds to 0 for pmax below
+   * 2^-53, which would make every gap -inf */
+  const double log1m = log1p(-pmax);  /* -inf when pmax = 1 */
   for (int64_t i = 0; i < n_shots; ++i) {
     uint64_t* row = F + (size_t)i * ldf;
     memset(row, 0, sizeof(uint64_t) * (size_t)ldf);
@@ -573,7 +575,7 @@ int or_detector_sample(int n_err, int n_f, const int32_t* col_ptr, const int32_t
       if (pmax < 1.0) {
         const double U = (double)((sm_draw(seed, base + t++) >> 11) + 1) / two53;
         const double g = floor(log(U) / log1m);
-        if (g >= (double)(n_err - pos)) break;
+        if (!(g < (double)(n_err - pos))) break;  /* also ends on a NaN quotient */
         gap = (int64_t)g;
       }
       pos += gap;

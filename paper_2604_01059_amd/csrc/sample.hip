@@ -80,7 +80,7 @@ __global__ __launch_bounds__(DS_BS) void det_prep_kernel(const int32_t* __restri
   if (threadIdx.x == 0) {
     ws->hdr.status = 0;
     ws->pmax = pmax;
-    ws->log1m = log(1.0 - pmax);
+    ws->log1m = log1p(-pmax);  // log(1 - pmax) would round to 0 below pmax = 2^-53
     ws->valid = 1;
   }
 }
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(DS_BS) void det_sample_kernel(const int32_t* __rest
         state += gamma;
         const double U = (double)((sm_mix(state) >> 11) + 1) / two53;
         const double g = floor(log(U) / log1m);
-        if (g >= (double)(n_err - pos)) break;
+        if (!(g < (double)(n_err - pos))) break;  // a NaN quotient ends the shot too
         pos += (int64_t)g;
       }
       if (pos >= n_err) break;

@@ -30,7 +30,8 @@ def test_wide_rows_and_deterministic_cases(zx):
     fw = (M.n_f + 63) // 64
     # ld_out beyond the row: the extra words are not written
     out = torch.full((300, fw + 3), -1, dtype=torch.int64, device="cuda")
-    for prob in (np.zeros(M.n_err), np.ones(M.n_err), (np.arange(M.n_err) % 4 == 1) * 1.0, M.prob):
+    for prob in (np.zeros(M.n_err), np.ones(M.n_err), (np.arange(M.n_err) % 4 == 1) * 1.0, M.prob,
+                 np.full(M.n_err, 1e-18)):
         S = zx.DetectorSampler(M.col_ptr, M.col_idx, prob, M.n_f)
         S.sample(5, 0, 300, out=out)
         torch.cuda.synchronize()
