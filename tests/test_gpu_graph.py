@@ -116,8 +116,8 @@ def check_simplified(zg, d, extract=True, ctx=""):
 
 
 def test_single_diagram_workload(zx):
-    """8 qubits, 64 spiders, ER p = 0.1: seeds 1..200 in one batch."""
-    ds = [single_diagram(s) for s in range(1, 201)]
+    """8 qubits, 64 spiders, ER p = 0.1: all seeds 1..1000 in one batch."""
+    ds = [single_diagram(s) for s in range(1, 1001)]
     gs = [zx.Graph.from_diagram(d) for d in ds]
     zx.simplify(gs, extract=True)
     for s, (g, d) in enumerate(zip(gs, ds), start=1):
