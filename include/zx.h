@@ -92,7 +92,7 @@ typedef struct {
   int32_t rounds;      /* rewrite rounds of the last zx_simplify */
   int64_t fill_in;     /* edges toggled on by rewrites */
   int32_t rank;        /* rank of the output frontier (-1 if not extracted) */
-  int32_t pad;
+  int32_t policy;      /* schedule of the CURRENT diagram (ZX_POLICY_*) */
   int64_t rowops;      /* row additions of the frontier elimination */
 } zx_graph_info;
 
@@ -198,6 +198,16 @@ zx_status zx_pivot(zx_graph* g, int32_t u, int32_t v, uint32_t flags, hipStream_
  * ZX rewrites whatever the scores; only the schedule differs. */
 #define ZX_POLICY_LEARNED 1
 #define ZX_RESUME 0x2u   /* continue from the CURRENT diagram, trace and round count */
+/* Greedy fallback (with ZX_POLICY_LEARNED): per diagram, the greedy schedule
+ * also runs (its result is not kept), and the CURRENT diagram ends as the
+ * learned result when its gate2q -- Hadamard edges left plus, with extract,
+ * the row additions of the output frontier -- is not above the greedy one,
+ * else as the greedy result (the greedy schedule runs again to write it,
+ * trace included).  A diagram beyond the learned policy's LDS budget, or
+ * whose learned run fails on the device, gets the greedy result.
+ * zx_graph_info.policy tells which schedule the arena holds.  Not combined
+ * with max_rounds or ZX_RESUME (ZX_EINVAL). */
+#define ZX_FALLBACK 0x4u
 
 typedef struct zx_mlp zx_mlp;
 
@@ -509,9 +519,12 @@ typedef struct {
   int32_t status;               /* sticky status of the request's diagram */
   int32_t n_alive, rounds, n_trace, rank, phase8;
   int64_t n_edges, rowops, pow_sqrt2, fill_in;
-  double t_submit, t_launch, t_done;  /* host steady clock, seconds; t_launch =
-                                         t_submit (requests start as soon as a
-                                         workgroup is free) */
+  int32_t policy;               /* schedule of the result (ZX_POLICY_*) */
+  int32_t pad;
+  double t_submit, t_launch, t_done;  /* host steady clock, seconds: submission,
+                                         start on the device, result seen by poll */
+  double t_device;              /* seconds from a workgroup claiming the request
+                                   to its result written (device clock) */
 } zx_result;
 
 typedef struct {
@@ -524,8 +537,9 @@ typedef struct {
 /* pool: device memory owned by the caller (256-byte aligned) that the server
  * uses for a 256-byte control block and the request arenas.  max_batch is
  * kept for compatibility (the ring holds 65536 requests).  o: policy and
- * extract (tune_id and max_rounds are ignored); NULL = greedy with
- * extraction.  Requests up to 8192 spiders (4096 with the learned policy). */
+ * extract and flags (ZX_FALLBACK; tune_id and max_rounds are ignored); NULL
+ * = greedy with extraction.  Requests up to 8192 spiders (4096 with the
+ * learned policy without ZX_FALLBACK; with it, larger requests run greedy). */
 zx_status zx_server_create(zx_server** sv, void* pool, size_t pool_bytes, int32_t max_batch,
                            const zx_simplify_opts* o, uint32_t flags);
 /* Validate and upload a request (synchronous for the host arrays).

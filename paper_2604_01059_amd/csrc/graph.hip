@@ -119,6 +119,11 @@ __device__ __forceinline__ uint64_t wave_shfl64(uint64_t v, int src, int width) 
 // visibly uniform to the compiler: branches and loop bounds on it then
 // compile to scalar control flow instead of exec-mask control flow.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // Lane l's 64-bit value, to every lane.  The builtin returns a signed int:
 // each half is taken as uint32 so that the low word is not sign-extended.
@@ -828,6 +833,10 @@ __device__ __forceinline__ bool par_nonzero(const uint64_t* par, int pw, int v) 
   return o != 0;
 }
 
+// The two parameter steps are kept out of line and called only for diagrams
+// with parameters: inlined, their registers pushed the greedy kernel from 120
+// to about 184 VGPRs (two waves per SIMD instead of four) for every diagram.
+//
 // Terms of the round's rewrites whose scalar depends on the parameters, in
 // trace order (ascending spider for local complementation, ascending lower
 // end for pivots; slist is ascending).  Local complementation at u with
@@ -840,7 +849,7 @@ __device__ __forceinline__ bool par_nonzero(const uint64_t* par, int pw, int v) 
 // Reads only phases, partners and parameter rows of the selected spiders,
 // none of which the round has changed yet.
 template <int BS, bool LA>
-__device__ void terms_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+__device__ __noinline__ void terms_round(Ctx<LA>& c, Shared& sh, bool pivot) {
   if (!c.pw) return;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x, pw = c.pw, ns = uni(sh.ns);
@@ -903,7 +912,7 @@ __device__ void terms_round(Ctx<LA>& c, Shared& sh, bool pivot) {
 // thread per (present unselected row, parameter word); runs before the
 // round changes any unselected row (selected columns are still set).
 template <int BS, bool LA>
-__device__ void param_round(Ctx<LA>& c, Shared& sh, bool pivot) {
+__device__ __noinline__ void param_round(Ctx<LA>& c, Shared& sh, bool pivot) {
   if (!c.pw) return;
   const int pw = c.pw, n = c.n, nsw = uni(sh.nsw);
   const LDSP int32_t* sw = (const LDSP int32_t*)c.blocked;
@@ -967,8 +976,10 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     trace_lc_round<BS, LA>(c, sh);
     prepare_round<BS, LA>(c, sh, false, false);
     collect_swords<BS, LA>(c, sh);
-    terms_round<BS, LA>(c, sh, false);
-    param_round<BS, LA>(c, sh, false);
+    if (c.pw) {
+      terms_round<BS, LA>(c, sh, false);
+      param_round<BS, LA>(c, sh, false);
+    }
     const bool cc = apply_round<BS, LA>(c, sh, false);
     delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, removed);
@@ -988,8 +999,10 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     if (npairs == 0) break;
     prepare_round<BS, LA>(c, sh, true, false);
     collect_swords<BS, LA>(c, sh);
-    terms_round<BS, LA>(c, sh, true);
-    param_round<BS, LA>(c, sh, true);
+    if (c.pw) {
+      terms_round<BS, LA>(c, sh, true);
+      param_round<BS, LA>(c, sh, true);
+    }
     const bool cc = apply_round<BS, LA>(c, sh, true);
     delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, 2 * npairs);
@@ -1101,7 +1114,7 @@ struct SimpArgs {
   int32_t extract;
   int32_t max_rounds;  // 0: to the fixed point
   int32_t resume;      // continue from the CURRENT diagram
-  int32_t pad;
+  int32_t fallback;    // learned policy: keep the greedy result where its gate2q is lower
   const uint16_t* wbf;  // learned policy: network (bf16 copy)
   const float* param;   // learned policy: network (fp32 master)
 };
@@ -1142,19 +1155,83 @@ __device__ void run_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Sha
     uint64_t* M = LA ? (uint64_t*)lds : (uint64_t*)(arena + h->off_front);
     __syncthreads();
     frontier<BS, LA>(c, sh, M, false, true);
-  } else if (threadIdx.x == 0) {
-    h->rank = -1;
-    h->rowops = 0;
+  } else {
+    if (threadIdx.x == 0) {
+      h->rank = -1;
+      h->rowops = 0;
+      sh.rowops = 0;
+    }
   }
+  if (threadIdx.x == 0) h->policy_used = LEARN ? ZX_POLICY_LEARNED : ZX_POLICY_GREEDY;
   __syncthreads();
+}
+
+// gate2q of the greedy schedule without keeping its result: Hadamard edges
+// left plus the row additions of the output frontier.  Reads SOURCE; writes
+// nothing a later run from SOURCE does not overwrite (arena mode works in
+// the CURRENT adjacency, the frontier goes to the arena's frontier section);
+// no trace, no parameter rows, no header fields.
+template <int BS, bool LA>
+__device__ int64_t greedy_cost(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Shared& sh) {
+  ZxHeader* h = (ZxHeader*)arena;
+  Ctx<LA> c;
+  setup_ctx<BS, LA>(c, arena, lds);
+  c.trace = nullptr;
+  c.pw = 0;
+  c.par = nullptr;
+  c.terms = nullptr;
+  load_state<BS, LA>(c, sh, true);
+  if constexpr (!LA) {
+    uint8_t* at = align16(lds + aux_bytes(c.n, c.W));
+    const int64_t free_bytes = a.lds_cap - (int64_t)(at - lds);
+    c.scr = (LDSP uint64_t*)at;
+    c.scr_words = free_bytes > 0 ? (int)(free_bytes / 8) : 0;
+  }
+  simplify_rounds<BS, LA, false>(c, sh, nullptr, 0);
+  int64_t rowops = 0;
+  if (a.extract && c.q_out > 0) {
+    __syncthreads();
+    frontier<BS, LA>(c, sh, (uint64_t*)(arena + h->off_front), true, false);
+    rowops = uni64(sh.rowops);
+  }
+  const bool ok = uni(sh.status) == 0;
+  const int64_t cost = uni64(sh.E) + rowops;
+  __syncthreads();
+  return ok ? cost : INT64_MAX;
 }
 
 template <int BS, bool LEARN>
 __device__ void process_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Shared& sh) {
   ZxHeader* h = (ZxHeader*)arena;
-  const int n = h->n, W = h->W;
-  const int64_t aux = aux_bytes(n, W) + (LEARN ? pol_bytes(n, BS) : 0);
-  if (h->magic != ZX_MAGIC || n < 1 || W != (n + 63) / 64 || W > MAXW || n > 32767 || aux > a.lds_cap) {
+  const int n = uni(h->n), W = uni(h->W);
+  const int64_t aux_g = aux_bytes(n, W);
+  const int64_t aux = aux_g + (LEARN ? pol_bytes(n, BS) : 0);
+  const bool valid = uni(h->magic) == ZX_MAGIC && n >= 1 && W == (n + 63) / 64 && W <= MAXW && n <= 32767;
+  if constexpr (LEARN) {
+    // Greedy fallback: the learned schedule where it fits and its gate2q is
+    // not above the greedy one's, else the greedy schedule.
+    if (a.fallback && valid && aux_g <= a.lds_cap) {
+      const bool la_g = lds_adj_bytes(n, W) + aux_g <= a.lds_cap;
+      const int32_t st0 = uni(h->status);
+      bool learned_kept = false;
+      if (aux <= a.lds_cap) {
+        const int64_t cg = la_g ? greedy_cost<BS, true>(arena, lds, a, sh) : greedy_cost<BS, false>(arena, lds, a, sh);
+        if (lds_adj_bytes(n, W) + aux <= a.lds_cap) run_diagram<BS, true, true>(arena, lds, a, sh);
+        else run_diagram<BS, false, true>(arena, lds, a, sh);
+        const int64_t cl = uni(sh.status) == 0 ? uni64(sh.E) + uni64(sh.rowops) : INT64_MAX;
+        learned_kept = cl <= cg && cl != INT64_MAX;
+        __syncthreads();
+      }
+      if (!learned_kept) {
+        if (threadIdx.x == 0) h->status = st0;  // a failed learned run does not stick to the greedy result
+        __syncthreads();
+        if (la_g) run_diagram<BS, true, false>(arena, lds, a, sh);
+        else run_diagram<BS, false, false>(arena, lds, a, sh);
+      }
+      return;
+    }
+  }
+  if (!valid || aux > a.lds_cap) {
     if (threadIdx.x == 0) zx_dev_fail(&h->status, ZX_ECAPACITY);
     __syncthreads();
     return;
@@ -1347,11 +1424,6 @@ __global__ __launch_bounds__(BS) void features_kernel(FeatArgs a) {
 }
 
 // ------------------------------------------------------------- serving --
-__device__ __forceinline__ int64_t uni64(int64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 
 // Resident serving kernel: each workgroup claims the next ring entry (in
 // submission order), simplifies that diagram, publishes its summary and the
@@ -1389,6 +1461,7 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
     if (idx == -2) break;
     if (idx >= 0) {
       const int64_t slot = idx & (a.cap - 1);
+      const uint64_t t_claim = wall_clock64();
       uint8_t* arena =
           (uint8_t*)uni64((int64_t)__hip_atomic_load(&a.entries[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
       process_diagram<BS, LEARN>(arena, smem_dyn, sa, sh);
@@ -1406,6 +1479,10 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
         r->rowops = h->rowops;
         r->pow_sqrt2 = h->pow_sqrt2;
         r->fill_in = h->fill_in;
+        r->policy = h->policy_used;
+        r->pad = 0;
+        r->t_claim = t_claim;
+        r->t_end = wall_clock64();
         __threadfence_system();
         __hip_atomic_store(&a.done[slot], idx + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         last = wall_clock64();
@@ -1728,7 +1805,7 @@ static SimpArgs simp_args(const zx_simplify_opts* o) {
   a.extract = o->extract;
   a.max_rounds = o->max_rounds > 0 ? o->max_rounds : 0;
   a.resume = (o->flags & ZX_RESUME) ? 1 : 0;
-  a.pad = 0;
+  a.fallback = (o->policy == ZX_POLICY_LEARNED && (o->flags & ZX_FALLBACK)) ? 1 : 0;
   a.wbf = o->mlp ? o->mlp->wbf16 : nullptr;
   a.param = o->mlp ? o->mlp->param : nullptr;
   return a;
@@ -1768,7 +1845,7 @@ zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s) {
   if (!d) return ZX_EDEVICE;
   constexpr int BS = 512;
   const int v = 4;  // bs512-lds64k: two workgroups per CU
-  zx_simplify_opts o = {a.policy, a.extract, -1, 0, 0, 0, a.mlp};
+  zx_simplify_opts o = {a.policy, a.extract, -1, a.fallback ? ZX_FALLBACK : 0u, 0, 0, a.mlp};
   SimpArgs sa = simp_args(&o);
   sa.lds_cap = kVariants[v].lds_cap;
   const bool learned = a.policy == ZX_POLICY_LEARNED;
@@ -1800,8 +1877,13 @@ extern "C" zx_status zx_batch_simplify(zx_batch* b, const zx_simplify_opts* o, h
   if (learned)
     ZX_CHECK_ARG(o->mlp && o->mlp->param && o->mlp->wbf16, "learned policy needs a network");
   ZX_CHECK_ARG(o->max_rounds >= 0, "negative max_rounds");
-  const int v = pick_variant(b, o->tune_id, learned);
-  if (!variant_fits(b, v, learned)) {
+  const bool fb = learned && (o->flags & ZX_FALLBACK);
+  ZX_CHECK_ARG(!fb || (o->max_rounds == 0 && !(o->flags & ZX_RESUME)),
+               "ZX_FALLBACK compares whole schedules: no max_rounds, no ZX_RESUME");
+  int v = pick_variant(b, o->tune_id, learned);
+  // with the fallback, diagrams beyond the learned policy's LDS budget run greedy
+  if (fb && !variant_fits(b, v, true) && o->tune_id < 0) v = pick_variant(b, o->tune_id, false);
+  if (!variant_fits(b, v, learned && !fb)) {
     zx_set_error("diagrams too large for simplify variant %d", v);
     return ZX_ECAPACITY;
   }

@@ -110,40 +110,63 @@ __device__ float pauli_mask_and_scale(Ctx<LA>& c, Shared& sh) {
 
 // The seven features of endpoint x into f[0..6] (one wavefront; lane 0
 // writes).  Two-hop set: OR of the neighbours' rows minus N[x].
+// Lanes form Q groups of Wp (Wp = W rounded up to a power of two, Q = 64 / Wp
+// capped at 8; one group of 64 lanes with two words each beyond 64 words):
+// lane (g, j) ORs word j of every neighbour whose place in the neighbour
+// order is g mod Q.  Neighbours are taken eight at a time from the row's
+// words, so each LDS load instruction reads Q neighbour rows and eight are
+// in flight per pass; the groups' ORs are merged by lane shuffles.
 template <bool LA>
 __device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* f) {
   const int lane = threadIdx.x & 63, W = c.W;
   const auto rx = row_ptr(c, x);
-  uint64_t acc[MAXS], own[MAXS];
-#pragma unroll
-  for (int s = 0; s < MAXS; ++s) {
-    const int j = lane + 64 * s;
-    acc[s] = 0;
-    own[s] = j < W ? rx[j] : 0;
-  }
+  int Wp = 1;
+  while (Wp < W && Wp < 64) Wp <<= 1;
+  const int Q = W <= 64 ? (64 / Wp < 8 ? 64 / Wp : 8) : 1;
+  const int g = lane / Wp, jl = lane - g * Wp;
+  const bool act = g < Q && jl < W;
+  const bool two = W > 64 && jl + 64 < W;
+  uint64_t acc[MAXS] = {0, 0}, own[MAXS];
+  own[0] = jl < W ? rx[jl] : 0;
+  own[1] = two ? rx[jl + 64] : 0;
   for (int kw = 0; kw < W; ++kw) {
-    uint64_t m = rx[kw];  // same address in every lane
+    uint64_t m = (uint64_t)uni64((int64_t)rx[kw]);  // the same word in every lane
     while (m) {
-      const int b = __ffsll((long long)m) - 1;
-      m &= m - 1;
-      const auto rw = row_ptr(c, 64 * kw + b);
+      int nb[8];
 #pragma unroll
-      for (int s = 0; s < MAXS; ++s) {
-        const int j = lane + 64 * s;
-        if (j < W) acc[s] |= rw[j];
+      for (int t = 0; t < 8; ++t) {
+        nb[t] = m ? 64 * kw + __builtin_ctzll(m) : -1;
+        m &= m - 1;
+      }
+#pragma unroll
+      for (int t0 = 0; t0 < 8; ++t0) {
+        if (t0 % Q != 0 || nb[t0] < 0) continue;  // uniform
+        int w = nb[t0];
+#pragma unroll
+        for (int q = 1; q < 8; ++q)
+          if (t0 + q < 8 && q == g) w = nb[t0 + q];
+        if (act && w >= 0) {
+          const auto rw = row_ptr(c, w);
+          acc[0] |= rw[jl];
+          if (two) acc[1] |= rw[jl + 64];
+        }
       }
     }
+  }
+  for (int o = Wp; o < 64; o <<= 1) {
+    acc[0] |= (uint64_t)__shfl_xor((long long)acc[0], o);
+    acc[1] |= (uint64_t)__shfl_xor((long long)acc[1], o);
   }
   int deg = 0, bn = 0, th = 0, pn = 0;
 #pragma unroll
   for (int s = 0; s < MAXS; ++s) {
-    const int j = lane + 64 * s;
-    if (j < W) {
-      uint64_t two = acc[s] & ~own[s];
-      if (j == (x >> 6)) two &= ~(1ull << (x & 63));
+    const int j = jl + 64 * s;
+    if (g == 0 && j < W) {
+      uint64_t hop2 = acc[s] & ~own[s];
+      if (j == (x >> 6)) hop2 &= ~(1ull << (x & 63));
       deg += __popcll(own[s]);
       bn += __popcll(own[s] & c.bnd[j]);
-      th += __popcll(two);
+      th += __popcll(hop2);
       pn += __popcll(own[s] & c.inm[j]);
     }
   }

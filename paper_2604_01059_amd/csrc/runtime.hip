@@ -256,7 +256,7 @@ extern "C" zx_status zx_graph_read(const zx_graph* g, uint64_t* adj, int8_t* pha
     info->rounds = h.rounds;
     info->fill_in = h.fill_in;
     info->rank = h.rank;
-    info->pad = 0;
+    info->policy = h.policy_used;
     info->rowops = h.rowops;
   }
   return ZX_OK;

@@ -108,6 +108,7 @@ struct zx_server {
   int64_t oldest;  // smallest sequence number not yet harvested
   std::deque<zx_result> finished;
   int64_t submitted, refused, completed, launches;
+  double wall_hz;  // device wall clock (s_memrealtime) frequency
 };
 
 static zx_status relaunch(zx_server* S) {
@@ -123,6 +124,8 @@ static zx_status relaunch(zx_server* S) {
   a.extract = S->opts.extract;
   a.policy = S->opts.policy;
   a.mlp = S->opts.mlp;
+  a.fallback = (S->opts.policy == ZX_POLICY_LEARNED && (S->opts.flags & ZX_FALLBACK)) ? 1 : 0;
+  a.pad = 0;
   zx_status st = zx_launch_serve(a, S->stream);
   if (st != ZX_OK) return st;
   ZX_HIP(hipEventRecord(S->ended, S->stream));
@@ -154,9 +157,18 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   S->opts = *o;
   S->opts.tune_id = -1;
   S->opts.max_rounds = 0;
-  S->opts.flags = 0;
-  // the serving kernel runs 64 KiB workgroups
-  S->max_n = std::min(zx_max_spiders(o->policy), o->policy == ZX_POLICY_LEARNED ? 4096 : 8192);
+  S->opts.flags = o->flags & ZX_FALLBACK;
+  // the serving kernel runs 64 KiB workgroups; with the greedy fallback a
+  // request beyond the learned policy's budget runs greedy
+  const bool learned_only = o->policy == ZX_POLICY_LEARNED && !(o->flags & ZX_FALLBACK);
+  S->max_n = std::min(zx_max_spiders(learned_only ? ZX_POLICY_LEARNED : ZX_POLICY_GREEDY), learned_only ? 4096 : 8192);
+  S->wall_hz = 1e8;
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+        khz > 0)
+      S->wall_hz = 1e3 * khz;
+  }
   S->head = (int64_t*)S->pool;
   S->arenas = S->pool + head;
   S->alloc.init(pool_bytes - head);
@@ -283,9 +295,15 @@ extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, i
     r.rowops = d.rowops;
     r.pow_sqrt2 = d.pow_sqrt2;
     r.fill_in = d.fill_in;
+    r.policy = d.policy;
+    r.pad = 0;
     r.t_submit = q.t_submit;
-    r.t_launch = q.t_submit;
+    r.t_device = d.t_end > d.t_claim ? (double)(d.t_end - d.t_claim) / S->wall_hz : 0.0;
     r.t_done = t;
+    // start on the device, on the host clock: the poll that saw the result
+    // minus the device time (the lag between the result's write and this
+    // poll counts as device time)
+    r.t_launch = std::max(q.t_submit, t - r.t_device);
     S->finished.push_back(r);
     S->alloc.release(q.off, q.bytes);
     S->completed++;

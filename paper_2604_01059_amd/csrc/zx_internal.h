@@ -39,7 +39,7 @@ struct ZxHeader {
   int32_t n_params, pw;  // parameters, 64-bit words per parameter row
   int64_t off_src_par, off_par, off_terms;
   int32_t n_terms;       // phase-pair terms recorded
-  int32_t pad1;
+  int32_t policy_used;   // schedule of the CURRENT diagram: ZX_POLICY_GREEDY or ZX_POLICY_LEARNED
   int64_t reserved[2];
 };
 static_assert(sizeof(ZxHeader) <= 256, "header fits 256 bytes");
@@ -118,6 +118,8 @@ int32_t zx_max_spiders(int32_t policy);
 struct ZxServeRes {
   int32_t status, n_alive, rounds, n_trace, rank, phase8;
   int64_t n_edges, rowops, pow_sqrt2, fill_in;
+  int32_t policy, pad;
+  uint64_t t_claim, t_end;  // device wall clock: request claimed, result written
 };
 struct ZxServeArgs {
   uint64_t* entries;
@@ -131,6 +133,8 @@ struct ZxServeArgs {
   int32_t extract;
   int32_t policy;
   const zx_mlp* mlp;
+  int32_t fallback;  // learned policy: keep the greedy result where it is cheaper
+  int32_t pad;
 };
 // Launch the resident serving kernel on s (grid: 2 workgroups per CU).
 zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s);

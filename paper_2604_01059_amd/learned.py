@@ -14,8 +14,9 @@ a different cost.  This module learns an order.
 * Loss: softmax cross-entropy of the scores of a state's candidates toward
   its cheapest candidate (``zx_mlp_loss``).
 * Use: ``policy=ZX_POLICY_LEARNED`` takes each LC round's candidates in
-  descending score order; ``simplify_with_fallback`` keeps, per diagram, the
-  cheaper of the learned and the greedy result.
+  descending score order; with ``ZX_FALLBACK`` the library keeps, per
+  diagram, the cheaper of the learned and the greedy result
+  (``simplify_with_fallback``).
 
 Every step runs in the HIP library; this module only moves tensors.
 """
@@ -172,20 +173,12 @@ def evaluate(mlp: zx.MLP, n: int = 1024, seed: int = EVAL_SEED, q_lo: int = 32, 
 
 
 def simplify_with_fallback(graphs, mlp: zx.MLP):
-    """Simplify each graph with the learned policy and with the greedy one;
-    keep the cheaper result (gate2q) in ``graphs``.  Returns, per graph,
-    True where the learned result was kept."""
-    twins = [g.snapshot() for g in graphs]
-    zx.simplify(graphs, extract=True, policy=zx.ZX_POLICY_LEARNED, mlp=mlp)
-    zx.simplify(twins, extract=True)
-    kept = []
-    for g, t in zip(graphs, twins):
-        if gate2q(t.info()) < gate2q(g.info()):
-            g.arena.copy_(t.arena)
-            kept.append(False)
-        else:
-            kept.append(True)
-    return kept
+    """Simplify each graph with the learned policy and the library's greedy
+    fallback (ZX_FALLBACK): the arena keeps the learned result unless the
+    greedy one has lower gate2q.  Returns, per graph, True where the learned
+    result was kept."""
+    zx.simplify(graphs, extract=True, policy=zx.ZX_POLICY_LEARNED, mlp=mlp, fallback=True)
+    return [g.info().policy == zx.ZX_POLICY_LEARNED for g in graphs]
 
 
 def save(mlp: zx.MLP, path: str):

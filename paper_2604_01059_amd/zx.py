@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libzx.so")
 ZX_OK, ZX_EINVAL, ZX_ENOMATCH, ZX_ECAPACITY, ZX_EDEVICE, ZX_EBUSY = 0, -1, -2, -3, -4, -5
 ZX_GRAPH_ONLY = 0x1
 ZX_RESUME = 0x2
+ZX_FALLBACK = 0x4
 ZX_SYNC = 0x100
 ZX_POLICY_GREEDY, ZX_POLICY_LEARNED = 0, 1
 MLP_IN, MLP_HID = 16, 256
@@ -36,7 +37,7 @@ class GraphInfo(C.Structure):
     _fields_ = [("pow_sqrt2", C.c_int64), ("phase8", C.c_int32), ("status", C.c_int32),
                 ("n", C.c_int32), ("n_alive", C.c_int32), ("n_edges", C.c_int64),
                 ("n_trace", C.c_int32), ("rounds", C.c_int32), ("fill_in", C.c_int64),
-                ("rank", C.c_int32), ("pad", C.c_int32), ("rowops", C.c_int64)]
+                ("rank", C.c_int32), ("policy", C.c_int32), ("rowops", C.c_int64)]
 
 
 class MlpHandle(C.Structure):
@@ -59,7 +60,9 @@ class Result(C.Structure):
     _fields_ = [("ticket", C.c_int64), ("tag", C.c_int64), ("status", C.c_int32), ("n_alive", C.c_int32),
                 ("rounds", C.c_int32), ("n_trace", C.c_int32), ("rank", C.c_int32), ("phase8", C.c_int32),
                 ("n_edges", C.c_int64), ("rowops", C.c_int64), ("pow_sqrt2", C.c_int64), ("fill_in", C.c_int64),
-                ("t_submit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double)]
+                ("policy", C.c_int32), ("pad", C.c_int32),
+                ("t_submit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double),
+                ("t_device", C.c_double)]
 
 
 class ServerStats(C.Structure):
@@ -320,21 +323,23 @@ def _graph_array(graphs):
     return arr
 
 
-def _opts(extract, tune_id, policy, mlp, max_rounds, resume):
-    o = SimplifyOpts(policy, 1 if extract else 0, tune_id, ZX_RESUME if resume else 0, int(max_rounds), 0, None)
+def _opts(extract, tune_id, policy, mlp, max_rounds, resume, fallback=False):
+    flags = (ZX_RESUME if resume else 0) | (ZX_FALLBACK if fallback else 0)
+    o = SimplifyOpts(policy, 1 if extract else 0, tune_id, flags, int(max_rounds), 0, None)
     if mlp is not None:
         o.mlp = C.pointer(mlp.handle)
     return o
 
 
 def simplify(graphs, extract=True, tune_id=-1, ws=None, stream=None, policy=ZX_POLICY_GREEDY, mlp=None,
-             max_rounds=0, resume=False):
+             max_rounds=0, resume=False, fallback=False):
+    """fallback (learned policy): keep the greedy result where its gate2q is lower (ZX_FALLBACK)."""
     import torch
     n = len(graphs)
     nb = simplify_workspace_bytes(n)
     if ws is None:
         ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    opts = _opts(extract, tune_id, policy, mlp, max_rounds, resume)
+    opts = _opts(extract, tune_id, policy, mlp, max_rounds, resume, fallback)
     _check(load().zx_simplify(_graph_array(graphs), n, C.byref(opts), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
 
@@ -353,8 +358,8 @@ class Batch:
         self.h = h
 
     def run(self, extract=True, tune_id=-1, stream=None, policy=ZX_POLICY_GREEDY, mlp=None, max_rounds=0,
-            resume=False):
-        self._opts = _opts(extract, tune_id, policy, mlp, max_rounds, resume)
+            resume=False, fallback=False):
+        self._opts = _opts(extract, tune_id, policy, mlp, max_rounds, resume, fallback)
         _check(load().zx_batch_simplify(self.h, C.byref(self._opts), _stream(stream)))
 
     def status(self, stream=None):
@@ -433,11 +438,11 @@ class Server:
     """Continuous-batching simplification service over a device pool."""
 
     def __init__(self, pool_bytes, max_batch=1024, policy=ZX_POLICY_GREEDY, mlp=None, extract=True,
-                 trusted=False):
+                 trusted=False, fallback=False):
         import torch
         self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
         self.mlp = mlp
-        self._opts = _opts(extract, -1, policy, mlp, 0, False)
+        self._opts = _opts(extract, -1, policy, mlp, 0, False, fallback)
         h = C.c_void_p()
         _check(load().zx_server_create(C.byref(h), _ptr(self.pool), pool_bytes, max_batch, C.byref(self._opts),
                                        ZX_SERVE_TRUSTED if trusted else 0))

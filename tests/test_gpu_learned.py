@@ -267,3 +267,106 @@ def test_policy_features_match_oracle(zx, item):
     zg = zx.Graph.from_diagram(d)
     cand, feats, C = zx.policy_features(zg, max_cand=2)
     assert C == len(opol.candidate_list(oracle.Graph.from_diagram(d))) and len(cand) == min(C, 2)
+
+
+def replay_and_compare(zg, d, ctx):
+    tr = zg.trace()
+    g0 = oracle.Graph.from_diagram(d)
+    fin = opol.replay(g0, tr)
+    compare_state(zg, fin, ctx)
+    _, _, rank, ops = fin.frontier()
+    info = zg.info()
+    assert info.rank == rank and info.rowops == ops, ctx
+
+
+def test_learned_arena_mode_replays(zx):
+    """Learned runs on diagrams of 1190 to 1952 spiders (adjacency in the arena,
+    not in LDS), checked by replaying their traces on the oracle."""
+    rng = np.random.default_rng(21)
+    p = rand_param(rng, 0.5)
+    items = [8, 13, 19]
+    ds = [batch_diagram(42, i, q_lo=100, q_hi=128) for i in items]
+    assert all(1100 <= d.n <= 2048 for d in ds)
+    print("learned arena", [d.n for d in ds], flush=True)
+    gs = learned_run(zx, ds, p)
+    for i, (zg, d) in enumerate(zip(gs, ds)):
+        assert zg.info().policy == zx.ZX_POLICY_LEARNED
+        replay_and_compare(zg, d, ("arena", items[i], d.n))
+
+
+def gate2q(info):
+    return int(info.n_edges) + int(info.rowops)
+
+
+def test_fallback_keeps_the_cheaper_schedule(zx):
+    """ZX_FALLBACK: each arena ends with the learned result unless the greedy
+    one has lower gate2q, bit for bit as the separate runs, and says which."""
+    rng = np.random.default_rng(22)
+    p = rand_param(rng, 0.5)
+    ds = [batch_diagram(42, i, q_lo=32, q_hi=128) for i in range(40)]
+    m = make_mlp(zx, p)
+    G = [zx.Graph.from_diagram(d) for d in ds]
+    L = [zx.Graph.from_diagram(d) for d in ds]
+    F = [zx.Graph.from_diagram(d) for d in ds]
+    print("fallback", [d.n for d in ds], flush=True)
+    zx.simplify(G, extract=True)
+    zx.simplify(L, extract=True, policy=zx.ZX_POLICY_LEARNED, mlp=m)
+    zx.simplify(F, extract=True, policy=zx.ZX_POLICY_LEARNED, mlp=m, fallback=True)
+    kinds = set()
+    for i in range(len(ds)):
+        gi, li = G[i].info(), L[i].info()
+        exp, pol = (L[i], zx.ZX_POLICY_LEARNED) if gate2q(li) <= gate2q(gi) else (G[i], zx.ZX_POLICY_GREEDY)
+        kinds.add(pol)
+        fa, fp, fl, fi = F[i].read()
+        ea, ep, el, ei = exp.read()
+        assert fi.status == 0 and fi.policy == pol, i
+        assert np.array_equal(fa, ea) and np.array_equal(fp, ep) and np.array_equal(fl, el), i
+        for f in ("pow_sqrt2", "phase8", "n_edges", "n_alive", "fill_in", "rounds", "n_trace", "rank", "rowops"):
+            assert getattr(fi, f) == getattr(ei, f), (i, f)
+        np.testing.assert_array_equal(F[i].trace(), exp.trace())
+        assert np.array_equal(F[i].frontier()[0], exp.frontier()[0])
+    assert kinds == {zx.ZX_POLICY_LEARNED, zx.ZX_POLICY_GREEDY}, kinds
+    # the kept learned results are exact rewrites (oracle replay)
+    for i in range(6):
+        if F[i].info().policy == zx.ZX_POLICY_LEARNED:
+            replay_and_compare(F[i], ds[i], ("fallback", i))
+
+
+def test_fallback_rejects_partial_schedules(zx):
+    m = make_mlp(zx, rand_param(np.random.default_rng(3)))
+    g = zx.Graph.from_diagram(batch_diagram(42, 0))
+    with pytest.raises(zx.ZxError):
+        zx.simplify([g], policy=zx.ZX_POLICY_LEARNED, mlp=m, fallback=True, max_rounds=2)
+
+
+def test_serve_learned_with_fallback(zx):
+    """The server with the learned policy and the greedy fallback answers each
+    request with the stand-alone ZX_FALLBACK result of the same diagram."""
+    import time
+    from workloads import serve_diagram
+    rng = np.random.default_rng(23)
+    m = make_mlp(zx, rand_param(rng, 0.5))
+    ds = [serve_diagram(5, 3000 + i, q_hi=128) for i in range(48)]
+    ref = [zx.Graph.from_diagram(d) for d in ds]
+    zx.simplify(ref, extract=True, policy=zx.ZX_POLICY_LEARNED, mlp=m, fallback=True)
+    sv = zx.Server(512 << 20, policy=zx.ZX_POLICY_LEARNED, mlp=m, fallback=True)
+    print("serve learned", [d.n for d in ds], flush=True)
+    for i, d in enumerate(ds):
+        assert sv.submit(d, tag=i) is not None
+    res = []
+    t0 = time.time()
+    while len(res) < len(ds):
+        res += sv.poll()
+        assert time.time() - t0 < 100, "server did not finish"
+    pols = set()
+    for r in res:
+        e = ref[r.tag].info()
+        ctx = (r.tag, ds[r.tag].n)
+        assert r.status == 0 and e.status == 0, ctx
+        for f in ("n_edges", "n_alive", "pow_sqrt2", "phase8", "fill_in", "rounds", "n_trace", "rank", "rowops",
+                  "policy"):
+            assert getattr(r, f) == getattr(e, f), (ctx, f)
+        assert r.t_submit <= r.t_launch <= r.t_done and r.t_device > 0, ctx
+        pols.add(r.policy)
+    assert zx.ZX_POLICY_LEARNED in pols
+    sv.close()
