@@ -12,6 +12,7 @@ struct Pol {
   LDSP uint32_t* list;    // candidate spiders of an LC round
   LDSP uint64_t* key;     // sort keys, descending = priority order
   LDSP uint16_t* fbuf;    // per wavefront 32 x ZX_MLP_IN bf16 features
+  LDSP int32_t* thbuf;    // per wavefront 32 two-hop counts
 };
 
 __host__ __device__ inline int pol_cap(int n) {
@@ -21,7 +22,8 @@ __host__ __device__ inline int pol_cap(int n) {
 }
 __host__ __device__ inline int64_t pol_bytes(int n, int bs) {
   const int cap = pol_cap(n);
-  return 16 + (int64_t)cap * 4 + (int64_t)cap * 8 + (int64_t)(bs / 64) * 32 * zxmlp::IN * 2;
+  return 16 + (int64_t)cap * 4 + (int64_t)cap * 8 + (int64_t)(bs / 64) * 32 * zxmlp::IN * 2 +
+         (int64_t)(bs / 64) * 32 * 4;
 }
 
 // The feature rows are read 16 bytes at a time: start the area on 16 bytes.
@@ -38,6 +40,8 @@ __device__ void setup_pol(Pol& p, uint8_t* at, int n, const uint16_t* wbf, const
   p.list = (LDSP uint32_t*)at;
   at += (int64_t)p.cap * 4;
   p.fbuf = (LDSP uint16_t*)at;
+  at += (int64_t)(BS / 64) * 32 * zxmlp::IN * 2;
+  p.thbuf = (LDSP int32_t*)at;
 }
 
 // Exclusive prefix over the wavefront of values in [0, 127], and the total.
@@ -117,7 +121,7 @@ __device__ float pauli_mask_and_scale(Ctx<LA>& c, Shared& sh) {
 // words, so each LDS load instruction reads Q neighbour rows and eight are
 // in flight per pass; the groups' ORs are merged by lane shuffles.
 template <bool LA>
-__device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* f) {
+__device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* f, int th_given = -1) {
   const int lane = threadIdx.x & 63, W = c.W;
   const auto rx = row_ptr(c, x);
   int Wp = 1;
@@ -129,7 +133,7 @@ __device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* 
   uint64_t acc[MAXS] = {0, 0}, own[MAXS];
   own[0] = jl < W ? rx[jl] : 0;
   own[1] = two ? rx[jl + 64] : 0;
-  for (int kw = 0; kw < W; ++kw) {
+  for (int kw = 0; kw < (th_given < 0 ? W : 0); ++kw) {
     uint64_t m = (uint64_t)uni64((int64_t)rx[kw]);  // the same word in every lane
     while (m) {
       int nb[8];
@@ -172,7 +176,7 @@ __device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* 
   }
   deg = wave_sum8(deg);
   bn = wave_sum8(bn);
-  th = wave_sum8(th);
+  th = th_given < 0 ? wave_sum8(th) : th_given;
   pn = wave_sum8(pn);
   if (lane == 0) {
     const int k = c.k[x];
@@ -189,14 +193,81 @@ __device__ void endpoint_features(Ctx<LA>& c, int x, float invN, LDSP uint16_t* 
 // Features of LC candidate u into f[0..15] (one wavefront): its endpoint
 // features, zeros for the second endpoint, rule bit 0, constant 1.
 template <bool LA>
-__device__ void candidate_features(Ctx<LA>& c, int u, float invN, LDSP uint16_t* f) {
+__device__ void candidate_features(Ctx<LA>& c, int u, float invN, LDSP uint16_t* f, int th_given = -1) {
   const int lane = threadIdx.x & 63;
-  endpoint_features(c, u, invN, f);
+  endpoint_features(c, u, invN, f, th_given);
   if (lane < 7) f[7 + lane] = 0;
   if (lane == 0) {
     f[14] = zxmlp::to_bf16(0.f);
     f[15] = zxmlp::to_bf16(1.f);
   }
+}
+
+typedef int pol_v8i __attribute__((ext_vector_type(8)));
+typedef float pol_v16f __attribute__((ext_vector_type(16)));
+
+// 32 bits as 32 FP4 (E2M1) operand values of a 64-deep matrix-core product:
+// nibble r of dword t is bit 4r + t (code 1 = 0.5, or 0).
+__device__ __forceinline__ pol_v8i bits_fp4(uint32_t d) {
+  pol_v8i o;
+  o[0] = (int)(d & 0x11111111u);
+  o[1] = (int)((d >> 1) & 0x11111111u);
+  o[2] = (int)((d >> 2) & 0x11111111u);
+  o[3] = (int)((d >> 3) & 0x11111111u);
+  o[4] = o[5] = o[6] = o[7] = 0;
+  return o;
+}
+
+// Two-hop counts of candidates list[base + r], r < 32 (entries past C count
+// nothing), into th[r] (one wavefront): the spiders v other than x and not
+// adjacent to x that share a neighbour with x.  A x A counts the common
+// neighbours of the 32 candidates and 32 spiders v at a time on the matrix
+// cores (v_mfma_scale_f32_32x32x64_f8f6f4: a bit is the FP4 value 0.5 scaled
+// by 2^1 to 1, every sum an exact fp32 count below 2^13).  Each block's
+// accumulator first takes -12288 at v = x and at v adjacent to x (one more
+// product: x's row with its own bit against a one-hot operand of value -6
+// scaled by 2^11), so a positive sum marks exactly a two-hop spider; one
+// ballot per accumulator register counts them per candidate.
+template <bool LA>
+__device__ void two_hop32(Ctx<LA>& c, const LDSP uint32_t* list, int base, int C, LDSP int32_t* th) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+  const int n = c.n, W = c.W;
+  const int xr = base + l32 < C ? (int)list[base + l32] : -1;
+  const auto rx = row_ptr(c, xr < 0 ? 0 : xr);
+  int cnt[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) cnt[r] = 0;
+  for (int jb = 0; 32 * jb < n; ++jb) {
+    const int v = 32 * jb + l32;
+    const bool vin = v < n;
+    const auto rv = row_ptr(c, vin ? v : 0);
+    const int wj = jb >> 1;
+    uint64_t ax = xr >= 0 ? rx[wj] : 0;
+    if (xr >= 0 && (xr >> 6) == wj) ax |= 1ull << (xr & 63);
+    pol_v8i bo = bits_fp4(h == (jb & 1) && vin ? 1u << l32 : 0u);
+    bo[0] *= 15;  // nibble 0xF: -6
+    bo[1] *= 15;
+    bo[2] *= 15;
+    bo[3] *= 15;
+    pol_v16f acc = {};
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bits_fp4((uint32_t)(ax >> (32 * h))), bo, acc, 4, 4, 0,
+                                                          128, 0, 138);
+    for (int ks = 0; ks < W; ++ks) {
+      const uint32_t ad = xr >= 0 ? (uint32_t)(rx[ks] >> (32 * h)) : 0u;
+      const uint32_t bd = vin ? (uint32_t)(rv[ks] >> (32 * h)) : 0u;
+      acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bits_fp4(ad), bits_fp4(bd), acc, 4, 4, 0, 128, 0, 128);
+    }
+    // register r of lane (h, l32): candidate 8 (r / 4) + 4 h + r % 4, spider 32 jb + l32
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint64_t b = __ballot(acc[r] > 0.0f);
+      cnt[8 * (r >> 2) + (r & 3)] += __popcll(b & 0xffffffffull);
+      cnt[8 * (r >> 2) + 4 + (r & 3)] += __popcll(b >> 32);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 32; ++r)
+    if (lane == r) th[r] = cnt[r];
 }
 
 // Order-preserving map of a float onto uint32.
@@ -211,10 +282,14 @@ template <int BS, bool LA>
 __device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   LDSP uint16_t* fb = p.fbuf + wv * 32 * zxmlp::IN;
+  LDSP int32_t* tb = p.thbuf + wv * 32;
   for (int base = wv * 32; base < C; base += (BS / 64) * 32) {
+    two_hop32(c, p.list, base, C, tb);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
     for (int r = 0; r < 32; ++r) {
       LDSP uint16_t* f = fb + r * zxmlp::IN;
-      if (base + r < C) candidate_features(c, (int)p.list[base + r], invN, f);
+      if (base + r < C) candidate_features(c, (int)p.list[base + r], invN, f, uni(tb[r]));
       else if (lane < zxmlp::IN) f[lane] = 0;
     }
     __builtin_amdgcn_s_waitcnt(0);
