@@ -555,31 +555,78 @@ def _oracle_eval(d):
     return g.n_edges() + ops
 
 
+def _oracle_replay(args):
+    """Replay one learned trace on the oracle and compare the final state with
+    the GPU's (digests of adjacency, phases, alive mask; scalar; frontier)."""
+    import hashlib
+    import oracle
+    from oracle import policy as opol
+    from workloads import batch_diagram
+    item, trace, dig, scal = args
+    d = batch_diagram(42, item, q_lo=32, q_hi=128)
+    try:
+        fin = opol.replay(oracle.Graph.from_diagram(d), trace)
+    except AssertionError:
+        return False
+    h = lambda a: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+    rank, ops = -1, 0
+    if len(fin.outputs):
+        _, _, rank, ops = fin.frontier()
+    got = (h(fin.adj), h(fin.k), h(fin.alive), int(fin.scalar.pow_sqrt2), int(fin.scalar.phase8 % 8), int(rank),
+           int(ops))
+    return got == tuple(dig) + tuple(scal)
+
+
 def bench_learned(zx, args, pool):
     """Learned proposal: dataset from greedy runs (rollout labels), training
-    with the network kernels, evaluation on held-out diagrams vs greedy."""
+    with the network kernels, held-out ranking quality, evaluation on
+    held-out diagrams vs greedy and with the greedy fallback, every learned
+    trace replayed on the oracle."""
+    import hashlib
     import torch
     from paper_2604_01059_amd import learned
-    from workloads import batch_diagram
     t0 = time.perf_counter()
     mlp = learned.new_network()
-    feats, costs = learned.make_dataset(args.learned_states, per_state=16, log=log)
+    ev0 = learned.evaluate(mlp, n=1024)  # the untrained network, for comparison
+    feats, costs = learned.make_dataset(args.learned_states, per_state=16, log=log, label=args.learned_label)
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
     rollouts = int((costs >= 0).sum())
+    # held-out states: greedy runs of other diagrams of the same generator
+    vf, vc = learned.make_dataset(args.learned_val_states, per_state=16, first_item=1 << 20,
+                                  label=args.learned_label)
+    untrained = learned.state_metrics(mlp, vf, vc)
     t0 = time.perf_counter()
-    curve = learned.train(mlp, feats, costs, per_state=16, epochs=args.learned_epochs, log=log)
+    curve, val_curve = learned.train(mlp, feats, costs, per_state=16, epochs=args.learned_epochs, log=log,
+                                     val=(vf, vc))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    ev = learned.evaluate(mlp, n=1024)
-    out = dict(workload="train: %d greedy-run states of the batched generator (seed %d), 16 rollouts each; "
-                        "eval: 1024 diagrams q~U{32..128}, N=q*U{4..16}, seed %d"
-                        % (args.learned_states, learned.TRAIN_SEED, learned.EVAL_SEED),
-               dataset_s=round(data_s, 2), rollouts=rollouts, train_s=round(train_s, 2),
+    trained = learned.state_metrics(mlp, vf, vc)
+    ev, ds, lg, fg = learned.evaluate(mlp, n=1024, keep_graphs=True)
+    out = dict(workload="train: %d greedy-run states of the batched generator (seed %d) whose candidates differ "
+                        "in rollout %s, 16 rollouts each; held-out: %d states of other diagrams; eval: 1024 "
+                        "diagrams q~U{32..128}, N=q*U{4..16}, seed %d"
+                        % (args.learned_states, learned.TRAIN_SEED, args.learned_label, args.learned_val_states,
+                           learned.EVAL_SEED),
+               label=args.learned_label,
+               dataset_s=round(data_s, 2), rollouts=rollouts, train_s=round(train_s, 2), epochs=args.learned_epochs,
                loss_first=curve[0][1] if curve else None, loss_last=curve[-1][1] if curve else None,
-               loss_curve=curve[:: max(1, len(curve) // 12)], **ev)
+               loss_curve=curve[:: max(1, len(curve) // 12)], heldout_loss_per_epoch=val_curve,
+               heldout_untrained=untrained, heldout_trained=trained,
+               untrained_network={k: ev0[k] for k in ("gate2q_learned", "gate2q_fallback", "fill_learned",
+                                                      "fill_fallback", "learned_better", "learned_worse")},
+               **ev)
     if pool is not None:
-        ds = [batch_diagram(learned.EVAL_SEED, i, q_lo=32, q_hi=128) for i in range(1024)]
+        h = lambda a: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+        jobs = []
+        for i, g in enumerate(lg):
+            adj, ph, al, info = g.read()
+            jobs.append((i, g.trace(), (h(adj), h(ph), h(al)),
+                         (int(info.pow_sqrt2), int(info.phase8), int(info.rank), int(info.rowops))))
+        t0 = time.perf_counter()
+        ok = list(pool.map(_oracle_replay, jobs, chunksize=8))
+        out["learned_replay_exact"] = "%d/%d" % (sum(ok), len(ok))
+        out["replay_s"] = round(time.perf_counter() - t0, 1)
         t0 = time.perf_counter()
         costs_cpu = list(pool.map(_oracle_eval, ds, chunksize=8))
         out["cpu_baseline"] = {"value": round(1024 / (time.perf_counter() - t0), 1), "unit": "diagrams/s",
@@ -612,34 +659,81 @@ def bench_serve(zx, args, pool):
     start = time.perf_counter() + 0.05
     backlog = []
     lat, refused, nxt, done = [], 0, 0, 0
+    dev, queue, sizes = [], [], []
+    claim_dev, end_dev, done_host, arr_host = [], [], [], []
+    host_submit_s = host_poll_s = 0.0
     max_backlog = 0
+    last_log = 0.0
+    deadline = warm + dur + args.serve_drain
     while done < len(arr):
         now = time.perf_counter() - start
+        if now - last_log >= 5.0:
+            log("serve: t=%.1f s, %d arrived, %d submitted, %d done, %d waiting on the host"
+                % (now, nxt, nxt - len(backlog), done, len(backlog)))
+            last_log = now
+        if now > deadline:
+            log("serve: not drained %.0f s after the last arrival; stopping" % args.serve_drain)
+            break
         while nxt < len(arr) and arr[nxt] <= now:
             backlog.append(nxt)
             nxt += 1
+        ts = time.perf_counter()
         while backlog:
             i = backlog[0]
             if sv.submit(ds[i % n_unique], tag=i) is None:
                 refused += 1
                 break
             backlog.pop(0)
+        tp = time.perf_counter()
+        host_submit_s += tp - ts
         max_backlog = max(max_backlog, len(backlog))
-        for r in sv.poll():
+        got = sv.poll()
+        host_poll_s += time.perf_counter() - tp
+        for r in got:
             done += 1
             if arr[r.tag] >= warm:
                 lat.append(r.t_done - (start + arr[r.tag]))
+                dev.append(r.t_device)
+                queue.append(r.t_launch - (start + arr[r.tag]))
+                sizes.append(ds[r.tag % n_unique].n)
+                claim_dev.append(r.t_claim_dev)
+                end_dev.append(r.t_end_dev)
+                done_host.append(r.t_done)
+                arr_host.append(start + arr[r.tag])
     wall = time.perf_counter() - start
     st = sv.stats()
     sv.close()
-    lat = np.array(lat)
+    drained = done == len(arr)
+    # device clock on the host clock: the smallest (seen - written) gap is
+    # taken as a poll lag of zero; then submit -> claim is the true queue,
+    # claim -> written the device time, written -> seen the host's lag
+    if end_dev:
+        ce, ee, dh, ah = map(np.array, (claim_dev, end_dev, done_host, arr_host))
+        off = float(np.min(dh - ee))
+        true_queue = (ce + off) - ah
+        lag = dh - (ee + off)
+    else:
+        true_queue = lag = np.array([])
+    lat, dev, queue, sizes = np.array(lat), np.array(dev), np.array(queue), np.array(sizes)
     measured = int((arr >= warm).sum())
+    ms = lambda a, q: round(float(np.percentile(a, q)) * 1e3, 3) if len(a) else None
+    by_size = {}
+    for lo, hi in ((0, 1000), (1000, 3000), (3000, 1 << 20)):
+        sel = (sizes >= lo) & (sizes < hi)
+        by_size["N%d-%d" % (lo, hi)] = {"share": round(float(sel.mean()), 4), "device_ms_p50": ms(dev[sel], 50),
+                                        "device_ms_p99": ms(dev[sel], 99), "latency_ms_p50": ms(lat[sel], 50),
+                                        "device_s_share": round(float(dev[sel].sum() / max(1e-12, dev.sum())), 4)}
     return dict(workload="Poisson %g req/s (seed 5), q=round(exp(U[ln 8, ln 512])), N=q*U{4..16}, "
                          "p~U[0.05,0.3]; %d unique diagrams cycled; %g s warm-up + %g s measured"
                          % (rate, n_unique, warm, dur),
                 requests=len(arr), measured=measured, throughput_req_s=round(measured / max(1e-9, wall - warm), 1),
-                p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
-                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3), max_ms=round(float(lat.max()) * 1e3, 3),
+                p50_ms=ms(lat, 50), p99_ms=ms(lat, 99), max_ms=ms(lat, 100),
+                device_ms_p50=ms(dev, 50), device_ms_p99=ms(dev, 99), queue_ms_p50=ms(queue, 50),
+                queue_ms_p99=ms(queue, 99), busy_workgroups_mean=round(float(dev.sum()) / max(1e-9, wall - warm), 1),
+                by_size=by_size, claim_queue_ms_p50=ms(true_queue, 50), claim_queue_ms_p99=ms(true_queue, 99),
+                result_seen_lag_ms_p50=ms(lag, 50), result_seen_lag_ms_p99=ms(lag, 99),
+                host_submit_s=round(host_submit_s, 2), host_poll_s=round(host_poll_s, 2),
+                drained=drained, completed=done,
                 refused=refused, max_backlog=max_backlog, batches=int(st.batches),
                 pool_gib=args.serve_pool_gib, pool_peak_gib=round(st.pool_peak / 2 ** 30, 3))
 
@@ -651,12 +745,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy",
                                                       "parity", "sample", "params", "c1"])
-    ap.add_argument("--learned-states", type=int, default=20000)
-    ap.add_argument("--learned-epochs", type=int, default=4)
+    ap.add_argument("--learned-states", type=int, default=200000)
+    ap.add_argument("--learned-val-states", type=int, default=8000)
+    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--learned-label", default="fill", choices=["fill", "gate2q"])
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-unique", type=int, default=2048)
+    ap.add_argument("--serve-drain", type=float, default=60.0, help="seconds allowed after the last arrival")
     ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--rref-strips", action="store_true",

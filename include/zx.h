@@ -431,10 +431,10 @@ zx_status zx_mlp_sync(const zx_mlp* w, hipStream_t s);
 zx_status zx_mlp_forward(const zx_mlp* w, const uint16_t* x, int64_t rows, float* score,
                          hipStream_t s);
 /* Softmax cross-entropy per segment: rows seg_off[i] .. seg_off[i+1]-1 are
- * the candidates of state i; rows with cost < 0 are absent.  Target = the
- * present row of least cost (first on ties).  loss[i] = logsumexp - score of
- * the target (0 for a segment with no present row); dscore = (softmax -
- * onehot) / n_seg on present rows, 0 elsewhere. */
+ * the candidates of state i; rows with cost < 0 are absent.  Target = even
+ * over the t present rows of least cost.  loss[i] = logsumexp - (sum of the
+ * targets' scores) / t (0 for a segment with no present row); dscore =
+ * (softmax - target) / n_seg on present rows, 0 elsewhere. */
 zx_status zx_mlp_loss(const float* score, const int64_t* cost, const int32_t* seg_off,
                       int32_t n_seg, float* dscore, float* loss, hipStream_t s);
 /* grad (ZX_MLP_NPARAM floats, overwritten) = d(sum_r dscore[r] score[r]) /
@@ -525,6 +525,7 @@ typedef struct {
                                          start on the device, result seen by poll */
   double t_device;              /* seconds from a workgroup claiming the request
                                    to its result written (device clock) */
+  double t_claim_dev, t_end_dev;  /* the two device-clock instants, seconds */
 } zx_result;
 
 typedef struct {

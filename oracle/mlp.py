@@ -54,9 +54,10 @@ def forward(param, X, round_weights: bool = True):
 
 
 def loss_and_dscore(score, cost, seg_off):
-    """Softmax cross-entropy per segment toward its least-cost present row
-    (first on ties; rows with cost < 0 absent).  dscore = (softmax - onehot)
-    / n_seg.  Returns (loss per segment, dscore)."""
+    """Softmax cross-entropy per segment toward its least-cost present rows:
+    the target spreads evenly over every present row of least cost (rows
+    with cost < 0 absent).  dscore = (softmax - target) / n_seg.  Returns
+    (loss per segment, dscore)."""
     score = np.asarray(score, dtype=np.float64)
     cost = np.asarray(cost)
     n_seg = len(seg_off) - 1
@@ -67,14 +68,15 @@ def loss_and_dscore(score, cost, seg_off):
         rows = [r for r in range(a, b) if cost[r] >= 0]
         if not rows:
             continue
-        t = min(rows, key=lambda r: (cost[r], r))
+        best = min(cost[r] for r in rows)
+        tgt = [r for r in rows if cost[r] == best]
         s = np.array([score[r] for r in rows])
         mx = s.max()
         e = np.exp(s - mx)
         z = e.sum()
-        loss[i] = np.log(z) + mx - score[t]
+        loss[i] = np.log(z) + mx - sum(score[r] for r in tgt) / len(tgt)
         for r, ei in zip(rows, e):
-            ds[r] = (ei / z - (1.0 if r == t else 0.0)) / n_seg
+            ds[r] = (ei / z - (1.0 / len(tgt) if r in tgt else 0.0)) / n_seg
     return loss, ds
 
 

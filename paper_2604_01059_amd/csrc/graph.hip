@@ -1435,19 +1435,47 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
   __shared__ int64_t claimed;
   uint64_t last = wall_clock64();  // used by thread 0 only
   for (;;) {
+    // Idle workgroups look for work in device memory: dtail, a copy of the
+    // host's ring tail.  One of them at a time (the one holding the poller
+    // flag) reads the tail itself across the bus and raises dtail; with every
+    // idle workgroup reading host memory in a loop, those small reads filled
+    // the link and claims waited behind them.
     if (threadIdx.x == 0) {
+      int64_t* dtail = a.head + 1;
+      int64_t* poller = a.head + 2;
+      int64_t* active = a.head + 3;  // device clock of the latest claim by any workgroup
       int64_t got = -1;
       for (int spin = 0; spin < 64 && got == -1; ++spin) {
-        const int64_t t = __hip_atomic_load(a.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        const int64_t t = __hip_atomic_load(dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int64_t h = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (h < t) {
           if (__hip_atomic_compare_exchange_strong(a.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT))
+                                                   __HIP_MEMORY_SCOPE_AGENT)) {
             got = h;
+            __hip_atomic_store(active, (int64_t)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
           continue;  // claimed, or lost the race: look again at once
         }
+        int64_t free_ = 0;
+        if (__hip_atomic_compare_exchange_strong(poller, &free_, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+          // an acquire: a relaxed read of host memory can return a stale
+          // cached line (the acquire drops such lines first), and with a
+          // stale tail no workgroup would see the requests waiting
+          const int64_t ht = __hip_atomic_load(a.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (ht > t) __hip_atomic_fetch_max(dtail, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(poller, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (ht > t) continue;  // new entries: claim at once
+        }
+        // leave on the stop flag, or when the whole server has been idle:
+        // no claim by this or any other workgroup for idle_ticks.  (A
+        // workgroup idle on its own is not enough: under a thin stream of
+        // requests most workgroups go without one for a while, and those
+        // that left would not come back while others stay busy.)
+        const uint64_t now = wall_clock64();
+        const uint64_t act = (uint64_t)__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
-            wall_clock64() - last > a.idle_ticks) {
+            (now - last > a.idle_ticks && (int64_t)(now - act) > (int64_t)a.idle_ticks)) {
           got = -2;
           break;
         }
@@ -1462,8 +1490,27 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
     if (idx >= 0) {
       const int64_t slot = idx & (a.cap - 1);
       const uint64_t t_claim = wall_clock64();
+      // Entry idx was written before the host's release of a tail above idx;
+      // the poller's read of that tail orders nothing for this workgroup, so
+      // it acquires the host tail itself before reading the entry and the
+      // staged bytes (the tail it reads is above idx: tails only grow).
+      if (threadIdx.x == 0) (void)__hip_atomic_load(a.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
       uint8_t* arena =
           (uint8_t*)uni64((int64_t)__hip_atomic_load(&a.entries[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+      const uint4* stage =
+          (const uint4*)uni64((int64_t)__hip_atomic_load(&a.stage[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+      const int64_t sbytes =
+          uni64((int64_t)__hip_atomic_load(&a.stage_bytes[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+      // the staged header and SOURCE sections into the arena (16 bytes per
+      // thread and step), then drop this CU's L1 lines: the arena's memory
+      // served earlier requests, and its old contents may still be cached
+      uint4* dst = (uint4*)arena;
+      for (int64_t i = threadIdx.x; i < sbytes / 16; i += BS) dst[i] = stage[i];
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       process_diagram<BS, LEARN>(arena, smem_dyn, sa, sh);
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1844,7 +1891,7 @@ zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s) {
   const ZxDevice* d = zx_device();
   if (!d) return ZX_EDEVICE;
   constexpr int BS = 512;
-  const int v = 4;  // bs512-lds64k: two workgroups per CU
+  const int v = 4;  // bs512-lds64k
   zx_simplify_opts o = {a.policy, a.extract, -1, a.fallback ? ZX_FALLBACK : 0u, 0, 0, a.mlp};
   SimpArgs sa = simp_args(&o);
   sa.lds_cap = kVariants[v].lds_cap;
@@ -1857,7 +1904,12 @@ zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s) {
     zx_set_error("serving kernel does not fit a CU");
     return ZX_ECAPACITY;
   }
-  const int grid = std::min(per_cu, 2) * d->n_cu;
+  // One resident workgroup per CU.  The kernel stays resident between
+  // requests, so it must leave each CU room for other work: two 512-thread
+  // workgroups of 128 VGPRs fill a CU's whole register file, and then no
+  // other kernel -- a copy kernel of the request uploads among them -- can
+  // start anywhere until the server idles out.
+  const int grid = d->n_cu;
   if (learned)
     hipLaunchKernelGGL((serve_kernel<BS, true>), dim3(grid), dim3(BS), (size_t)sa.lds_cap, s, a, sa);
   else

@@ -54,44 +54,47 @@ __global__ void mlp_loss_kernel(const float* score, const int64_t* cost, const i
   const int seg = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (seg >= n_seg) return;
   const int a = seg_off[seg], b = seg_off[seg + 1];
-  // target: least cost among present rows, first on ties
+  // target: even over the present rows of least cost
   int64_t bc = INT64_MAX;
-  int bi = INT32_MAX;
   float mx = -INFINITY;
   for (int r = a + lane; r < b; r += 64) {
     const int64_t cr = cost[r];
     if (cr < 0) continue;
-    if (cr < bc || (cr == bc && r < bi)) {
-      bc = cr;
-      bi = r;
-    }
+    bc = cr < bc ? cr : bc;
     mx = fmaxf(mx, score[r]);
   }
   for (int o = 32; o > 0; o >>= 1) {
     const int64_t oc = __shfl_xor(bc, o);
-    const int oi = __shfl_xor(bi, o);
-    if (oc < bc || (oc == bc && oi < bi)) {
-      bc = oc;
-      bi = oi;
-    }
+    bc = oc < bc ? oc : bc;
     mx = fmaxf(mx, __shfl_xor(mx, o));
   }
-  if (bi == INT32_MAX) {  // no present row
+  if (bc == INT64_MAX) {  // no present row
     for (int r = a + lane; r < b; r += 64) dscore[r] = 0.f;
     if (lane == 0) loss[seg] = 0.f;
     return;
   }
-  float se = 0.f;
-  for (int r = a + lane; r < b; r += 64)
-    if (cost[r] >= 0) se += expf(score[r] - mx);
-  for (int o = 32; o > 0; o >>= 1) se += __shfl_xor(se, o);
-  const float inv = 1.0f / (float)n_seg;
+  float se = 0.f, st = 0.f;
+  int nt = 0;
+  for (int r = a + lane; r < b; r += 64) {
+    if (cost[r] < 0) continue;
+    se += expf(score[r] - mx);
+    if (cost[r] == bc) {
+      st += score[r];
+      ++nt;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_xor(se, o);
+    st += __shfl_xor(st, o);
+    nt += __shfl_xor(nt, o);
+  }
+  const float inv = 1.0f / (float)n_seg, tw = 1.0f / (float)nt;
   for (int r = a + lane; r < b; r += 64) {
     float d = 0.f;
-    if (cost[r] >= 0) d = (expf(score[r] - mx) / se - (r == bi ? 1.f : 0.f)) * inv;
+    if (cost[r] >= 0) d = (expf(score[r] - mx) / se - (cost[r] == bc ? tw : 0.f)) * inv;
     dscore[r] = d;
   }
-  if (lane == 0) loss[seg] = logf(se) + mx - score[bi];
+  if (lane == 0) loss[seg] = logf(se) + mx - st * tw;
 }
 
 // Backward.  Wavefront w of nw handles the 32-row chunks w, w + nw, ... in

@@ -60,17 +60,25 @@ extern "C" size_t zx_graph_bytes(int32_t n, int32_t n_in, int32_t n_out) {
 // SOURCE and CURRENT sections, boundary tables, masks).  Bits at or beyond n,
 // self loops, phases outside 0..7 and bad boundary ids are always rejected:
 // the kernels index by spider id.  The O(n^2) symmetry test is optional.
-zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
-                         const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
-                         int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
-                         std::vector<uint8_t>& img, int32_t n_params, const uint64_t* param_rows) {
+// Validate a diagram and write its arena image into dst: the whole arena
+// (source_only false, dst of the layout's bytes) or only the header and the
+// SOURCE sections, which come first (source_only true, dst of off_adj bytes;
+// a run from SOURCE initialises the rest).  L receives the layout.
+zx_status zx_write_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host, const int32_t* in_spider,
+                         int32_t n_in, const int32_t* out_spider, int32_t n_out, const uint8_t* bnd_is_h,
+                         bool check_symmetry, int32_t n_params, const uint64_t* param_rows, bool source_only,
+                         uint8_t* dst, size_t dst_bytes, ZxLayout* Lout) {
   ZX_CHECK_ARG(adj_host && phase_host, "null argument");
   ZX_CHECK_ARG(n > 0 && n <= (1 << 20), "n out of range: %d", n);
   ZX_CHECK_ARG(n_in >= 0 && n_out >= 0 && n_in + n_out <= n, "bad boundary counts");
   ZX_CHECK_ARG((n_in == 0 || in_spider) && (n_out == 0 || out_spider), "null boundary list");
   ZX_CHECK_ARG(n_params >= 0 && n_params <= ZX_MAX_PARAMS, "n_params %d not in 0..%d", n_params, ZX_MAX_PARAMS);
   ZX_CHECK_ARG(n_params == 0 || param_rows, "null parameter rows");
+  ZX_CHECK_ARG(!source_only || n_params == 0, "parameters need the whole image");
   ZxLayout L = zx_layout(n, n_in, n_out, n_params);
+  if (Lout) *Lout = L;
+  const size_t need = source_only ? (size_t)L.off_adj : (size_t)L.bytes;
+  ZX_CHECK_ARG(dst && dst_bytes >= need, "image buffer of %zu bytes < %zu", dst_bytes, need);
   const int pw = (n_params + 63) / 64;
   if (n_params % 64)
     for (int r = 0; r < n; ++r)
@@ -98,8 +106,6 @@ zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phas
     ZX_CHECK_ARG(!seen[v], "spider %d carries two boundary wires", v);
     seen[v] = 1;
   }
-  // assemble the whole arena image on the host, then one copy
-  img.assign((size_t)L.bytes, 0);
   ZxHeader h;
   memset(&h, 0, sizeof(h));
   h.magic = ZX_MAGIC;
@@ -131,26 +137,44 @@ zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phas
   int64_t edges = 0;
   for (size_t i = 0; i < (size_t)n * W; ++i) edges += __builtin_popcountll(adj_host[i]);
   h.n_edges = edges / 2;
-  memcpy(img.data(), &h, sizeof(h));
-  memcpy(img.data() + L.off_src_adj, adj_host, (size_t)n * W * 8);
-  memcpy(img.data() + L.off_adj, adj_host, (size_t)n * W * 8);
-  memcpy(img.data() + L.off_src_phase, phase_host, (size_t)n);
-  memcpy(img.data() + L.off_phase, phase_host, (size_t)n);
-  if (n_in) memcpy(img.data() + L.off_in, in_spider, 4 * (size_t)n_in);
-  if (n_out) memcpy(img.data() + L.off_out, out_spider, 4 * (size_t)n_out);
-  if (bnd_is_h) memcpy(img.data() + L.off_is_h, bnd_is_h, (size_t)(n_in + n_out));
-  if (pw) {
-    memcpy(img.data() + L.off_src_par, param_rows, (size_t)n * pw * 8);
-    memcpy(img.data() + L.off_par, param_rows, (size_t)n * pw * 8);
-  }
-  uint64_t* bm = (uint64_t*)(img.data() + L.off_bndmask);
+  // header and SOURCE sections (the gaps between them zeroed)
+  memset(dst, 0, 256);
+  memcpy(dst, &h, sizeof(h));
+  memcpy(dst + L.off_src_adj, adj_host, (size_t)n * W * 8);
+  memset(dst + L.off_src_phase, 0, (size_t)(L.off_in - L.off_src_phase));
+  memcpy(dst + L.off_src_phase, phase_host, (size_t)n);
+  memset(dst + L.off_in, 0, (size_t)(L.off_adj - L.off_in));
+  if (n_in) memcpy(dst + L.off_in, in_spider, 4 * (size_t)n_in);
+  if (n_out) memcpy(dst + L.off_out, out_spider, 4 * (size_t)n_out);
+  if (bnd_is_h) memcpy(dst + L.off_is_h, bnd_is_h, (size_t)(n_in + n_out));
+  uint64_t* bm = (uint64_t*)(dst + L.off_bndmask);
   for (int v = 0; v < n; ++v)
     if (seen[v]) bm[v / 64] |= (uint64_t)1 << (v % 64);
-  uint64_t* al = (uint64_t*)(img.data() + L.off_alive);
+  if (source_only) return ZX_OK;
+  // CURRENT sections: the diagram as given
+  memset(dst + L.off_adj, 0, (size_t)(L.bytes - L.off_adj));
+  memcpy(dst + L.off_adj, adj_host, (size_t)n * W * 8);
+  memcpy(dst + L.off_phase, phase_host, (size_t)n);
+  if (pw) {
+    memcpy(dst + L.off_src_par, param_rows, (size_t)n * pw * 8);
+    memcpy(dst + L.off_par, param_rows, (size_t)n * pw * 8);
+  }
+  uint64_t* al = (uint64_t*)(dst + L.off_alive);
   for (int v = 0; v < n; ++v) al[v / 64] |= (uint64_t)1 << (v % 64);
-  int32_t* fp = (int32_t*)(img.data() + L.off_fpiv);
+  int32_t* fp = (int32_t*)(dst + L.off_fpiv);
   for (int j = 0; j < n_out; ++j) fp[j] = -1;
   return ZX_OK;
+}
+
+zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
+                         const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
+                         int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
+                         std::vector<uint8_t>& img, int32_t n_params, const uint64_t* param_rows) {
+  ZX_CHECK_ARG(n > 0 && n <= (1 << 20), "n out of range: %d", n);
+  ZX_CHECK_ARG(n_in >= 0 && n_out >= 0 && n_params >= 0 && n_params <= ZX_MAX_PARAMS, "bad sizes");
+  img.assign((size_t)zx_layout(n, n_in, n_out, n_params).bytes, 0);
+  return zx_write_image(n, adj_host, phase_host, in_spider, n_in, out_spider, n_out, bnd_is_h, check_symmetry,
+                        n_params, param_rows, false, img.data(), img.size(), nullptr);
 }
 
 extern "C" size_t zx_graph_bytes_ex(int32_t n, int32_t n_in, int32_t n_out, int32_t n_params) {

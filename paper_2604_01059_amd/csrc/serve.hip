@@ -1,6 +1,9 @@
 // Serving loop (host side): admission into a device pool, a request ring in
 // coherent host memory read by the resident serving kernel of graph.hip,
-// completion by per-entry flags, result harvest.
+// completion by per-entry flags, result harvest.  A request's header and
+// SOURCE sections are written into pinned, coherent staging memory; the
+// workgroup that claims the request copies them into its device arena, so
+// a submission issues no copy and no synchronisation.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -64,7 +67,8 @@ class PoolAlloc {
 struct Req {
   int64_t ticket, tag;
   uint8_t* arena;
-  size_t off, bytes;
+  size_t off, bytes;    // device pool slice
+  size_t soff, sbytes;  // staging slice
   int32_t n;
   double t_submit;
 };
@@ -81,6 +85,8 @@ constexpr uint64_t kIdleTicks = 50ull * 100000;  // 50 ms at 100 MHz
 // Coherent host memory shared with the serving kernel.
 struct Shared_ {
   uint64_t entries[kRing];
+  uint64_t stage[kRing];        // staged header + SOURCE sections of the entry
+  uint64_t stage_bytes[kRing];  // bytes to copy (a multiple of 256)
   int64_t done[kRing];
   ZxServeRes res[kRing];
   int64_t tail;
@@ -99,6 +105,9 @@ struct zx_server {
   int64_t* head;    // device, at the head of the pool
   uint8_t* arenas;  // request slices start here
   PoolAlloc alloc;
+  uint8_t* staging;  // pinned, coherent host memory
+  size_t staging_bytes;
+  PoolAlloc salloc;
   Shared_* sh;      // coherent host memory
   hipStream_t stream, upload;
   hipEvent_t ended;  // recorded after each launch of the serving kernel
@@ -125,6 +134,8 @@ static zx_status relaunch(zx_server* S) {
   a.policy = S->opts.policy;
   a.mlp = S->opts.mlp;
   a.fallback = (S->opts.policy == ZX_POLICY_LEARNED && (S->opts.flags & ZX_FALLBACK)) ? 1 : 0;
+  a.stage = S->sh->stage;
+  a.stage_bytes = S->sh->stage_bytes;
   a.pad = 0;
   zx_status st = zx_launch_serve(a, S->stream);
   if (st != ZX_OK) return st;
@@ -172,6 +183,9 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   S->head = (int64_t*)S->pool;
   S->arenas = S->pool + head;
   S->alloc.init(pool_bytes - head);
+  S->staging = nullptr;
+  S->staging_bytes = std::min(pool_bytes, (size_t)1 << 30);
+  S->salloc.init(S->staging_bytes);
   S->sh = nullptr;
   S->stream = S->upload = nullptr;
   S->ended = nullptr;
@@ -180,10 +194,13 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   S->oldest = 0;
   S->submitted = S->refused = S->completed = S->launches = 0;
   hipError_t e = hipHostMalloc((void**)&S->sh, sizeof(Shared_), hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&S->staging, S->staging_bytes, hipHostMallocCoherent | hipHostMallocMapped);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ended, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMemsetAsync(S->head, 0, sizeof(int64_t), S->stream);
+  // control block: head, device copy of the tail, host-poller flag
+  if (e == hipSuccess) e = hipMemsetAsync(S->head, 0, 256, S->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) {
     zx_set_error("server set-up failed: %s", hipGetErrorString(e));
@@ -204,6 +221,7 @@ extern "C" void zx_server_destroy(zx_server* S) {
   if (S->stream) (void)hipStreamDestroy(S->stream);
   if (S->upload) (void)hipStreamDestroy(S->upload);
   if (S->sh) (void)hipHostFree(S->sh);
+  if (S->staging) (void)hipHostFree(S->staging);
   delete S;
 }
 
@@ -219,25 +237,37 @@ extern "C" zx_status zx_server_submit(zx_server* S, const zx_request* r, int64_t
     zx_set_error("request ring full");
     return ZX_EBUSY;
   }
-  std::vector<uint8_t> img;
-  zx_status st = zx_build_image(r->n, r->adj, r->phase, r->inputs, r->n_in, r->outputs, r->n_out, r->bnd_is_h,
-                                !(S->flags & ZX_SERVE_TRUSTED), img);
-  if (st != ZX_OK) return st;
-  const size_t bytes = align256(img.size());
-  size_t off = 0;
+  ZX_CHECK_ARG(r->n > 0 && r->n_in >= 0 && r->n_out >= 0 && r->n_in + r->n_out <= r->n, "bad request sizes");
+  const ZxLayout L = zx_layout(r->n, r->n_in, r->n_out);
+  const size_t bytes = align256((size_t)L.bytes);
+  // the kernel loads its working state from the header and SOURCE sections,
+  // which come first in the arena: only they are staged
+  const size_t sbytes = align256((size_t)L.off_adj);
+  if (sbytes > S->staging_bytes) {
+    zx_set_error("request of %zu staged bytes exceeds the staging area of %zu", sbytes, S->staging_bytes);
+    return ZX_ECAPACITY;
+  }
+  size_t off = 0, soff = 0;
   if (!S->alloc.alloc(bytes, &off)) {
     S->refused++;
     zx_set_error("pool full (%zu of %zu bytes in use)", S->alloc.used(), S->pool_bytes);
     return ZX_EBUSY;
   }
-  uint8_t* arena = S->arenas + off;
-  hipError_t e = hipMemcpyAsync(arena, img.data(), img.size(), hipMemcpyHostToDevice, S->upload);
-  if (e == hipSuccess) e = hipStreamSynchronize(S->upload);
-  if (e != hipSuccess) {
+  if (!S->salloc.alloc(sbytes, &soff)) {
     S->alloc.release(off, bytes);
-    zx_set_error("upload failed: %s", hipGetErrorString(e));
-    return ZX_EDEVICE;
+    S->refused++;
+    zx_set_error("staging full (%zu of %zu bytes in use)", S->salloc.used(), S->staging_bytes);
+    return ZX_EBUSY;
   }
+  zx_status st = zx_write_image(r->n, r->adj, r->phase, r->inputs, r->n_in, r->outputs, r->n_out, r->bnd_is_h,
+                                !(S->flags & ZX_SERVE_TRUSTED), 0, nullptr, true, S->staging + soff, sbytes,
+                                nullptr);
+  if (st != ZX_OK) {
+    S->alloc.release(off, bytes);
+    S->salloc.release(soff, sbytes);
+    return st;
+  }
+  uint8_t* arena = S->arenas + off;
   const int64_t seq = S->next_seq++;
   Req q;
   q.ticket = seq;
@@ -245,12 +275,16 @@ extern "C" zx_status zx_server_submit(zx_server* S, const zx_request* r, int64_t
   q.arena = arena;
   q.off = off;
   q.bytes = bytes;
+  q.soff = soff;
+  q.sbytes = sbytes;
   q.n = r->n;
   q.t_submit = now_s();
   S->inflight.emplace(seq, q);
   const int64_t slot = seq & (kRing - 1);
   __atomic_store_n(&S->sh->done[slot], (int64_t)0, __ATOMIC_RELAXED);
   __atomic_store_n(&S->sh->entries[slot], (uint64_t)(uintptr_t)arena, __ATOMIC_RELAXED);
+  __atomic_store_n(&S->sh->stage[slot], (uint64_t)(uintptr_t)(S->staging + soff), __ATOMIC_RELAXED);
+  __atomic_store_n(&S->sh->stage_bytes[slot], (uint64_t)sbytes, __ATOMIC_RELAXED);
   __atomic_store_n(&S->sh->tail, seq + 1, __ATOMIC_RELEASE);  // publishes the entry
   S->submitted++;
   if (ticket) *ticket = seq;
@@ -299,6 +333,8 @@ extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, i
     r.pad = 0;
     r.t_submit = q.t_submit;
     r.t_device = d.t_end > d.t_claim ? (double)(d.t_end - d.t_claim) / S->wall_hz : 0.0;
+    r.t_claim_dev = (double)d.t_claim / S->wall_hz;
+    r.t_end_dev = (double)d.t_end / S->wall_hz;
     r.t_done = t;
     // start on the device, on the host clock: the poll that saw the result
     // minus the device time (the lag between the result's write and this
@@ -306,6 +342,7 @@ extern "C" zx_status zx_server_poll(zx_server* S, zx_result* out, int32_t max, i
     r.t_launch = std::max(q.t_submit, t - r.t_device);
     S->finished.push_back(r);
     S->alloc.release(q.off, q.bytes);
+    S->salloc.release(q.soff, q.sbytes);
     S->completed++;
     it = S->inflight.erase(it);
   }

@@ -99,6 +99,10 @@ struct zx_graph {
 void zx_set_error(const char* fmt, ...);
 
 // Host validation + arena image of a diagram (runtime.hip).
+zx_status zx_write_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host, const int32_t* in_spider,
+                         int32_t n_in, const int32_t* out_spider, int32_t n_out, const uint8_t* bnd_is_h,
+                         bool check_symmetry, int32_t n_params, const uint64_t* param_rows, bool source_only,
+                         uint8_t* dst, size_t dst_bytes, ZxLayout* L);
 zx_status zx_build_image(int32_t n, const uint64_t* adj_host, const int8_t* phase_host,
                          const int32_t* in_spider, int32_t n_in, const int32_t* out_spider,
                          int32_t n_out, const uint8_t* bnd_is_h, bool check_symmetry,
@@ -135,8 +139,10 @@ struct ZxServeArgs {
   const zx_mlp* mlp;
   int32_t fallback;  // learned policy: keep the greedy result where it is cheaper
   int32_t pad;
+  const uint64_t* stage;        // per entry: staged header + SOURCE sections (host memory)
+  const uint64_t* stage_bytes;  // per entry: bytes to copy into the arena
 };
-// Launch the resident serving kernel on s (grid: 2 workgroups per CU).
+// Launch the resident serving kernel on s (grid: one workgroup per CU).
 zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s);
 void zx_clear_error();
 

@@ -62,7 +62,7 @@ class Result(C.Structure):
                 ("n_edges", C.c_int64), ("rowops", C.c_int64), ("pow_sqrt2", C.c_int64), ("fill_in", C.c_int64),
                 ("policy", C.c_int32), ("pad", C.c_int32),
                 ("t_submit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double),
-                ("t_device", C.c_double)]
+                ("t_device", C.c_double), ("t_claim_dev", C.c_double), ("t_end_dev", C.c_double)]
 
 
 class ServerStats(C.Structure):

@@ -370,3 +370,26 @@ def test_serve_learned_with_fallback(zx):
         pols.add(r.policy)
     assert zx.ZX_POLICY_LEARNED in pols
     sv.close()
+
+
+def test_training_gains(zx):
+    """What training buys: on held-out states of other diagrams the trained
+    network's loss is below the untrained one's, and on held-out diagrams its
+    schedule toggles fewer edges on (fill-in) than the greedy schedule, while
+    the greedy fallback keeps gate2q at or below greedy's on every diagram
+    (every result an exact rewrite sequence: the fallback test replays them)."""
+    from paper_2604_01059_amd import learned
+    mlp = learned.new_network()
+    feats, costs = learned.make_dataset(6000, per_state=16)
+    vf, vc = learned.make_dataset(2000, per_state=16, first_item=1 << 20)
+    before = learned.state_metrics(mlp, vf, vc)
+    ev0 = learned.evaluate(mlp, n=128)
+    learned.train(mlp, feats, costs, epochs=4)
+    after = learned.state_metrics(mlp, vf, vc)
+    ev = learned.evaluate(mlp, n=128)
+    print("held-out before", before, "after", after, flush=True)
+    print("eval untrained", ev0, "trained", ev, flush=True)
+    assert after["loss"] < before["loss"] - 0.01
+    assert after["top1_least_cost"] > after["random_least_cost"]
+    assert ev["fill_learned"] < ev["fill_greedy"]
+    assert ev["fallback_equals_min"] and ev["gate2q_fallback"] <= ev["gate2q_greedy"]

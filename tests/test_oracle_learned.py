@@ -73,7 +73,7 @@ def test_backward_matches_autograd_and_finite_differences():
 
 def test_loss_matches_torch_cross_entropy():
     score = rng.standard_normal(40)
-    cost = rng.integers(0, 5, 40)
+    cost = rng.integers(0, 3, 40)  # ties at the least cost are common
     cost[[3, 17, 18]] = -1  # absent rows
     seg = np.array([0, 7, 7, 20, 33, 40])
     loss, ds = mlp.loss_and_dscore(score, cost, seg)
@@ -82,13 +82,18 @@ def test_loss_matches_torch_cross_entropy():
         if not rows:
             assert loss[i] == 0
             continue
-        t = min(rows, key=lambda r: (cost[r], r))
+        best = min(cost[r] for r in rows)
+        prob = torch.tensor([1.0 if cost[r] == best else 0.0 for r in rows], dtype=torch.float64)
+        prob /= prob.sum()  # even over the least-cost rows
         st = torch.tensor(score[rows], requires_grad=True)
-        ref = torch.nn.functional.cross_entropy(st[None], torch.tensor([rows.index(t)]))
+        ref = torch.nn.functional.cross_entropy(st[None], prob[None])
         ref.backward()
         assert abs(loss[i] - ref.item()) < 1e-12
         np.testing.assert_allclose(ds[rows] * (len(seg) - 1), st.grad.numpy(), atol=1e-12)
     assert np.all(ds[[3, 17, 18]] == 0)
+    ties = [sum(1 for r in range(seg[i], seg[i + 1]) if cost[r] >= 0 and cost[r] == min(
+        [cost[q] for q in range(seg[i], seg[i + 1]) if cost[q] >= 0] or [-9])) for i in range(len(seg) - 1)]
+    assert max(ties) >= 2  # the even target over tied rows is exercised
 
 
 def test_adam_matches_torch():
