@@ -350,9 +350,15 @@ __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
       bool free_ = isc;
       uint64_t inblk = 0;
       if (isc) {
+        // eight words of u's row per step, loaded together
         const auto ru = row_ptr(c, u);
-        for (int jj = 0; jj < b; ++jj)
-          if (ru[jj] & c.sel[jj]) { free_ = false; break; }
+        for (int jj = 0; jj < b && free_; jj += 8) {
+          uint64_t hit = 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (jj + q < b) hit |= ru[jj + q] & c.sel[jj + q];
+          free_ = hit == 0;
+        }
         inblk = ru[b];
       }
       uint64_t R = __ballot(free_);  // survivors, to resolve in order
@@ -587,20 +593,63 @@ constexpr int SPIDER_MAJOR_MAX = 64;
 template <int BS>
 __device__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool pivot) {
   const int W = c.W, n = c.n, ns = uni(sh.ns), tid = threadIdx.x;
-  const bool staged = (int64_t)ns * W + 64 <= c.scr_words;
+  const bool staged = (int64_t)ns * W + 64 + 8 <= c.scr_words;
   LDSP uint64_t* cs = c.scr;
-  LDSP uint64_t* hm = staged ? c.scr + (int64_t)ns * W : c.scr;
-  const int room = c.scr_words - (staged ? ns * W : 0);
+  // slist index of each selected spider's pivot partner (64 bytes after the
+  // staged contributions)
+  LDSP int8_t* pidx = (LDSP int8_t*)(c.scr + (staged ? (int64_t)ns * W : 0));
+  LDSP uint64_t* hm = staged ? c.scr + (int64_t)ns * W + 8 : c.scr;
+  const int room = c.scr_words - (staged ? ns * W + 8 : 0);
   const int CH = room < n ? room : n;
-  if (staged)
+  if (staged) {
     for (int i = tid; i < ns * W; i += BS) {
       const int si = i / W, j = i - si * W;
       cs[i] = row_ptr(c, c.slist[si])[j];
     }
+    if (pivot)
+      for (int i = tid; i < ns; i += BS) {
+        const int p = c.partner[c.slist[i]];
+        int q = 0;
+        while (q < ns - 1 && c.slist[q] != p) ++q;
+        pidx[i] = (int8_t)q;
+      }
+  }
   int64_t pc = 0;
   for (int r0 = 0; r0 < n; r0 += CH) {
     const int rn = n - r0 < CH ? n - r0 : CH;
     __syncthreads();  // staging done; the previous chunk is through with hm
+    if (staged) {
+      // Hit masks from the staged rows: w ~ x is bit w of x's row (the
+      // adjacency is symmetric).  The staged row of a local complementation
+      // is x's own row; a pivot swapped each pair's rows into contributions,
+      // so x's row is its partner's staged row (without the partner's bit,
+      // which is no unselected w).  Rows of one 64-row block read the same
+      // staged words (LDS broadcast).
+      for (int t = tid; t < rn; t += BS) {
+        const int w = r0 + t;
+        uint64_t m = 0;
+        if (bit_of(c.alive, w) && !bit_of(c.sel, w)) {
+          const int jw = w >> 6, bw = w & 63;
+          uint64_t R = 0;
+          for (int i = 0; i < ns; ++i) R |= ((cs[(int64_t)i * W + jw] >> bw) & 1ull) << i;
+          if (pivot) {
+            for (int i = 0; i < ns; ++i) m |= ((R >> pidx[i]) & 1ull) << i;
+          } else {
+            m = R;
+          }
+          int dk = 0;
+          uint64_t mm = m;
+          while (mm) {
+            const int i = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            dk += c.kc[c.slist[i]];
+            if (pivot && ((m >> pidx[i]) & 1)) dk += 2;  // adjacent to both ends
+          }
+          if (dk) c.k[w] = (int8_t)((c.k[w] + dk) & 7);
+        }
+        hm[t] = m;
+      }
+    } else {
     for (int t = tid; t < rn; t += BS) {
       const int w = r0 + t;
       uint64_t m = 0;
@@ -622,24 +671,42 @@ __device__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool pivot) {
       }
       hm[t] = m;
     }
+    }
     __syncthreads();
-    for (int64_t it = tid; it < (int64_t)rn * W; it += BS) {
-      const int t = (int)(it / W), j = (int)(it - (int64_t)t * W);
-      const int w = r0 + t;
-      if (!bit_of(c.alive, w) || bit_of(c.sel, w)) continue;
-      auto rw = row_ptr(c, w);
-      const uint64_t old = rw[j];
-      uint64_t v = old;
-      uint64_t m = hm[t];
-      while (m) {
-        const int i = __builtin_ctzll(m);
-        m &= m - 1;
-        v ^= staged ? cs[(int64_t)i * W + j] : row_ptr(c, c.slist[i])[j];
+    // (row, word) items, four per thread at a time: their row words are
+    // loaded together, so four loads per thread are in flight (one at a
+    // time left a single workgroup latency-bound on the arena).
+    constexpr int U = 4;
+    const int64_t total = (int64_t)rn * W;
+    for (int64_t it0 = tid; it0 < total; it0 += U * BS) {
+      uint64_t old[U];
+      int tt[U], jj[U];
+      bool act[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t it = it0 + (int64_t)u * BS;
+        tt[u] = it < total ? (int)(it / W) : 0;
+        jj[u] = it < total ? (int)(it - (int64_t)tt[u] * W) : 0;
+        const int w = r0 + tt[u];
+        act[u] = it < total && bit_of(c.alive, w) && !bit_of(c.sel, w);
+        old[u] = act[u] ? row_ptr(c, w)[jj[u]] : 0;
       }
-      if (j == (w >> 6)) v &= ~(1ull << (w & 63));
-      v &= ~c.sel[j];
-      if (v != old) rw[j] = v;
-      pc += __popcll(v);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        const int t = tt[u], j = jj[u], w = r0 + t;
+        uint64_t v = old[u];
+        uint64_t m = hm[t];
+        while (m) {
+          const int i = __builtin_ctzll(m);
+          m &= m - 1;
+          v ^= staged ? cs[(int64_t)i * W + j] : row_ptr(c, c.slist[i])[j];
+        }
+        if (j == (w >> 6)) v &= ~(1ull << (w & 63));
+        v &= ~c.sel[j];
+        if (v != old[u]) row_ptr(c, w)[j] = v;
+        pc += __popcll(v);
+      }
     }
   }
   __syncthreads();
