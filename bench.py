@@ -603,6 +603,7 @@ def bench_learned(zx, args, pool):
     train_s = time.perf_counter() - t0
     trained = learned.state_metrics(mlp, vf, vc)
     ev, ds, lg, fg = learned.evaluate(mlp, n=1024, keep_graphs=True)
+    args._trained_mlp = mlp
     out = dict(workload="train: %d greedy-run states of the batched generator (seed %d) whose candidates differ "
                         "in rollout %s, 16 rollouts each; held-out: %d states of other diagrams; eval: 1024 "
                         "diagrams q~U{32..128}, N=q*U{4..16}, seed %d"
@@ -642,26 +643,38 @@ def _gen_serve(i):
     return serve_diagram(5, i)
 
 
-def bench_serve(zx, args, pool):
-    """Serving: Poisson arrivals into a continuous-batching server."""
-    from workloads import poisson_arrivals
+def serve_diagrams(args, pool):
     n_unique = args.serve_unique
     t0 = time.perf_counter()
     ds = list(pool.map(_gen_serve, range(n_unique), chunksize=8)) if pool is not None else \
         [_gen_serve(i) for i in range(n_unique)]
     log("serve: generated %d request diagrams in %.1f s (median N %d, max N %d)" %
         (n_unique, time.perf_counter() - t0, int(np.median([d.n for d in ds])), max(d.n for d in ds)))
-    rate, warm, dur = args.serve_rate, args.serve_warmup, args.serve_seconds
+    return ds
+
+
+def bench_serve(zx, args, ds, mlp=None, seconds=None):
+    """Serving: Poisson arrivals into a continuous-batching server; with mlp,
+    the learned policy with the greedy fallback, else greedy."""
+    from workloads import poisson_arrivals
+    n_unique = len(ds)
+    rate, warm = args.serve_rate, args.serve_warmup
+    dur = args.serve_seconds if seconds is None else seconds
     count = int(rate * (warm + dur) * 1.05) + 16
     arr = poisson_arrivals(5, rate, count)
     arr = arr[arr < warm + dur]
-    sv = zx.Server(args.serve_pool_gib << 30, max_batch=2048, trusted=True)
+    if mlp is None:
+        sv = zx.Server(args.serve_pool_gib << 30, max_batch=2048, trusted=True)
+    else:
+        sv = zx.Server(args.serve_pool_gib << 30, max_batch=2048, trusted=True, policy=zx.ZX_POLICY_LEARNED, mlp=mlp,
+                       fallback=True)
     start = time.perf_counter() + 0.05
     backlog = []
     lat, refused, nxt, done = [], 0, 0, 0
     dev, queue, sizes = [], [], []
     claim_dev, end_dev, done_host, arr_host = [], [], [], []
     host_submit_s = host_poll_s = 0.0
+    learned_kept = 0
     max_backlog = 0
     last_log = 0.0
     deadline = warm + dur + args.serve_drain
@@ -696,6 +709,7 @@ def bench_serve(zx, args, pool):
                 dev.append(r.t_device)
                 queue.append(r.t_launch - (start + arr[r.tag]))
                 sizes.append(ds[r.tag % n_unique].n)
+                learned_kept += r.policy == zx.ZX_POLICY_LEARNED
                 claim_dev.append(r.t_claim_dev)
                 end_dev.append(r.t_end_dev)
                 done_host.append(r.t_done)
@@ -724,8 +738,9 @@ def bench_serve(zx, args, pool):
                                         "device_ms_p99": ms(dev[sel], 99), "latency_ms_p50": ms(lat[sel], 50),
                                         "device_s_share": round(float(dev[sel].sum() / max(1e-12, dev.sum())), 4)}
     return dict(workload="Poisson %g req/s (seed 5), q=round(exp(U[ln 8, ln 512])), N=q*U{4..16}, "
-                         "p~U[0.05,0.3]; %d unique diagrams cycled; %g s warm-up + %g s measured"
-                         % (rate, n_unique, warm, dur),
+                         "p~U[0.05,0.3]; %d unique diagrams cycled; %g s warm-up + %g s measured; %s"
+                         % (rate, n_unique, warm, dur,
+                            "learned policy with the greedy fallback" if mlp is not None else "greedy policy"),
                 requests=len(arr), measured=measured, throughput_req_s=round(measured / max(1e-9, wall - warm), 1),
                 p50_ms=ms(lat, 50), p99_ms=ms(lat, 99), max_ms=ms(lat, 100),
                 device_ms_p50=ms(dev, 50), device_ms_p99=ms(dev, 99), queue_ms_p50=ms(queue, 50),
@@ -733,7 +748,7 @@ def bench_serve(zx, args, pool):
                 by_size=by_size, claim_queue_ms_p50=ms(true_queue, 50), claim_queue_ms_p99=ms(true_queue, 99),
                 result_seen_lag_ms_p50=ms(lag, 50), result_seen_lag_ms_p99=ms(lag, 99),
                 host_submit_s=round(host_submit_s, 2), host_poll_s=round(host_poll_s, 2),
-                drained=drained, completed=done,
+                drained=drained, completed=done, learned_result_share=round(learned_kept / max(1, len(lat)), 4),
                 refused=refused, max_backlog=max_backlog, batches=int(st.batches),
                 pool_gib=args.serve_pool_gib, pool_peak_gib=round(st.pool_peak / 2 ** 30, 3))
 
@@ -750,8 +765,9 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--learned-label", default="fill", choices=["fill", "gate2q"])
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-learned-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-unique", type=int, default=2048)
     ap.add_argument("--serve-drain", type=float, default=60.0, help="seconds allowed after the last arrival")
     ap.add_argument("--serve-pool-gib", type=int, default=8)
@@ -831,12 +847,6 @@ def main():
     if args.only in ("all", "c1"):
         out["c1"] = bench_c1(zx)
         log("c1: %s" % out["c1"])
-    # serving runs before the batched and learned legs: measured after the
-    # learned leg in the same process, its median latency was higher in every
-    # run (cause not found; a pause or an emptied allocator cache did not help)
-    if args.only in ("all", "serve"):
-        out["serve"] = bench_serve(zx, args, pool)
-        log("serve: %s" % out["serve"])
     if args.only in ("all", "batched"):
         out["batched"] = bench_batched(zx, args, pool)
         log("batched: %s" % out["batched"])
@@ -846,6 +856,17 @@ def main():
     if args.only in ("all", "learned"):
         out["learned"] = bench_learned(zx, args, pool)
         log("learned: %s" % out["learned"])
+    if args.only in ("all", "serve"):
+        ds = serve_diagrams(args, pool)
+        out["serve"] = bench_serve(zx, args, ds)
+        log("serve: %s" % out["serve"])
+        mlp = getattr(args, "_trained_mlp", None)
+        if mlp is None:
+            from paper_2604_01059_amd import learned
+            mlp = learned.new_network()  # untrained when the learned leg did not run
+        out["serve_learned"] = bench_serve(zx, args, ds, mlp=mlp, seconds=args.serve_learned_seconds)
+        out["serve_learned"]["network"] = "trained" if hasattr(args, "_trained_mlp") else "untrained"
+        log("serve (learned + fallback): %s" % out["serve_learned"])
     if pool is not None:
         pool.close()
         pool.join()

@@ -370,6 +370,31 @@ zx_status zx_phase_pair_product(const uint64_t* A, const uint64_t* B, int64_t ld
                                 hipStream_t s);
 
 /* ======================================================================
+ * Generalised flow (the flow check before circuit extraction)
+ *
+ * The paper reduces diagrams by local complementation and pivoting and
+ * eliminates binary matrices over F2 (detectors section, after equation
+ * detector_sampling); circuit extraction and its flow check are the
+ * standard procedures (Mhalla and Perdrix, ICALP 2008, for generalised
+ * flow).  On the CURRENT diagram of each graph: output spiders form layer
+ * 0; a spider u joins layer k when some set of processed spiders without an
+ * input wire has odd neighbourhood, restricted to the spiders not yet
+ * processed, equal to {u}; every layer is found by one Gauss-Jordan
+ * elimination of those spiders' rows over F2 (its single-bit rows).
+ * layers: sum of the graphs' n int32 (graph i's spiders after those of
+ * graphs 0..i-1): the layer, or -1 for a spider that gets none or is not
+ * present.  exists[i]: 1 if every present spider has a layer, 0 if not,
+ * ZX_ECAPACITY for an arena the kernel does not take (layers unwritten).
+ * Diagrams of up to 1024 spiders (ZX_ECAPACITY on the host otherwise).
+ * ws: device workspace of zx_gflow_workspace_bytes(n_graphs), 256-byte
+ * aligned; the call uploads the batch table into it and synchronises s
+ * once before launching.  Device arrays; asynchronous on s after that.
+ * ==================================================================== */
+size_t zx_gflow_workspace_bytes(int32_t n_graphs);
+zx_status zx_gflow(zx_graph* const* graphs, int32_t n_graphs, int32_t* layers, int32_t* exists, void* ws,
+                   size_t ws_bytes, hipStream_t s);
+
+/* ======================================================================
  * Detector sampling: f = T e mod 2
  *
  * Section on the repetition-code example (equation detector_sampling) and

@@ -125,6 +125,8 @@ def load():
         "zx_detector_workspace_bytes": ([i32], sz),
         "zx_detector_sample": ([P, P, i64, P, i32, i32, C.c_uint64, i64, i64, P, i64, P, sz, P], i32),
         "zx_detector_status": ([P, P], i32),
+        "zx_gflow_workspace_bytes": ([i32], sz),
+        "zx_gflow": ([P, i32, P, P, P, sz, P], i32),
         "zx_mlp_sync": ([C.POINTER(MlpHandle), P], i32),
         "zx_mlp_forward": ([C.POINTER(MlpHandle), P, i64, P, P], i32),
         "zx_mlp_loss": ([P, P, P, i32, P, P, P], i32),
@@ -159,7 +161,7 @@ def exported_symbols():
             "zx_batch_status", "zx_batch_autotune", "zx_batch_destroy", "zx_gf2_workspace_bytes",
             "zx_gf2_eliminate", "zx_gf2_eliminate_noalloc", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
             "zx_gf2_matmul", "zx_phase_pair_product", "zx_detector_workspace_bytes",
-            "zx_detector_sample", "zx_detector_status",
+            "zx_detector_sample", "zx_detector_status", "zx_gflow_workspace_bytes", "zx_gflow",
             "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
             "zx_mlp_adam", "zx_rollout_workspace_bytes", "zx_rollout", "zx_policy_features", "zx_server_create",
             "zx_server_submit", "zx_server_poll", "zx_server_stats_read", "zx_server_destroy"]
@@ -654,6 +656,26 @@ def to_host_words(t) -> np.ndarray:
 
 
 # ------------------------------------------------------- detector sampling --
+
+def gflow(graphs, stream=None):
+    """Generalised-flow layers of the CURRENT diagrams (zx_gflow): returns
+    (exists, layers) with exists[i] in {1, 0, ZX_ECAPACITY} and layers[i] the
+    int32 layer of each spider of graph i (-1: none)."""
+    import torch
+    n = len(graphs)
+    total = sum(g.n for g in graphs)
+    layers = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+    exists = torch.empty(n, dtype=torch.int32, device="cuda")
+    nb = load().zx_gflow_workspace_bytes(n)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    _check(load().zx_gflow(_graph_array(graphs), n, _ptr(layers), _ptr(exists), _ptr(ws), nb, _stream(stream)))
+    lay = layers.cpu().numpy()
+    out, off = [], 0
+    for g in graphs:
+        out.append(lay[off:off + g.n].copy())
+        off += g.n
+    return exists.cpu().numpy(), out
+
 
 class DetectorSampler:
     """Device copy of a detector error model (T as CSC, probabilities) and a
