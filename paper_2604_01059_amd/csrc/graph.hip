@@ -350,14 +350,19 @@ __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
       bool free_ = isc;
       uint64_t inblk = 0;
       if (isc) {
-        // eight words of u's row per step, loaded together
         const auto ru = row_ptr(c, u);
-        for (int jj = 0; jj < b && free_; jj += 8) {
-          uint64_t hit = 0;
+        if constexpr (LA) {
+          for (int jj = 0; jj < b; ++jj)
+            if (ru[jj] & c.sel[jj]) { free_ = false; break; }
+        } else {
+          // rows in the arena: eight words of u's row per step, loaded together
+          for (int jj = 0; jj < b && free_; jj += 8) {
+            uint64_t hit = 0;
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (jj + q < b) hit |= ru[jj + q] & c.sel[jj + q];
-          free_ = hit == 0;
+            for (int q = 0; q < 8; ++q)
+              if (jj + q < b) hit |= ru[jj + q] & c.sel[jj + q];
+            free_ = hit == 0;
+          }
         }
         inblk = ru[b];
       }
@@ -590,8 +595,10 @@ constexpr int SPIDER_MAJOR_MAX = 64;
 // then a (row, word) pass XORs the hit contributions, staged in LDS when
 // they fit, and drops the selected columns in the same write.  Each row
 // word is read and written once; each selected-column bit once per row.
+// Not inlined: its unrolled update would otherwise set the register
+// allocation of the LDS-resident path that shares the kernel.
 template <int BS>
-__device__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool pivot) {
+__device__ __noinline__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool pivot) {
   const int W = c.W, n = c.n, ns = uni(sh.ns), tid = threadIdx.x;
   const bool staged = (int64_t)ns * W + 64 + 8 <= c.scr_words;
   LDSP uint64_t* cs = c.scr;
@@ -673,40 +680,23 @@ __device__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool pivot) {
     }
     }
     __syncthreads();
-    // (row, word) items, four per thread at a time: their row words are
-    // loaded together, so four loads per thread are in flight (one at a
-    // time left a single workgroup latency-bound on the arena).
-    constexpr int U = 4;
-    const int64_t total = (int64_t)rn * W;
-    for (int64_t it0 = tid; it0 < total; it0 += U * BS) {
-      uint64_t old[U];
-      int tt[U], jj[U];
-      bool act[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t it = it0 + (int64_t)u * BS;
-        tt[u] = it < total ? (int)(it / W) : 0;
-        jj[u] = it < total ? (int)(it - (int64_t)tt[u] * W) : 0;
-        const int w = r0 + tt[u];
-        act[u] = it < total && bit_of(c.alive, w) && !bit_of(c.sel, w);
-        old[u] = act[u] ? row_ptr(c, w)[jj[u]] : 0;
+    for (int64_t it = tid; it < (int64_t)rn * W; it += BS) {
+      const int t = (int)(it / W), j = (int)(it - (int64_t)t * W);
+      const int w = r0 + t;
+      if (!bit_of(c.alive, w) || bit_of(c.sel, w)) continue;
+      auto rw = row_ptr(c, w);
+      const uint64_t old = rw[j];
+      uint64_t v = old;
+      uint64_t m = hm[t];
+      while (m) {
+        const int i = __builtin_ctzll(m);
+        m &= m - 1;
+        v ^= staged ? cs[(int64_t)i * W + j] : row_ptr(c, c.slist[i])[j];
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (!act[u]) continue;
-        const int t = tt[u], j = jj[u], w = r0 + t;
-        uint64_t v = old[u];
-        uint64_t m = hm[t];
-        while (m) {
-          const int i = __builtin_ctzll(m);
-          m &= m - 1;
-          v ^= staged ? cs[(int64_t)i * W + j] : row_ptr(c, c.slist[i])[j];
-        }
-        if (j == (w >> 6)) v &= ~(1ull << (w & 63));
-        v &= ~c.sel[j];
-        if (v != old[u]) row_ptr(c, w)[j] = v;
-        pc += __popcll(v);
-      }
+      if (j == (w >> 6)) v &= ~(1ull << (w & 63));
+      v &= ~c.sel[j];
+      if (v != old) rw[j] = v;
+      pc += __popcll(v);
     }
   }
   __syncthreads();
@@ -1312,9 +1302,13 @@ struct Queue {
   uint32_t pad[63];
 };
 
+// The greedy kernel keeps four waves per SIMD (at most 128 VGPRs): the
+// 512-thread, 64 KiB variant runs two workgroups per CU only then, and it is
+// the fastest on the batched workload by a wide margin (5.4 against 9.6 ms
+// at three waves).  The learned kernel's matrix-core scoring needs more.
 template <int BS, bool LEARN>
-__global__ __launch_bounds__(BS) void simplify_kernel(uint8_t* const* table, int32_t n_graphs,
-                                                      Queue* q, SimpArgs a) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(LEARN ? 1 : 4)))
+void simplify_kernel(uint8_t* const* table, int32_t n_graphs, Queue* q, SimpArgs a) {
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
   for (;;) {
