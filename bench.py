@@ -450,6 +450,88 @@ def bench_c1(zx):
                              "kind": "oracle", "sample": "the same 1000 diagrams, one at a time"}}
 
 
+def _circ_diag(i):
+    from workloads.circuits import circuit_workload
+    return circuit_workload(12, i, q_lo=20, q_hi=20)
+
+
+def _oracle_extract(d):
+    """The oracle's flow check and circuit of one simplified circuit diagram
+    (digest of the gate list and permutation)."""
+    import hashlib
+    import oracle
+    from oracle import extract as ox
+    g = oracle.Graph.from_diagram(d)
+    g.simplify()
+    ex, layers = ox.gflow_layers(g)
+    gates, perm, _ = ox.extract_circuit(g)
+    return bool(ex), hashlib.sha256(repr((gates, [int(p) for p in perm])).encode()).hexdigest(), len(gates)
+
+
+def bench_extract(zx, pool, steps=5):
+    """Flow check and circuit extraction of 4096 simplified circuit diagrams
+    (20 qubits, 1-21 exponentiated Pauli strings of weight 2-4), each kernel
+    timed over the whole batch with HIP events; every circuit compared with
+    the oracle's."""
+    import hashlib
+    import torch
+    t0 = time.perf_counter()
+    ds = list(pool.map(_circ_diag, range(4096), chunksize=32))
+    log("extract: generated 4096 circuit diagrams in %.1f s (mean N %.0f, max N %d)" %
+        (time.perf_counter() - t0, np.mean([d.n for d in ds]), max(d.n for d in ds)))
+    gs, big = make_graphs(zx, ds)
+    b = zx.Batch(gs)
+    simp_ms = _time_launches(lambda: b.run(extract=False), 1)
+    b.run(extract=False)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    lib = zx.load()
+    n = len(gs)
+    arr = zx._graph_array(gs)
+    layers = torch.empty(sum(g.n for g in gs), dtype=torch.int32, device="cuda")
+    exists = torch.empty(n, dtype=torch.int32, device="cuda")
+    fws_b = lib.zx_gflow_workspace_bytes(n)
+    fws = torch.empty(fws_b, dtype=torch.uint8, device="cuda")
+    cap = max((g.n + 2 * g.n_in) * (g.n_out + 4) for g in gs)
+    gates = torch.empty(n * cap, dtype=torch.int32, device="cuda")
+    n_gates = torch.empty(n, dtype=torch.int32, device="cuda")
+    perm = torch.empty(sum(g.n_out for g in gs), dtype=torch.int32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    ews_b = lib.zx_extract_workspace_bytes(n)
+    ews = torch.empty(ews_b, dtype=torch.uint8, device="cuda")
+    st = zx._stream(None)
+    flow_ms = _time_launches(lambda: zx._check(lib.zx_gflow(arr, n, zx._ptr(layers), zx._ptr(exists),
+                                                            zx._ptr(fws), fws_b, st)), steps)
+    ext_ms = _time_launches(lambda: zx._check(lib.zx_extract(arr, n, cap, zx._ptr(gates), zx._ptr(n_gates),
+                                                             zx._ptr(perm), zx._ptr(status), zx._ptr(ews),
+                                                             ews_b, st)), steps)
+    ex_h, st_h, ng_h = exists.cpu().numpy(), status.cpu().numpy(), n_gates.cpu().numpy()
+    G = gates.cpu().numpy().view(np.uint32).reshape(n, cap)
+    P = perm.cpu().numpy()
+    out = {"workload": "4096 circuit diagrams: 20 qubits, U{1..21} exponentiated Pauli strings of weight "
+                       "U{2..4} (seed 12), simplified; flow layers, then the circuit",
+           "mean_spiders_simplified": round(float(np.mean([g.info().n_alive for g in gs])), 1),
+           "simplify_ms": round(simp_ms, 3), "gflow_ms": round(flow_ms, 3), "extract_ms": round(ext_ms, 3),
+           "circuits_per_s": round(n / ((flow_ms + ext_ms) * 1e-3), 1),
+           "gates_total": int(ng_h.sum()), "all_have_flow": bool((ex_h == 1).all()),
+           "all_extracted": bool((st_h == 0).all())}
+    t0 = time.perf_counter()
+    refs = list(pool.map(_oracle_extract, ds, chunksize=16))
+    cpu_s = time.perf_counter() - t0
+    same, off = 0, 0
+    for i, g in enumerate(gs):
+        ref_ex, ref_dg, _ = refs[i]
+        pm = [int(x) for x in P[off:off + g.n_out]]
+        off += g.n_out
+        dg = hashlib.sha256(repr((zx.decode_gates(G[i, :int(ng_h[i])]), pm)).encode()).hexdigest()
+        same += int(ex_h[i] == int(ref_ex) and st_h[i] == 0 and dg == ref_dg)
+    out["bit_exact_vs_oracle"] = "%d/%d" % (same, n)
+    out["cpu_baseline"] = {"value": round(n / cpu_s, 1), "unit": "circuits/s", "cores": pool._processes,
+                           "kind": "oracle", "sample": "all 4096 diagrams (simplify, flow layers, extraction), "
+                                                       "one per worker process"}
+    return out
+
+
 def _gen_diag(i):
     from workloads import batch_diagram
     return batch_diagram(3, i)
@@ -759,7 +841,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy",
-                                                      "parity", "sample", "params", "c1"])
+                                                      "parity", "sample", "params", "c1", "extract"])
     ap.add_argument("--learned-states", type=int, default=200000)
     ap.add_argument("--learned-val-states", type=int, default=8000)
     ap.add_argument("--learned-epochs", type=int, default=8)
@@ -783,7 +865,7 @@ def main():
               "see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     pool = None
-    if args.only in ("all", "batched", "learned", "serve", "pauli", "params"):
+    if args.only in ("all", "batched", "learned", "serve", "pauli", "params", "extract"):
         # worker processes (generation, oracle checks) are forked before any
         # GPU call, so they never inherit an initialised device
         import multiprocessing as mp
@@ -853,6 +935,9 @@ def main():
     if args.only in ("all", "params"):
         out["params"] = bench_params(zx, pool)
         log("params: %s" % out["params"])
+    if args.only in ("all", "extract"):
+        out["extract"] = bench_extract(zx, pool)
+        log("extract: %s" % out["extract"])
     if args.only in ("all", "learned"):
         out["learned"] = bench_learned(zx, args, pool)
         log("learned: %s" % out["learned"])

@@ -395,6 +395,52 @@ zx_status zx_gflow(zx_graph* const* graphs, int32_t n_graphs, int32_t* layers, i
                    size_t ws_bytes, hipStream_t s);
 
 /* ======================================================================
+ * Circuit extraction
+ *
+ * The paper reduces diagrams and eliminates binary matrices over F2 but
+ * leaves extraction to the standard procedure (Backens, Miller-Bakewell, de
+ * Felice, Lobski, van de Wetering, "There and back again", Quantum 2021),
+ * run here on the CURRENT diagram of each graph.  Every input spider is
+ * first unfused into input -- a -H- b -H- v.  From the outputs inwards,
+ * each round: Z rotations for the frontier spiders' phases (qubit order), CZ
+ * gates for their mutual edges (pairs a < b in order), then Gauss-Jordan
+ * elimination over F2 of the biadjacency between the frontier spiders that
+ * are not input spiders (rows, qubit order) and their other neighbours
+ * (columns, ascending id): lowest pivot column first, lowest row within
+ * it, a row swap as three row additions, every row addition row_t += row_s
+ * a CNOT with control t and target s, applied to the graph; then every row
+ * with a single neighbour w is an H gate and that qubit's frontier moves to
+ * w.  A Hadamard output wire is an H gate first.
+ *
+ * Gate q (uint32): type << 30 | a << 15 | b; types ZX_GATE_H (a = qubit),
+ * ZX_GATE_RZ (a = qubit, b = k for diag(1, e^{i k pi/4})), ZX_GATE_CZ
+ * (a < b), ZX_GATE_CNOT (a = control, b = target).  Gates closest to the
+ * outputs come first: the diagram's map is G_1 G_2 ... G_m P up to a scalar,
+ * where P takes input wire perm[q] to qubit q (after the Hadamards of
+ * Hadamard input wires).
+ * gates: n_graphs x max_gates (graph i's from i * max_gates); n_gates[i]:
+ * gates of graph i's circuit (beyond max_gates only the first max_gates are
+ * written, and status[i] = ZX_ECAPACITY); perm: sum of the graphs' n_out
+ * int32 (graph i's after those of graphs 0..i-1), -1 for a qubit whose
+ * frontier spider carries no input; status[i]: ZX_OK, ZX_ENOMATCH when the
+ * procedure stops (no frontier row with a single neighbour, spiders left
+ * outside the frontier, or a frontier spider without an input: the diagram
+ * has no flow), ZX_ECAPACITY, or the diagram's own sticky status.
+ * n + 2 n_in <= 1024 per graph (ZX_ECAPACITY on the host otherwise).
+ * ws: device workspace of zx_extract_workspace_bytes(n_graphs), 256-byte
+ * aligned; the call uploads the batch table into it and synchronises s
+ * once before launching.  Device arrays; asynchronous on s after that.
+ * ==================================================================== */
+#define ZX_GATE_H 0u
+#define ZX_GATE_RZ 1u
+#define ZX_GATE_CZ 2u
+#define ZX_GATE_CNOT 3u
+size_t zx_extract_workspace_bytes(int32_t n_graphs);
+zx_status zx_extract(zx_graph* const* graphs, int32_t n_graphs, int32_t max_gates, uint32_t* gates,
+                     int32_t* n_gates, int32_t* perm, int32_t* status, void* ws, size_t ws_bytes,
+                     hipStream_t s);
+
+/* ======================================================================
  * Detector sampling: f = T e mod 2
  *
  * Section on the repetition-code example (equation detector_sampling) and

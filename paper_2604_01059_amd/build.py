@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzx.so")
 ROOT = os.path.dirname(HERE)
-SOURCES = ["runtime.hip", "gf2.hip", "gf2mm.hip", "pauli.hip", "graph.hip", "mlp.hip", "serve.hip", "sample.hip", "flow.hip"]
+SOURCES = ["runtime.hip", "gf2.hip", "gf2mm.hip", "pauli.hip", "graph.hip", "mlp.hip", "serve.hip", "sample.hip", "flow.hip", "extract.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -20,6 +20,7 @@ ZX_RESUME = 0x2
 ZX_FALLBACK = 0x4
 ZX_SYNC = 0x100
 ZX_POLICY_GREEDY, ZX_POLICY_LEARNED = 0, 1
+ZX_GATE_H, ZX_GATE_RZ, ZX_GATE_CZ, ZX_GATE_CNOT = 0, 1, 2, 3
 MLP_IN, MLP_HID = 16, 256
 MLP_NPARAM = MLP_IN * MLP_HID + 2 * MLP_HID + 1
 MLP_NBF16 = MLP_IN * MLP_HID + MLP_HID
@@ -127,6 +128,8 @@ def load():
         "zx_detector_status": ([P, P], i32),
         "zx_gflow_workspace_bytes": ([i32], sz),
         "zx_gflow": ([P, i32, P, P, P, sz, P], i32),
+        "zx_extract_workspace_bytes": ([i32], sz),
+        "zx_extract": ([P, i32, i32, P, P, P, P, P, sz, P], i32),
         "zx_mlp_sync": ([C.POINTER(MlpHandle), P], i32),
         "zx_mlp_forward": ([C.POINTER(MlpHandle), P, i64, P, P], i32),
         "zx_mlp_loss": ([P, P, P, i32, P, P, P], i32),
@@ -162,7 +165,7 @@ def exported_symbols():
             "zx_gf2_eliminate", "zx_gf2_eliminate_noalloc", "zx_gf2_status", "zx_gf2_profile_read", "zx_pauli_commute",
             "zx_gf2_matmul", "zx_phase_pair_product", "zx_detector_workspace_bytes",
             "zx_detector_sample", "zx_detector_status", "zx_gflow_workspace_bytes", "zx_gflow",
-            "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
+            "zx_extract_workspace_bytes", "zx_extract", "zx_mlp_sync", "zx_mlp_forward", "zx_mlp_loss", "zx_mlp_workspace_bytes", "zx_mlp_backward",
             "zx_mlp_adam", "zx_rollout_workspace_bytes", "zx_rollout", "zx_policy_features", "zx_server_create",
             "zx_server_submit", "zx_server_poll", "zx_server_stats_read", "zx_server_destroy"]
 
@@ -675,6 +678,52 @@ def gflow(graphs, stream=None):
         out.append(lay[off:off + g.n].copy())
         off += g.n
     return exists.cpu().numpy(), out
+
+
+def decode_gates(words):
+    """uint32 gate words -> ("H", q) / ("RZ", q, k) / ("CZ", a, b) / ("CNOT", c, t)."""
+    out = []
+    for w in np.asarray(words, np.uint32).tolist():
+        t, a, b = w >> 30, (w >> 15) & 0x7FFF, w & 0x7FFF
+        if t == ZX_GATE_H:
+            out.append(("H", a))
+        elif t == ZX_GATE_RZ:
+            out.append(("RZ", a, b))
+        elif t == ZX_GATE_CZ:
+            out.append(("CZ", a, b))
+        else:
+            out.append(("CNOT", a, b))
+    return out
+
+
+def extract(graphs, max_gates=None, stream=None, raw=False):
+    """Circuits of the CURRENT diagrams (zx_extract).  Returns one
+    (status, gates, perm) per graph: gates decoded (``raw``: the uint32
+    words), perm[q] = input wire of qubit q.  max_gates defaults to a bound
+    on what a diagram of that size can emit."""
+    import torch
+    n = len(graphs)
+    if max_gates is None:
+        max_gates = max(64, max((g.n + 2 * g.n_in) * (g.n_out + 4) for g in graphs))
+    gates = torch.empty(n * max_gates, dtype=torch.int32, device="cuda")
+    n_gates = torch.empty(n, dtype=torch.int32, device="cuda")
+    perm = torch.empty(max(1, sum(g.n_out for g in graphs)), dtype=torch.int32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    nb = load().zx_extract_workspace_bytes(n)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    _check(load().zx_extract(_graph_array(graphs), n, int(max_gates), _ptr(gates), _ptr(n_gates), _ptr(perm),
+                             _ptr(status), _ptr(ws), nb, _stream(stream)))
+    G = gates.cpu().numpy().view(np.uint32).reshape(n, max_gates)
+    ng, st, pm = n_gates.cpu().numpy(), status.cpu().numpy(), perm.cpu().numpy()
+    need = int(ng[st == ZX_ECAPACITY].max()) if (st == ZX_ECAPACITY).any() else 0
+    if need > max_gates:  # the buffer was short: once more with the counted size
+        return extract(graphs, max_gates=need, stream=stream, raw=raw)
+    out, off = [], 0
+    for i, g in enumerate(graphs):
+        words = G[i, :min(int(ng[i]), max_gates)].copy()
+        out.append((int(st[i]), words if raw else decode_gates(words), pm[off:off + g.n_out].copy()))
+        off += g.n_out
+    return out
 
 
 class DetectorSampler:
