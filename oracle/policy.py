@@ -1,6 +1,5 @@
-"""Reference of the learned proposal's candidate handling (local
-complementation rounds) and of the checks on schedules other than the
-canonical one.
+"""Reference of the learned proposal's candidate handling and of the checks
+on schedules other than the canonical one.
 
 TEST INFRASTRUCTURE ONLY (imported by ``tests/``).
 
@@ -10,6 +9,17 @@ decompositions", first paragraph) but no order of application.  Any order
 reaches a fixed point by sound rewrites, so a schedule that is not the
 canonical one is checked by replaying its trace with the rule
 implementations of the C oracle, which verify each precondition.
+
+The learned schedule keeps the canonical phases (local complementations
+until none is left, then pivots) and reorders each round's candidates by
+the network's scores:
+* an LC round lists its candidate spiders (ascending) and takes them in
+  priority order, each unless adjacent to one taken before;
+* a pivot round lists the candidate edges u < v between Pauli spiders in
+  lexicographic order, at most list_cap(n) of them, takes them in priority
+  order, each unless an end is taken or adjacent to a taken end, and then
+  completes the round with the canonical lexicographic pass over what is
+  left (so the round is maximal even when the list was cut short).
 
 Everything here is written with plain Python loops over an oracle ``Graph``.
 """
@@ -29,10 +39,34 @@ def pauli_candidates(g: Graph):
     return [u for u in range(g.n) if g.is_alive(u) and not g.has_boundary(u) and g.k[u] % 4 == 0]
 
 
+def list_cap(n: int) -> int:
+    """Length of a round's candidate list: the least power of two >= max(64, n)."""
+    c = 64
+    while c < n:
+        c *= 2
+    return c
+
+
+def pivot_edges(g: Graph):
+    """Edges (u, v), u < v, between Pauli candidates, lexicographic, at most
+    list_cap(n) of them."""
+    P = pauli_candidates(g)
+    edges = []
+    for i, u in enumerate(P):
+        for v in P[i + 1:]:
+            if g.edge(u, v):
+                edges.append((u, v))
+    return edges[: list_cap(g.n)]
+
+
 def candidate_list(g: Graph):
-    """The candidates of an LC round as the learned policy lists them:
-    (u, -1) for the LC candidates, ascending (empty past the LC phase)."""
-    return [(u, -1) for u in lc_candidates(g)]
+    """The candidates of the next round as the learned schedule lists them:
+    (u, -1) for the LC candidates, ascending, while there are any; then the
+    pivot edges (u, v)."""
+    lc = lc_candidates(g)
+    if lc:
+        return [(u, -1) for u in lc]
+    return pivot_edges(g)
 
 
 def neighbours(g: Graph, x):
@@ -58,12 +92,20 @@ def endpoint_features(g: Graph, x, N):
             f32(bnd) / Nf, f32(len(two)) / Nf, f32(pauli) / Nf]
 
 
-def features(g: Graph, u) -> np.ndarray:
-    """The 16 features of LC candidate u as bf16 bit patterns (uint16):
-    its seven endpoint features, seven zeros, rule bit 0, constant 1."""
+def _entry(e):
+    return (int(e), -1) if np.ndim(e) == 0 else (int(e[0]), int(e[1]))
+
+
+def features(g: Graph, entry) -> np.ndarray:
+    """The 16 features of a candidate as bf16 bit patterns (uint16): the seven
+    endpoint features of u, those of v (zeros for an LC candidate), the rule
+    bit (1 for a pivot), constant 1.  entry: u, (u, -1) or (u, v)."""
     from .mlp import bf16_round
+    u, v = _entry(entry)
     N = max(1, len(g.alive_list()))
-    f = endpoint_features(g, u, N) + [np.float32(0)] * 7 + [np.float32(0.0), np.float32(1.0)]
+    f = endpoint_features(g, u, N)
+    f += endpoint_features(g, v, N) if v >= 0 else [np.float32(0)] * 7
+    f += [np.float32(1.0 if v >= 0 else 0.0), np.float32(1.0)]
     r = bf16_round(np.array(f, dtype=np.float32))
     return (r.view(np.uint32) >> 16).astype(np.uint16)
 
@@ -77,16 +119,55 @@ def gate2q(g: Graph) -> int:
     return g.n_edges() + ops
 
 
-def rollout(state: Graph, u):
-    """Apply LC at u, then the canonical schedule to the fixed point:
-    (cost, fill-in added)."""
+def rollout(state: Graph, entry):
+    """Apply the candidate (LC at u, or the pivot on (u, v)), then the
+    canonical schedule to the fixed point: (cost, fill-in added)."""
     g = state.copy()
     f0 = g.scalar.fill_in
-    rc = g.local_comp(u)
+    u, v = _entry(entry)
+    rc = g.local_comp(u) if v < 0 else g.pivot(u, v)
     assert rc == OK, "candidate precondition failed"
     rc = g.simplify()
     assert rc == OK
     return gate2q(g), g.scalar.fill_in - f0
+
+
+def lc_round_in_order(g: Graph, order):
+    """An LC round that visits the candidates in the given order: each is
+    taken unless adjacent to one taken before it."""
+    taken = []
+    for u in order:
+        if not any(g.edge(u, t) for t in taken):
+            taken.append(u)
+    return taken
+
+
+def pivot_round_in_order(g: Graph, order):
+    """A pivot round that visits the listed edges in the given order, then
+    completes it canonically: for each Pauli candidate u (ascending) whose
+    end is free, the smallest free Pauli neighbour v > u.  An end is free
+    when it is neither taken nor adjacent to a taken end.  Returns the pairs
+    in the order taken."""
+    blocked = set()
+    pairs = []
+
+    def take(u, v):
+        pairs.append((u, v))
+        blocked.update((u, v))
+        blocked.update(y for y in range(g.n) if g.edge(u, y) or g.edge(v, y))
+
+    for u, v in order:
+        if u not in blocked and v not in blocked:
+            take(u, v)
+    P = pauli_candidates(g)
+    for u in P:
+        if u in blocked:
+            continue
+        for v in P:
+            if v > u and v not in blocked and g.edge(u, v):
+                take(u, v)
+                break
+    return pairs
 
 
 def replay(g: Graph, trace) -> Graph:

@@ -146,6 +146,103 @@ def test_candidate_list_is_the_lc_candidates():
     f = policy.features(g, expect[0])
     assert f.dtype == np.uint16 and f.shape == (16,)
     assert np.all(f[7:15] == 0) and f[15] == 0x3F80  # bf16(1.0)
+    np.testing.assert_array_equal(policy.features(g, ent[0]), f)
+
+
+def test_pivot_candidate_list_is_lexicographic_and_capped():
+    n = 20  # 16 interior Pauli spiders, complete among themselves: 120 edges > cap 64
+    adj = np.zeros((n, 1), np.uint64)
+    for i in range(2, 18):
+        for j in range(2, 18):
+            if i != j:
+                adj[i, 0] |= np.uint64(1) << np.uint64(j)
+    ph = np.zeros(n, np.int8)
+    g = oracle.Graph(n, adj, ph, inputs=[0, 1], outputs=[18, 19])
+    ent = policy.candidate_list(g)
+    assert len(ent) == 64 == policy.list_cap(n)
+    allp = [(u, v) for u in range(2, 18) for v in range(u + 1, 18)]
+    assert ent == allp[:64]
+    # features of an edge: both endpoints' seven, rule bit 1, constant 1
+    f = policy.features(g, ent[5])
+    N = n
+    from oracle.mlp import bf16_round
+    e = policy.endpoint_features(g, ent[5][0], N) + policy.endpoint_features(g, ent[5][1], N)
+    expect = (bf16_round(np.array(e + [1.0, 1.0], np.float32)).view(np.uint32) >> 16).astype(np.uint16)
+    np.testing.assert_array_equal(f, expect)
+    assert f[14] == 0x3F80 and f[15] == 0x3F80
+    # the list continues from an LC phase only once it is over
+    ph2 = ph.copy()
+    ph2[7] = 2
+    g2 = oracle.Graph(n, adj, ph2, inputs=[0, 1], outputs=[18, 19])
+    assert policy.candidate_list(g2) == [(7, -1)]
+
+
+def pivot_phase_states(seeds):
+    """(state, next round's pairs) at the pivot rounds of the C oracle's
+    canonical schedule."""
+    out = []
+    for seed in seeds:
+        d = single_diagram(seed)
+        full = oracle.Graph.from_diagram(d)
+        full.simplify()
+        tr = full.trace
+        for r in range(full.rounds):
+            sel = tr[tr[:, 0] == r]
+            if sel[0, 1] != 1:
+                continue
+            g = oracle.Graph.from_diagram(d)
+            if r:
+                g.simplify(max_rounds=r)
+            out.append((g, [(int(u), int(v)) for _, _, u, v in sel]))
+    return out
+
+
+def test_canonical_pivot_round_is_the_completion_alone():
+    """With nothing listed first, the learned pivot round is the canonical one
+    (the C oracle's trace), pair for pair and in order."""
+    states = pivot_phase_states(range(1, 9))
+    assert len(states) >= 5
+    for g, pairs in states:
+        assert not policy.lc_candidates(g)
+        assert policy.pivot_round_in_order(g, []) == pairs
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pivot_rounds_in_any_order_are_valid_and_maximal(seed):
+    """Any visiting order of the listed edges, including a list cut short,
+    gives a round the independent validity check accepts (pairs disjoint,
+    mutually non-adjacent, maximal); the visiting order decides which pairs
+    come first."""
+    r = np.random.default_rng(seed)
+    states = pivot_phase_states(range(1 + 8 * seed, 9 + 8 * seed))
+    checked = 0
+    for g, _ in states:
+        ent = policy.candidate_list(g)
+        assert ent and all(v >= 0 for _, v in ent)
+        for trial in range(3):
+            order = [ent[i] for i in r.permutation(len(ent))]
+            if trial == 2:
+                order = order[: max(1, len(order) // 3)]
+            pairs = policy.pivot_round_in_order(g, order)
+            assert policy.round_is_valid(g, pairs, True)
+            assert pairs[0] == order[0]
+            h = g.copy()
+            for u, v in pairs:
+                assert h.pivot(u, v) == oracle.OK
+            checked += 1
+    assert checked >= 6
+
+
+def test_lc_round_in_order_is_valid():
+    for seed in range(1, 6):
+        g = oracle.Graph.from_diagram(single_diagram(seed))
+        lc = policy.lc_candidates(g)
+        if not lc:
+            continue
+        order = list(reversed(lc))
+        taken = policy.lc_round_in_order(g, order)
+        assert taken[0] == order[0]
+        assert policy.round_is_valid(g, [(u, -1) for u in taken], False)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -202,3 +299,28 @@ def test_rollout_is_sound_on_a_tiny_diagram():
         assert evaluate_graph(h).equals(amp0)
         cost, _ = policy.rollout(g, u)
         assert cost == policy.gate2q(h)
+
+
+def test_pivot_rollout_is_sound_on_a_tiny_diagram():
+    """A pivot candidate's rollout: the pivot, then the canonical schedule;
+    the result has the diagram's exact tensor."""
+    found = 0
+    for seed in range(400):
+        g, _ = small_graph(9, 0.45, 500 + seed)
+        if policy.lc_candidates(g):
+            continue
+        ent = policy.candidate_list(g)
+        if not ent:
+            continue
+        amp0 = evaluate_graph(g)
+        for u, v in ent[:3]:
+            h = g.copy()
+            assert h.pivot(u, v) == oracle.OK
+            h.simplify()
+            assert evaluate_graph(h).equals(amp0)
+            cost, fill = policy.rollout(g, (u, v))
+            assert cost == policy.gate2q(h) and fill == h.scalar.fill_in - g.scalar.fill_in
+            found += 1
+        if found >= 4:
+            break
+    assert found >= 4
