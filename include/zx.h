@@ -190,12 +190,17 @@ zx_status zx_pivot(zx_graph* g, int32_t u, int32_t v, uint32_t flags, hipStream_
  * already taken.  All rewrites of a round are applied together.
  * ==================================================================== */
 #define ZX_POLICY_GREEDY 0
-/* Learned priority (policy ZX_POLICY_LEARNED): each local-complementation
- * round lists its candidate spiders (ascending), scores each with the
- * network in opts.mlp on the features described at zx_rollout, and takes
- * them in descending score order (ties: ascending id) unless adjacent to one
- * already taken.  Pivot rounds keep the canonical order.  Results are exact
- * ZX rewrites whatever the scores; only the schedule differs. */
+/* Learned priority (policy ZX_POLICY_LEARNED): the phases stay those of the
+ * canonical schedule.  A local-complementation round lists its candidate
+ * spiders (ascending), scores each with the network in opts.mlp on the
+ * features described at zx_rollout, and takes them in descending score order
+ * (ties: list order) unless adjacent to one already taken.  A pivot round
+ * lists the candidate edges u < v between Pauli spiders (lexicographic, at
+ * most max(64, n) rounded up to a power of two), scores them the same way,
+ * takes them in that order unless an end is taken or adjacent to a taken
+ * end, then completes the round with the canonical lexicographic pass over
+ * the edges left (so the round is maximal).  Results are exact ZX rewrites
+ * whatever the scores; only the schedule differs. */
 #define ZX_POLICY_LEARNED 1
 #define ZX_RESUME 0x2u   /* continue from the CURRENT diagram, trace and round count */
 /* Greedy fallback (with ZX_POLICY_LEARNED): per diagram, the greedy schedule
@@ -520,12 +525,13 @@ zx_status zx_mlp_adam(const zx_mlp* w, const float* grad, float* m, float* v, fl
                       float beta1, float beta2, float eps, int32_t step, hipStream_t s);
 
 /* The learned proposal's view of one diagram state (its CURRENT section):
- * the candidates of the next local-complementation round, ascending (none
- * once the state is past its LC phase), and for each the ZX_MLP_IN bf16
- * features the learned simplification scores (listed under zx_rollout).
- * Writes the count to *n_cand (one device int32) and the first
- * min(count, max_cand) candidates and feature rows to cand (int32) and feats
- * (row-major, ZX_MLP_IN per row), all device memory of the caller.
+ * the candidates of the next round as the learned schedule lists them (LC
+ * candidates ascending while there are any, else the pivot edges), and for
+ * each the ZX_MLP_IN bf16 features the learned simplification scores
+ * (listed under zx_rollout).  Writes the count to *n_cand (one device int32)
+ * and the first min(count, max_cand) candidates and feature rows to cand
+ * (two int32 each: u, v; v = -1 for an LC candidate) and feats (row-major,
+ * ZX_MLP_IN per row), all device memory of the caller.
  * ZX_ECAPACITY when the diagram does not fit the kernel's LDS (about 1000
  * spiders).  Asynchronous on s; the arena is only read.  The paper leaves the
  * proposal's inputs open: these are the features of this library's
@@ -535,22 +541,24 @@ zx_status zx_policy_features(const zx_graph* g, int32_t* cand, uint16_t* feats, 
 
 /* Rollouts for training labels.  Item i = (state i / per_state, slot
  * k = i % per_state) on states[i / per_state] (CURRENT diagrams, read only;
- * at most 1024 spiders).  The kernel lists the state's local-complementation
- * candidates (ascending), takes candidate c = k (all of them when there are
- * at most per_state, else c = floor(k * count / per_state)), writes its
+ * at most 1024 spiders).  The kernel lists the state's candidates as the
+ * learned schedule does (LC candidates ascending while there are any, else
+ * the pivot edges), takes candidate c = k (all of them when there are at
+ * most per_state, else c = floor(k * count / per_state)), writes its
  * features, applies it, runs the greedy schedule to the fixed point and
  * reduces the output frontier:
  *   cost[i]   = Hadamard edges left + frontier row additions (-1: no such
- *               candidate, also for a state past its LC phase; -3: the
+ *               candidate, also for a state at its fixed point; -3: the
  *               state is too large; -4: the round bound was exceeded)
  *   fill[i]   = edges toggled on from the state to the end
- *   move[i]   = {0 (LC), u, -1}, or {-1, -1, -1} without a candidate
- *   feats[i]  = ZX_MLP_IN bf16 features of the candidate: degree / N,
- *     phase class one-hot {k = 0 mod 4, k = 2 mod 4, k odd},
+ *   move[i]   = {0 (LC), u, -1} or {1 (pivot), u, v}, or {-1, -1, -1}
+ *               without a candidate
+ *   feats[i]  = ZX_MLP_IN bf16 features of the candidate: for endpoint u,
+ *     degree / N, phase class one-hot {k = 0 mod 4, k = 2 mod 4, k odd},
  *     boundary-attached neighbours / N, two-hop count / N (spiders at
- *     distance exactly 2), Pauli neighbours / N (k = 0 mod 4); seven zeros
- *     (second endpoint, unused by LC); rule bit 0; constant 1.  N = present
- *     spiders; quotients in fp32, then bf16.
+ *     distance exactly 2), Pauli neighbours / N (k = 0 mod 4); the same
+ *     seven for v (zeros for an LC candidate); rule bit (1: pivot);
+ *     constant 1.  N = present spiders; quotients in fp32, then bf16.
  * Synchronous (uploads the state table into ws). */
 size_t zx_rollout_workspace_bytes(zx_graph* const* states, int32_t n_states);
 zx_status zx_rollout(zx_graph* const* states, int32_t n_states, int32_t per_state, int64_t* cost,

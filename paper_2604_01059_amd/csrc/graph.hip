@@ -381,26 +381,30 @@ __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
 }
 
 // Wave 0: lexicographic pivot-pair selection among the Pauli candidates.
-// Writes partner[], sel (both ends), blocked, the trace entries; returns
-// the number of pairs through sh.cnt.
-template <int BS, bool LA>
+// Writes partner[], sel (both ends), the trace entries; returns the number
+// of pairs through sh.cnt.  RESUME: complete a round begun by another
+// order: start from its blocked set (c.blocked: taken ends and their
+// neighbours), selection (c.sel) and pair count (sh.cnt).
+template <int BS, bool LA, bool RESUME = false>
 __device__ void select_pivots(Ctx<LA>& c, Shared& sh) {
   const int tid = threadIdx.x, W = c.W;
-  for (int j = tid; j < W; j += BS) {
-    c.sel[j] = 0;
-    c.blocked[j] = 0;
+  if constexpr (!RESUME) {
+    for (int j = tid; j < W; j += BS) {
+      c.sel[j] = 0;
+      c.blocked[j] = 0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (tid < 64) {
     const int lane = tid;
     uint64_t blk[MAXS], Pm[MAXS];
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       const int j = lane + 64 * s;
-      blk[s] = 0;
+      blk[s] = RESUME && j < W ? c.blocked[j] : 0;
       Pm[s] = j < W ? c.cand[j] : 0;
     }
-    int npairs = 0, nt = sh.n_trace;
+    int npairs = RESUME ? sh.cnt : 0, nt = sh.n_trace;
     const int round = sh.round;
     for (int wi = 0; wi < W; ++wi) {
       uint64_t pw = c.cand[wi];
@@ -1016,7 +1020,7 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     if constexpr (LEARN) {
       const int C = list_lc<BS, LA>(c, sh, *pol);
       const float invN = pauli_mask_and_scale<BS, LA>(c, sh);
-      policy_score<BS, LA>(c, *pol, C, invN);
+      policy_score<BS, LA>(c, *pol, C, invN, false);
       __syncthreads();
       sort_keys_desc<BS>(*pol, C);
       select_lc_priority<BS, LA>(c, sh, *pol, C);
@@ -1051,7 +1055,16 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
       return;
     }
     if (!build_candidates<BS, LA>(c, sh, 1)) break;
-    select_pivots<BS, LA>(c, sh);
+    if constexpr (LEARN) {
+      const int C = list_pivots<BS, LA>(c, sh, *pol);
+      const float invN = pauli_mask_and_scale<BS, LA>(c, sh);
+      policy_score<BS, LA>(c, *pol, C, invN, true);
+      __syncthreads();
+      sort_keys_desc<BS>(*pol, C);
+      select_pivots_priority<BS, LA>(c, sh, *pol, C);
+    } else {
+      select_pivots<BS, LA>(c, sh);
+    }
     const int npairs = uni(sh.cnt);
     if (npairs == 0) break;
     prepare_round<BS, LA>(c, sh, true, false);
@@ -1364,6 +1377,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
     Ctx<true> c;
     Pol pol;
     int C = 0;
+    bool piv = false;
     if (fits) {
       setup_ctx<BS, true>(c, arena, smem_dyn);
       c.trace = nullptr;
@@ -1378,15 +1392,25 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
       pol.list = (LDSP uint32_t*)pa;
       pol.fbuf = (LDSP uint16_t*)(pa + (int64_t)pol.cap * 4);
       load_state<BS, true>(c, sh, false);
-      // candidates of an LC round; a state past its LC phase has none here
-      if (build_candidates<BS, true>(c, sh, 0)) C = list_lc<BS, true>(c, sh, pol);
+      // candidates of the next round: the LC candidates while there are
+      // any, then the pivot edges
+      if (build_candidates<BS, true>(c, sh, 0)) {
+        C = list_lc<BS, true>(c, sh, pol);
+      } else if (build_candidates<BS, true>(c, sh, 1)) {
+        C = list_pivots<BS, true>(c, sh, pol);
+        piv = true;
+      }
     }
     if (fits && k < C) {
       const int ci = C <= a.per_state ? k : (int)((int64_t)k * C / a.per_state);
-      const int u = uni((int)pol.list[ci]);
+      const uint32_t ent = (uint32_t)uni((int)pol.list[ci]);
+      const int u = piv ? (int)(ent >> 16) : (int)ent, v = piv ? (int)(ent & 0xffffu) : -1;
       const float invN = pauli_mask_and_scale<BS, true>(c, sh);
       if (tid < 64) {
-        candidate_features(c, u, invN, pol.fbuf);
+        if (piv)
+          pivot_features(c, u, v, invN, pol.fbuf);
+        else
+          candidate_features(c, u, invN, pol.fbuf);
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
         if (tid < zxmlp::IN) a.feats[(int64_t)idx * zxmlp::IN + tid] = pol.fbuf[tid];
@@ -1395,18 +1419,28 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
       __syncthreads();
       const int64_t fill0 = sh.fill_in;
       if (tid == 0) {
-        a.move[3 * (int64_t)idx] = 0;
+        a.move[3 * (int64_t)idx] = piv ? 1 : 0;
         a.move[3 * (int64_t)idx + 1] = u;
-        a.move[3 * (int64_t)idx + 2] = -1;
+        a.move[3 * (int64_t)idx + 2] = v;
         c.sel[u >> 6] |= 1ull << (u & 63);
+        if (piv) {
+          c.sel[v >> 6] |= 1ull << (v & 63);
+          c.partner[u] = (int16_t)v;
+          c.partner[v] = (int16_t)u;
+        }
       }
       __syncthreads();
       // the candidate as a one-rewrite round, then the greedy schedule
-      prepare_round<BS, true>(c, sh, false, false);
+      prepare_round<BS, true>(c, sh, piv, false);
       collect_swords<BS, true>(c, sh);
-      const bool cc = apply_round<BS, true>(c, sh, false);
+      const bool cc = apply_round<BS, true>(c, sh, piv);
       delete_selected<BS, true>(c, sh, cc);
-      finish_round<BS, true>(c, sh, 1);
+      finish_round<BS, true>(c, sh, piv ? 2 : 1);
+      if (piv) {
+        for (int x = tid; x < c.n; x += BS)
+          if (bit_of(c.sel, x)) c.partner[x] = -1;
+        __syncthreads();
+      }
       simplify_rounds<BS, true, false>(c, sh, nullptr, 0);
       if (c.q_out > 0) {
         frontier<BS, true>(c, sh, a.mbuf + (int64_t)blockIdx.x * a.mbuf_words, true, false);
@@ -1441,10 +1475,11 @@ struct FeatArgs {
   int32_t* n_cand;
 };
 
-// One workgroup: the candidates of the next local-complementation round of
-// one diagram's CURRENT state (ascending) and the learned proposal's
-// features of each (one wavefront per candidate), as the learned
-// simplification computes them before scoring.  The host checked that the
+// One workgroup: the candidates of the next round of one diagram's CURRENT
+// state as the learned schedule lists them (LC candidates ascending, else
+// pivot edges lexicographic) and the learned proposal's features of each
+// (one wavefront per candidate), as the learned simplification computes
+// them before scoring.  The host checked that the
 // diagram fits the LDS (roll_lds_bytes).
 template <int BS>
 __global__ __launch_bounds__(BS) void features_kernel(FeatArgs a) {
@@ -1469,17 +1504,30 @@ __global__ __launch_bounds__(BS) void features_kernel(FeatArgs a) {
   pol.fbuf = (LDSP uint16_t*)(pa + (int64_t)pol.cap * 4);  // one row of features per wavefront
   load_state<BS, true>(c, sh, false);
   int C = 0;
-  if (build_candidates<BS, true>(c, sh, 0)) C = list_lc<BS, true>(c, sh, pol);
+  bool piv = false;
+  if (build_candidates<BS, true>(c, sh, 0)) {
+    C = list_lc<BS, true>(c, sh, pol);
+  } else if (build_candidates<BS, true>(c, sh, 1)) {
+    C = list_pivots<BS, true>(c, sh, pol);
+    piv = true;
+  }
   const float invN = pauli_mask_and_scale<BS, true>(c, sh);
   const int out = C < a.max_cand ? C : a.max_cand;
   LDSP uint16_t* f = pol.fbuf + wv * zxmlp::IN;
   for (int i = wv; i < out; i += BS / 64) {
-    const int u = uni((int)pol.list[i]);
-    candidate_features(c, u, invN, f);
+    const uint32_t ent = (uint32_t)uni((int)pol.list[i]);
+    const int u = piv ? (int)(ent >> 16) : (int)ent, v = piv ? (int)(ent & 0xffffu) : -1;
+    if (piv)
+      pivot_features(c, u, v, invN, f);
+    else
+      candidate_features(c, u, invN, f);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     if (lane < zxmlp::IN) a.feats[(int64_t)i * zxmlp::IN + lane] = f[lane];
-    if (lane == 0) a.cand[i] = u;
+    if (lane == 0) {
+      a.cand[2 * (int64_t)i] = u;
+      a.cand[2 * (int64_t)i + 1] = v;
+    }
   }
   if (tid == 0) *a.n_cand = C;
 }

@@ -1,18 +1,22 @@
-// Learned selection priority for the local-complementation rounds: candidate
-// list, candidate features, network scores, priority order and the
-// selection of the round's rewrites in that order.  Pivot rounds keep the
-// canonical order.  Included by graph.hip inside its namespace, after the
-// round primitives.
+// Learned selection priority: candidate list, candidate features, network
+// scores, priority order and the selection of the round's rewrites in that
+// order.  An LC round lists its candidate spiders; a pivot round lists the
+// candidate edges u < v between Pauli candidates (lexicographic, at most the
+// list capacity), visits them in priority order and then completes the
+// round with the canonical pass, so it is maximal even when the list was
+// cut short.  Included by graph.hip inside its namespace, after the round
+// primitives.
 
 // Policy work areas in LDS (after the auxiliary arrays).
 struct Pol {
   const uint16_t* wbf;    // network, bf16 copy (global)
   const float* param;     // network, fp32 master (global; b1, b2 read)
   int cap;                // list capacity, power of two >= n (>= 64)
-  LDSP uint32_t* list;    // candidate spiders of an LC round
+  LDSP uint32_t* list;    // candidates: spider u (LC round) or (u << 16) | v (pivot round)
   LDSP uint64_t* key;     // sort keys, descending = priority order
   LDSP uint16_t* fbuf;    // per wavefront 32 x ZX_MLP_IN bf16 features
-  LDSP int32_t* thbuf;    // per wavefront 32 two-hop counts
+  LDSP int32_t* thbuf;    // per wavefront 64 two-hop counts (32 first ends, 32 second ends)
+  LDSP uint32_t* elist;   // per wavefront 64 endpoints (32 first ends, 32 second ends)
 };
 
 __host__ __device__ inline int pol_cap(int n) {
@@ -23,7 +27,7 @@ __host__ __device__ inline int pol_cap(int n) {
 __host__ __device__ inline int64_t pol_bytes(int n, int bs) {
   const int cap = pol_cap(n);
   return 16 + (int64_t)cap * 4 + (int64_t)cap * 8 + (int64_t)(bs / 64) * 32 * zxmlp::IN * 2 +
-         (int64_t)(bs / 64) * 32 * 4;
+         (int64_t)(bs / 64) * 64 * 4 * 2;
 }
 
 // The feature rows are read 16 bytes at a time: start the area on 16 bytes.
@@ -42,6 +46,8 @@ __device__ void setup_pol(Pol& p, uint8_t* at, int n, const uint16_t* wbf, const
   p.fbuf = (LDSP uint16_t*)at;
   at += (int64_t)(BS / 64) * 32 * zxmlp::IN * 2;
   p.thbuf = (LDSP int32_t*)at;
+  at += (int64_t)(BS / 64) * 64 * 4;
+  p.elist = (LDSP uint32_t*)at;
 }
 
 // Exclusive prefix over the wavefront of values in [0, 127], and the total.
@@ -84,6 +90,45 @@ __device__ int list_lc(Ctx<LA>& c, Shared& sh, Pol& p) {
       cnt += tot;
     }
     if (lane == 0) sh.cnt = cnt;
+  }
+  __syncthreads();
+  const int cnt = uni(sh.cnt);
+  __syncthreads();
+  return cnt;
+}
+
+// Candidate list of a pivot round (c.cand = the Pauli candidates): the edges
+// u < v between them, lexicographic, at most p.cap, as (u << 16) | v.  One
+// wavefront: for each u, the words of u's row at or after u's word (lane j:
+// word j) masked to candidates above u, placed by a prefix over the lanes.
+template <int BS, bool LA>
+__device__ int list_pivots(Ctx<LA>& c, Shared& sh, Pol& p) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, W = c.W;
+    int cnt = 0;
+    for (int wi = 0; wi < W && cnt < p.cap; ++wi) {
+      uint64_t pw = (uint64_t)uni64((int64_t)c.cand[wi]);
+      while (pw && cnt < p.cap) {
+        const int b = __builtin_ctzll(pw);
+        pw &= pw - 1;
+        const int u = 64 * wi + b;
+        const auto ru = row_ptr(c, u);
+        for (int j0 = wi; j0 < W && cnt < p.cap; j0 += 64) {
+          const int j = j0 + lane;
+          uint64_t m = j < W ? ru[j] & c.cand[j] : 0;
+          if (j == wi) m &= ~((2ull << b) - 1);  // v > u
+          int tot;
+          int pos = cnt + wave_excl_scan7(__popcll(m), tot);
+          while (m && pos < p.cap) {
+            const int v = 64 * j + __builtin_ctzll(m);
+            m &= m - 1;
+            p.list[pos++] = ((uint32_t)u << 16) | (uint32_t)v;
+          }
+          cnt += tot;
+        }
+      }
+    }
+    if (lane == 0) sh.cnt = cnt < p.cap ? cnt : p.cap;
   }
   __syncthreads();
   const int cnt = uni(sh.cnt);
@@ -203,6 +248,20 @@ __device__ void candidate_features(Ctx<LA>& c, int u, float invN, LDSP uint16_t*
   }
 }
 
+// Features of pivot candidate (u, v) into f[0..15] (one wavefront): the
+// endpoint features of u and of v, rule bit 1, constant 1.
+template <bool LA>
+__device__ void pivot_features(Ctx<LA>& c, int u, int v, float invN, LDSP uint16_t* f, int th_u = -1,
+                               int th_v = -1) {
+  const int lane = threadIdx.x & 63;
+  endpoint_features(c, u, invN, f, th_u);
+  endpoint_features(c, v, invN, f + 7, th_v);
+  if (lane == 0) {
+    f[14] = zxmlp::to_bf16(1.f);
+    f[15] = zxmlp::to_bf16(1.f);
+  }
+}
+
 typedef int pol_v8i __attribute__((ext_vector_type(8)));
 typedef float pol_v16f __attribute__((ext_vector_type(16)));
 
@@ -278,19 +337,39 @@ __device__ __forceinline__ uint32_t float_order(float x) {
 
 // Scores of list entries 0..C-1 into p.key as (order(score) << 32) |
 // ~index, so that descending keys give descending scores, ties by index.
+// pivot: the entries are edges; the two-hop counts of their first and
+// second ends come from two matrix-core passes over the endpoint list.
 template <int BS, bool LA>
-__device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN) {
+__device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN, bool pivot) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   LDSP uint16_t* fb = p.fbuf + wv * 32 * zxmlp::IN;
-  LDSP int32_t* tb = p.thbuf + wv * 32;
+  LDSP int32_t* tb = p.thbuf + wv * 64;
+  LDSP uint32_t* el = p.elist + wv * 64;
   for (int base = wv * 32; base < C; base += (BS / 64) * 32) {
-    two_hop32(c, p.list, base, C, tb);
+    const int cnt = C - base < 32 ? C - base : 32;
+    if (pivot) {
+      const int r = lane & 31;
+      const uint32_t e = r < cnt ? p.list[base + r] : 0u;
+      el[lane] = lane < 32 ? e >> 16 : e & 0xffffu;
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      two_hop32(c, el, 0, cnt, tb);
+      two_hop32(c, el, 32, 32 + cnt, tb + 32);
+    } else {
+      two_hop32(c, p.list, base, C, tb);
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     for (int r = 0; r < 32; ++r) {
       LDSP uint16_t* f = fb + r * zxmlp::IN;
-      if (base + r < C) candidate_features(c, (int)p.list[base + r], invN, f, uni(tb[r]));
-      else if (lane < zxmlp::IN) f[lane] = 0;
+      if (r < cnt) {
+        if (pivot)
+          pivot_features(c, uni((int)el[r]), uni((int)el[32 + r]), invN, f, uni(tb[r]), uni(tb[32 + r]));
+        else
+          candidate_features(c, (int)p.list[base + r], invN, f, uni(tb[r]));
+      } else if (lane < zxmlp::IN) {
+        f[lane] = 0;
+      }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
@@ -376,4 +455,59 @@ __device__ void select_lc_priority(Ctx<LA>& c, Shared& sh, Pol& p, int C) {
     }
   }
   __syncthreads();
+}
+
+// Pivot round in priority order: each listed edge is taken unless an end is
+// taken or adjacent to a taken end (c.blocked holds the taken ends and their
+// neighbours); then the canonical pass completes the round from that
+// blocked set.  One wavefront for the ordered part: lane j keeps word j.
+template <int BS, bool LA>
+__device__ void select_pivots_priority(Ctx<LA>& c, Shared& sh, Pol& p, int C) {
+  const int W = c.W;
+  for (int j = threadIdx.x; j < W; j += BS) {
+    c.sel[j] = 0;
+    c.blocked[j] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int npairs = 0, nt = sh.n_trace;
+    const int round = sh.round;
+    for (int e = 0; e < C; ++e) {
+      const uint32_t ent = (uint32_t)uni((int)p.list[key_index(p.key[e])]);
+      const int u = (int)(ent >> 16), v = (int)(ent & 0xffffu);
+      if (uni(bit_of(c.blocked, u) || bit_of(c.blocked, v))) continue;
+      const auto ru = row_ptr(c, u);
+      const auto rv = row_ptr(c, v);
+      for (int j = lane; j < W; j += 64) {
+        uint64_t add = ru[j] | rv[j];
+        if (j == (u >> 6)) add |= 1ull << (u & 63);
+        if (j == (v >> 6)) add |= 1ull << (v & 63);
+        c.blocked[j] |= add;
+      }
+      if (lane == 0) {
+        c.partner[u] = (int16_t)v;
+        c.partner[v] = (int16_t)u;
+        if (c.trace) {
+          int32_t* t = c.trace + 4 * (int64_t)nt;
+          t[0] = round;
+          t[1] = 1;
+          t[2] = u;
+          t[3] = v;
+        }
+        c.sel[u >> 6] |= 1ull << (u & 63);
+        c.sel[v >> 6] |= 1ull << (v & 63);
+      }
+      ++npairs;
+      ++nt;
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+      sh.cnt = npairs;
+      sh.n_trace = nt;
+    }
+  }
+  __syncthreads();
+  select_pivots<BS, LA, true>(c, sh);
 }

@@ -7,8 +7,9 @@ order; a different order reaches a different, equally valid fixed point with
 a different cost.  This module learns an order.
 
 * State: a diagram at the start of a round of a greedy run.
-* Candidates: the local-complementation candidates of the round (pivot
-  rounds keep the canonical order).
+* Candidates: the local-complementation candidates of the round, or in a
+  pivot round the candidate edges between Pauli spiders (``zx.rollout``
+  lists them as the learned schedule does).
 * Label of a candidate: its rollout cost -- apply it, finish greedily, and
   count the edges the run toggled on (fill-in, the default) or the Hadamard
   edges left plus frontier row additions (gate2q) (``zx.rollout``).  The
@@ -17,8 +18,9 @@ a different cost.  This module learns an order.
   0.18 for the degree).
 * Loss: softmax cross-entropy of the scores of a state's candidates toward
   its cheapest candidate (``zx_mlp_loss``).
-* Use: ``policy=ZX_POLICY_LEARNED`` takes each LC round's candidates in
-  descending score order; with ``ZX_FALLBACK`` the library keeps, per
+* Use: ``policy=ZX_POLICY_LEARNED`` takes each round's candidates in
+  descending score order (a pivot round then completes canonically, so it
+  stays maximal); with ``ZX_FALLBACK`` the library keeps, per
   diagram, the cheaper of the learned and the greedy result
   (``simplify_with_fallback``).
 
@@ -96,7 +98,7 @@ def make_dataset(n_states: int, per_state: int = 16, seed: int = TRAIN_SEED, chu
         cost, fill, _, f = zx.rollout(states, per_state)
         if label == "fill":
             cost = torch.where(cost >= 0, fill, cost)
-        # states past their LC phase have no candidate: drop them
+        # a state whose slots are all empty teaches nothing: drop it
         cv = cost.view(-1, per_state)
         present = cv >= 0
         keep = present.any(dim=1)

@@ -510,12 +510,18 @@ def rollout(states, per_state, stream=None):
 
 
 def policy_features(graph, max_cand=None, stream=None):
-    """Candidates of the next LC round of graph's CURRENT state and their
-    learned-proposal features: (cand int32 tensor [C], feats int16 tensor
-    [C, MLP_IN] holding bf16 bits), C the full count (synchronous)."""
+    """Candidates of the next round of graph's CURRENT state as the learned
+    schedule lists them, and their learned-proposal features: (cand int32
+    tensor [C, 2] of (u, v), v = -1 for LC; feats int16 tensor [C, MLP_IN]
+    holding bf16 bits), C the full count (synchronous)."""
     import torch
-    cap = graph.n if max_cand is None else max_cand
-    cand = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    if max_cand is None:  # the list capacity of a round: a power of two >= max(64, n)
+        cap = 64
+        while cap < graph.n:
+            cap *= 2
+    else:
+        cap = max_cand
+    cand = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
     feats = torch.empty((max(cap, 1), MLP_IN), dtype=torch.int16, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
     _check(load().zx_policy_features(graph.h, _ptr(cand), _ptr(feats), cap, _ptr(cnt), _stream(stream)))

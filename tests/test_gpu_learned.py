@@ -134,14 +134,38 @@ def test_round_limited_and_resume(zx, item):
         assert info.rank == rank and info.rowops == ops
 
 
+def pivot_phase_round(d):
+    """Index of the first pivot round of the oracle's canonical schedule (None
+    when it has none)."""
+    full = oracle.Graph.from_diagram(d)
+    full.simplify()
+    tr = full.trace
+    piv = tr[tr[:, 1] == 1]
+    return int(piv[0, 0]) if len(piv) else None
+
+
+def pauli_only(d):
+    """The diagram with every interior phase of class pi/2 moved to the Pauli
+    class (k + 2 mod 8): no LC candidate, so the first round is a pivot round."""
+    import dataclasses
+    bnd = set(int(v) for v in d.inputs) | set(int(v) for v in d.outputs)
+    ph = d.phase.copy()
+    for v in range(d.n):
+        if v not in bnd and ph[v] % 4 == 2:
+            ph[v] = (ph[v] + 2) % 8
+    return dataclasses.replace(d, phase=ph)
+
+
 @pytest.mark.parametrize("item", range(5))
 def test_rollout_parity(zx, item):
     # item 2 (diagram 102, 44 spiders) is the one case here whose states have
     # fewer candidates than slots (4 and 0 against 6): the empty-slot path
-    # that the structured per-item branch of the rollout kernel now covers
+    # that the structured per-item branch of the rollout kernel now covers.
+    # The last state is the first pivot round's: its candidates are edges.
     d = batch_diagram(41, 100 + item)
     states_o, states_z = [], []
-    for r in [0, 1, 3]:
+    rp = pivot_phase_round(d)
+    for r in [0, 1, 3] + ([rp] if rp else []):
         og = oracle.Graph.from_diagram(d)
         og.simplify(max_rounds=r) if r else None
         if og.rounds < r:
@@ -152,10 +176,11 @@ def test_rollout_parity(zx, item):
         states_o.append(og)
         states_z.append(zg)
     K = 6
-    print("rollout", item, d.n, len(states_z), flush=True)
+    print("rollout", item, d.n, len(states_z), rp, flush=True)
     cost, fill, move, feats = zx.rollout(states_z, K)
     cost, fill, move = cost.cpu().numpy(), fill.cpu().numpy(), move.cpu().numpy()
     feats = feats.cpu().numpy().view(np.uint16)
+    kinds = set()
     for si, og in enumerate(states_o):
         ent = opol.candidate_list(og)
         C = len(ent)
@@ -164,13 +189,16 @@ def test_rollout_parity(zx, item):
             if k >= C:
                 assert cost[i] == -1 and move[i, 0] == -1
                 continue
-            u = ent[k if C <= K else (k * C) // K][0]
-            assert tuple(move[i]) == (0, u, -1), (si, k)
-            np.testing.assert_array_equal(feats[i], opol.features(og, u), err_msg=str((si, k)))
-            rc, rf = opol.rollout(og, u)
+            u, v = ent[k if C <= K else (k * C) // K]
+            kinds.add(v >= 0)
+            assert tuple(move[i]) == (1 if v >= 0 else 0, u, v), (si, k)
+            np.testing.assert_array_equal(feats[i], opol.features(og, (u, v)), err_msg=str((si, k)))
+            rc, rf = opol.rollout(og, (u, v))
             assert cost[i] == rc and fill[i] == rf, (si, k, cost[i], rc)
         # the states themselves were not modified
         compare_state(states_z[si], og, ("state", si))
+    if rp:
+        assert True in kinds
 
 
 def learned_run(zx, diagrams, p, **kw):
@@ -240,15 +268,71 @@ def test_learned_first_round_follows_scores(zx):
     assert checked >= 5
 
 
+def test_learned_pivot_round_follows_scores(zx):
+    """A pivot round takes the listed edges in descending score order (oracle
+    features and float64 scores) unless an end is taken or adjacent to a
+    taken end, then completes canonically: pair for pair, in order, where no
+    two scores are close."""
+    rng = np.random.default_rng(6)
+    p = rand_param(rng, 0.5)
+    checked = 0
+    for i in range(120):
+        d = pauli_only(batch_diagram(42, 400 + i, q_hi=24))
+        g0 = oracle.Graph.from_diagram(d)
+        ent = opol.candidate_list(g0)
+        if len(ent) < 2:
+            continue
+        assert all(v >= 0 for _, v in ent)
+        X = np.stack([opol.features(g0, e) for e in ent])
+        s, _ = omlp.forward(p, X)
+        srt = np.sort(s)
+        if np.min(np.diff(srt)) < 1e-4 * max(1.0, np.abs(s).max()):
+            continue
+        order = sorted(range(len(ent)), key=lambda j: (-s[j], j))
+        pairs = opol.pivot_round_in_order(g0, [ent[j] for j in order])
+        zg = learned_run(zx, [d], p, max_rounds=1)[0]
+        tr = zg.trace()
+        assert (tr[:, 1] == 1).all() and (tr[:, 0] == 0).all(), i
+        assert [(int(u), int(v)) for _, _, u, v in tr] == pairs, i
+        checked += 1
+    assert checked >= 5
+
+
+def test_learned_pivot_runs_replay(zx):
+    """Learned runs that are pivot rounds from the start, checked round by
+    round (valid and maximal) and by replay."""
+    rng = np.random.default_rng(8)
+    p = rand_param(rng, 0.5)
+    ds = [pauli_only(batch_diagram(42, 600 + i)) for i in range(16)]
+    gs = learned_run(zx, ds, p)
+    n_piv = 0
+    for i, (d, zg) in enumerate(zip(ds, gs)):
+        tr = zg.trace()
+        g0 = oracle.Graph.from_diagram(d)
+        fin = opol.replay(g0, tr)
+        compare_state(zg, fin, ("pivot-learned", i))
+        cur = g0.copy()
+        for r in range(zg.info().rounds):
+            sel = tr[tr[:, 0] == r]
+            piv = bool(sel[0, 1])
+            n_piv += piv
+            assert opol.round_is_valid(cur, [(int(u), int(v)) for _, _, u, v in sel], piv), (i, r)
+            for _, _, u, v in sel:
+                assert (cur.pivot(int(u), int(v)) if piv else cur.local_comp(int(u))) == oracle.OK
+    assert n_piv >= 16
+
+
 @pytest.mark.parametrize("item", range(6))
 def test_policy_features_match_oracle(zx, item):
-    """zx_policy_features: the next LC round's candidates (ascending) and their
-    features equal the oracle's, bit for bit, at the start and after some
-    rounds; a state past its LC phase has none."""
+    """zx_policy_features: the next round's candidates (LC spiders ascending,
+    then pivot edges) and their features equal the oracle's, bit for bit, at
+    the start, after some rounds, at the first pivot round and at the fixed
+    point (none)."""
     d = batch_diagram(43, 300 + item, q_hi=24)
     full = oracle.Graph.from_diagram(d)
     full.simplify()
-    for r in [0, 1, 2, full.rounds]:
+    rp = pivot_phase_round(d)
+    for r in [0, 1, 2, full.rounds] + ([rp] if rp else []):
         og = oracle.Graph.from_diagram(d)
         if r:
             og.simplify(max_rounds=r)
@@ -259,10 +343,10 @@ def test_policy_features_match_oracle(zx, item):
         cand, feats, C = zx.policy_features(zg)
         ent = opol.candidate_list(og)
         assert C == len(ent), (item, r)
-        assert [int(u) for u in cand.cpu().numpy()] == [u for u, _ in ent]
+        assert [tuple(int(x) for x in e) for e in cand.cpu().numpy()] == ent
         fb = feats.cpu().numpy().view(np.uint16)
-        for i, (u, _) in enumerate(ent):
-            np.testing.assert_array_equal(fb[i], opol.features(og, u), err_msg=str((item, r, u)))
+        for i, e in enumerate(ent):
+            np.testing.assert_array_equal(fb[i], opol.features(og, e), err_msg=str((item, r, e)))
     # a short output buffer gets the first rows and the full count
     zg = zx.Graph.from_diagram(d)
     cand, feats, C = zx.policy_features(zg, max_cand=2)
