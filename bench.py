@@ -39,6 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # gf2.hip source they were measured on (sha256 prefix); see profiles/.
 RREF_TRAFFIC = {
     "33a1b390f0dd9346": {"fetch_kib": 25724.2, "write_kib": 11388.3},
+    # the same kernels with the allocation-free entry point beside them
+    "de70e2edf8bc1717": {"fetch_kib": 25725.0, "write_kib": 11388.3},
 }
 METRIC = "GF(2) elim GB/s (% HBM peak); diagrams simplified/sec batched vs plain, bit-exact"
 
