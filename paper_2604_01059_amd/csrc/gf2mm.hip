@@ -17,18 +17,22 @@
 //    reach the k positions of the instruction does not matter, since A and
 //    B fragments are unpacked the same way and the sum runs over all k.
 //
-//    Two tilings.  The symmetric table: workgroups of 256 threads, a
-//    256 x 256 output tile, each wavefront a 128 x 128 quarter (4 x 4
-//    blocks of 32 x 32, 256 fp32 accumulators per lane).  The rows' bits go
-//    through LDS in chunks of 256 bits (4 words, double buffered): 16 KiB
-//    per chunk for the 512 rows of the tile.  For each 64-bit step of a
-//    chunk, lane half h of a fragment takes dword 4h + s of its row's
-//    chunk.  General products with K up to 2048 bits: 128 x 128 tiles whose
-//    rows are staged whole (below), two workgroups per CU.  Parities leave
-//    through wave ballots (row words) and, for the symmetric table, through
-//    per-lane packing (the mirrored tile's row words).  Tiles are dealt to
-//    the eight XCDs in contiguous runs of the tile order, so one XCD's tiles
-//    share rows in its L2.
+//    Two tilings.  The symmetric table (and K beyond 2048 bits): one
+//    persistent workgroup of 256 threads per CU walking 256 x 256 output
+//    tiles, each wavefront a 128 x 128 quarter (4 x 4 blocks of 32 x 32, 256
+//    fp32 accumulators per lane).  The rows' bits go through LDS in chunks of
+//    256 bits (4 words, double buffered): 16 KiB per chunk for the 512 rows
+//    of the tile; the next chunk's rows are loaded while a chunk is
+//    multiplied, across tile boundaries too.  For each 64-bit step of a
+//    chunk, lane half h of a fragment takes dword 4h + s of its row's chunk.
+//    General products with K up to 2048 bits: 128 x 128 tiles whose rows are
+//    staged whole (below), two workgroups per CU.  Parities leave through
+//    wave ballots (row words) and, for the symmetric table, through per-lane
+//    packing (the mirrored tile's row words).  Tiles are dealt to the eight
+//    XCDs in contiguous runs of the tile order, so one XCD's tiles share rows
+//    in its L2.  Row loads are branch-free (the compiler otherwise waits for
+//    each load before issuing the next: 5.25 -> 3.96 ms for the 65536-string
+//    table together with the persistent pipeline).
 //
 // 2. Per setting l: omega^phase8 sqrt(2)^pow * prod_k h(alpha_k, beta_k;
 //    a_kl, b_kl), h of equation phase_pair, phases multiples of pi/4.  One
@@ -66,20 +70,23 @@ struct MmArgs {
   int64_t per_xcd;     // tiles per XCD run
 };
 
+// Word w of row r of a two-part operand (p0: kw0 words, then p1: kw1 words),
+// with the last word of each part masked to its valid bits; 0 beyond the
+// rows or the words.  Branch-free: w is the same in every lane, so the part,
+// the offset and the mask are scalar; the row is clamped to a valid address
+// and the lane's result selected.  (Branches here made the compiler wait
+// for each load before issuing the next.)
 __device__ __forceinline__ uint64_t row_word(const uint64_t* p0, const uint64_t* p1, int64_t ld, int64_t r,
                                              int64_t nrows, int w, int kw0, int kw1, uint64_t m0,
                                              uint64_t m1) {
-  if (r >= nrows) return 0;
-  if (w < kw0) {
-    const uint64_t v = p0[r * ld + w];
-    return w == kw0 - 1 ? v & m0 : v;
-  }
-  w -= kw0;
-  if (w < kw1) {
-    const uint64_t v = p1[r * ld + w];
-    return w == kw1 - 1 ? v & m1 : v;
-  }
-  return 0;
+  const bool first = w < kw0;
+  const bool in_k = w < kw0 + kw1;
+  const uint64_t* p = (first || !in_k) ? p0 : p1;
+  const int ww = first ? w : (in_k ? w - kw0 : 0);
+  uint64_t m = !in_k ? 0 : first ? (w == kw0 - 1 ? m0 : ~0ull) : (ww == kw1 - 1 ? m1 : ~0ull);
+  const int64_t rr = r < nrows ? r : nrows - 1;
+  const uint64_t v = p[rr * ld + ww];
+  return r < nrows ? v & m : 0;
 }
 
 __device__ __forceinline__ v8i unpack_fp4(uint32_t d) {
@@ -95,28 +102,33 @@ __device__ __forceinline__ v8i unpack_fp4(uint32_t d) {
   return o;
 }
 
-// tile t of the grid order -> (ti, tj)
-__device__ __forceinline__ void tile_of(const MmArgs& a, int64_t t, int& ti, int& tj) {
-  if (!a.sym) {
-    ti = (int)(t / a.tn);
-    tj = (int)(t % a.tn);
-    return;
-  }
-  // upper triangle, row by row: row i holds tn - i tiles
-  int i = 0;
-  int64_t start = 0;
-  while (start + (a.tn - i) <= t) {
-    start += a.tn - i;
-    ++i;
-  }
-  ti = i;
-  tj = i + (int)(t - start);
+// Accumulators start at 2^23: a count below 2^23 added to it stays an exact
+// fp32 integer in [2^23, 2^24), where one unit is the last mantissa bit, so
+// bit 0 of the float's bits is the count's parity.
+constexpr float ACC_BASE = 8388608.0f;
+
+// s_waitcnt operand that waits for LDS (lgkmcnt 0) and nothing else
+// (vmcnt and expcnt at their maximum).
+constexpr int WAIT_LDS = 0xC07F;
+
+// Parity bits of the 16 accumulator registers of each 32 x 32 block, as
+// one 16-bit mask per block (bit r = register r).
+__device__ __forceinline__ void parity_masks(const v16f (&acc)[4][4], uint32_t (&par)[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) m |= (__float_as_uint(acc[i][j][r]) & 1u) << r;
+      par[i][j] = m;
+    }
 }
 
-// Parities out.  Accumulator r of block (i, j) in lane (h, l32) is
-// row 32 i + 8 (r / 4) + 4 h + (r % 4), column 32 j + l32 of the wave's
-// quarter.  scratch: 8 KiB of LDS no wave reads any more.
-__device__ __forceinline__ void write_tile(const MmArgs& a, v16f (&acc)[4][4], int ti, int tj,
+// Parities out.  Register r of block (i, j) in lane (h, l32) is row
+// 32 i + 8 (r / 4) + 4 h + (r % 4), column 32 j + l32 of the wave's quarter.
+// scratch: this wave's 2 KiB of write-out LDS.
+__device__ __forceinline__ void write_tile(const MmArgs& a, const uint32_t (&par)[4][4], int ti, int tj,
                                            LDS uint32_t* scratch) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = (wv >> 1) * 128, wc = (wv & 1) * 128;
@@ -126,15 +138,17 @@ __device__ __forceinline__ void write_tile(const MmArgs& a, v16f (&acc)[4][4], i
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const uint32_t bit = (uint32_t)(int)acc[i][j][r] & 1u;
-        const uint64_t bal = __ballot(bit);
+        const uint64_t bal = __ballot((par[i][j] >> r) & 1u);
         const int row = 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
         if (l32 == 0) rows[row * 4 + j] = (uint32_t)(bal >> (32 * h));
       }
-  __builtin_amdgcn_s_waitcnt(0);
+      // one block's ballots at a time (hoisting all 256 runs out of registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  __builtin_amdgcn_s_waitcnt(WAIT_LDS);  // LDS only: the next chunks' loads stay in flight
   __builtin_amdgcn_wave_barrier();
   // row words: lane -> rows lane, lane + 64 of the quarter, two words each
   const int64_t cword = (n0 + wc) / 64;
@@ -153,109 +167,187 @@ __device__ __forceinline__ void write_tile(const MmArgs& a, v16f (&acc)[4][4], i
       }
     }
   }
+  __builtin_amdgcn_wave_barrier();
   if (!a.sym || ti == tj) return;
   // mirrored tile: row (column 32 j + l32 of the quarter), words over the
-  // quarter's rows; this lane holds rows 32 i + 8 q + 4 h + s (r = 4 q + s)
+  // quarter's rows; this lane holds rows 32 i + 8 q + 4 h + s (r = 4 q + s),
+  // so block (i, j)'s mask spreads to bits 8 q + s of a 32-bit word, shifted
+  // by 4 h, and the two lane halves OR together
   const int64_t rword = (m0 + wr) / 64;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    uint64_t w0 = 0, w1 = 0;
+    uint32_t d[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const uint64_t bit = (uint64_t)((uint32_t)(int)acc[i][j][r] & 1u);
-        const int pos = 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (pos < 64)
-          w0 |= bit << pos;
-        else
-          w1 |= bit << (pos - 64);
-      }
-    w0 |= (uint64_t)__shfl_xor((long long)w0, 32);
-    w1 |= (uint64_t)__shfl_xor((long long)w1, 32);
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t x = par[i][j];
+      d[i] = ((x & 0xFu) | ((x & 0xF0u) << 4) | ((x & 0xF00u) << 8) | ((x & 0xF000u) << 12)) << (4 * h);
+      d[i] |= (uint32_t)__shfl_xor((int)d[i], 32);
+    }
+    const uint64_t w = h ? ((uint64_t)d[2] | ((uint64_t)d[3] << 32)) : ((uint64_t)d[0] | ((uint64_t)d[1] << 32));
     const int64_t gj = n0 + wc + 32 * j + l32;
     const int64_t wcol = rword + h;
-    if (gj < a.n && wcol < a.cw) a.C[gj * a.ldc + wcol] = h ? w1 : w0;
+    if (gj < a.n && wcol < a.cw) a.C[gj * a.ldc + wcol] = w;
   }
 }
 
+// Upper-triangle tile t -> (ti, tj): row i of the triangle starts at tile
+// i tn - i (i - 1) / 2; i from the quadratic formula, then corrected by one
+// step either way against rounding.
+__device__ __forceinline__ int64_t tri_start(int64_t i, int64_t tn) { return i * tn - i * (i - 1) / 2; }
+
+__device__ __forceinline__ void tile_coords(const MmArgs& a, int64_t t, int& ti, int& tj) {
+  if (!a.sym) {
+    ti = (int)(t / a.tn);
+    tj = (int)(t % a.tn);
+    return;
+  }
+  const int64_t tn = a.tn;
+  const double b = 2.0 * (double)tn + 1.0;
+  int64_t i = (int64_t)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+  if (i < 0) i = 0;
+  if (i > tn - 1) i = tn - 1;
+  while (i > 0 && tri_start(i, tn) > t) --i;
+  while (i + 1 < tn && tri_start(i + 1, tn) <= t) ++i;
+  ti = (int)i;
+  tj = (int)(i + (t - tri_start(i, tn)));
+}
+
+// The tile G places further in the order (row by row; in the upper
+// triangle row i starts at column i).  Past the last tile ti reaches the
+// row count; such a tile is never multiplied (its loads read clamped rows).
+__device__ __forceinline__ void tile_step(const MmArgs& a, int& ti, int& tj, int G) {
+  tj += G;
+  if (a.sym) {
+    while (tj >= a.tn && ti < a.tn) {
+      ++ti;
+      tj = tj - a.tn + ti;
+    }
+  } else {
+    while (tj >= a.tn) {
+      tj -= a.tn;
+      ++ti;
+    }
+  }
+}
+
+// Persistent: workgroup k of XCD x (blockIdx = 8 k + x) takes tiles
+// x * per_xcd + k + j G (j = 0, 1, ...; G workgroups per XCD) of its XCD's
+// run, so the tiles in flight on one XCD are a contiguous window of the
+// tile order and share rows in its L2.  The chunks of all its tiles form one
+// sequence s = j nch + c: chunk s + 1 waits in registers while chunk s is
+// multiplied, goes to the other LDS buffer, and the loads of chunk s + 2
+// start, so the next tile's first chunk is in flight during a tile's parity
+// write-out (which has LDS of its own).
 __global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
   // two chunk buffers: [buf][row 0..255 A, 256..511 B][4 words]
   __shared__ __attribute__((aligned(16))) uint64_t sbuf[2][2 * MM_T][MM_CW];
+  __shared__ __attribute__((aligned(16))) uint32_t wscr[4 * 128 * 4];  // write-out rows, per wave
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-  if (t >= a.n_tiles) return;
-  int ti, tj;
-  tile_of(a, t, ti, tj);
-  const int64_t m0 = (int64_t)ti * MM_T, n0 = (int64_t)tj * MM_T;
+  const int G = (int)(gridDim.x >> 3);
+  const int64_t t_first = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+  int64_t t_last = (int64_t)((blockIdx.x & 7) + 1) * a.per_xcd;
+  if (t_last > a.n_tiles) t_last = a.n_tiles;
+  if (t_first >= t_last) return;
   const int kw = a.kw0 + a.kw1;
   const int nch = (kw + MM_CW - 1) / MM_CW;
+  const int64_t n_seq = (t_last - t_first + G - 1) / G * nch;
 
-  // staging: thread tid fetches A row m0 + tid and B row n0 + tid
+  // The loads of chunk q are straight-line code (no branch may separate them
+  // from the stash that uses them, or the compiler waits for each at once):
+  // the tile of q is one of the next three, whose first rows are kept in
+  // rm[0..2] / rn[0..2] (chunk q of a tile past the end loads clamped rows
+  // and is never used); tiles advance by tile_step, without divisions.
+  int64_t rm[3], rn[3];
+  int sti, stj;  // tile j + 2
+  tile_coords(a, t_first, sti, stj);
+  rm[0] = (int64_t)sti * MM_T;
+  rn[0] = (int64_t)stj * MM_T;
+  tile_step(a, sti, stj, G);
+  rm[1] = (int64_t)sti * MM_T;
+  rn[1] = (int64_t)stj * MM_T;
+  tile_step(a, sti, stj, G);
+  rm[2] = (int64_t)sti * MM_T;
+  rn[2] = (int64_t)stj * MM_T;
   uint64_t ra[MM_CW], rb[MM_CW];
-  auto fetch = [&](int c) {
-#pragma unroll
-    for (int w = 0; w < MM_CW; ++w) {
-      ra[w] = row_word(a.a0, a.a1, a.lda, m0 + tid, a.m, c * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);
-      rb[w] = row_word(a.b0, a.b1, a.ldb, n0 + tid, a.n, c * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int w = 0; w < MM_CW; ++w) {
-      sbuf[buf][tid][w] = ra[w];
-      sbuf[buf][MM_T + tid][w] = rb[w];
-    }
-  };
-
-  v16f acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+#define GF2MM_FETCH(JOFF, C)                                                                                   \
+  do {                                                                                                         \
+    const int64_t fm_ = (JOFF) == 0 ? rm[0] : ((JOFF) == 1 ? rm[1] : rm[2]);                                    \
+    const int64_t fn_ = (JOFF) == 0 ? rn[0] : ((JOFF) == 1 ? rn[1] : rn[2]);                                    \
+    _Pragma("unroll") for (int w = 0; w < MM_CW; ++w) {                                                        \
+      ra[w] = row_word(a.a0, a.a1, a.lda, fm_ + tid, a.m, (C) * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);    \
+      rb[w] = row_word(a.b0, a.b1, a.ldb, fn_ + tid, a.n, (C) * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);    \
+    }                                                                                                          \
+  } while (0)
+#define GF2MM_STASH(BUF)                                \
+  do {                                                  \
+    _Pragma("unroll") for (int w = 0; w < MM_CW; ++w) { \
+      sbuf[(BUF)][tid][w] = ra[w];                      \
+      sbuf[(BUF)][MM_T + tid][w] = rb[w];               \
+    }                                                   \
+  } while (0)
 
   const int wr = (wv >> 1) * 128, wc = (wv & 1) * 128;  // this wave's quarter
   const int h = lane >> 5, l32 = lane & 31;
-  fetch(0);
-  stash(0);
+  GF2MM_FETCH(0, 0);
+  GF2MM_STASH(0);
+  GF2MM_FETCH(nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) fetch(c + 1);
-    // this lane's fragments: 16 bytes (dwords 4h .. 4h+3) of each row's chunk
-    uint32_t fa[4][4], fb[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t* pa = (const uint32_t*)&sbuf[buf][wr + 32 * i + l32][2 * h];
-      const uint32_t* pb = (const uint32_t*)&sbuf[buf][MM_T + wc + 32 * i + l32][2 * h];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        fa[i][d] = pa[d];
-        fb[i][d] = pb[d];
-      }
+  const int64_t n_my = n_seq / nch;
+  for (int64_t j = 0; j < n_my; ++j) {
+    if (j > 0) {
+      rm[0] = rm[1];
+      rn[0] = rn[1];
+      rm[1] = rm[2];
+      rn[1] = rn[2];
+      tile_step(a, sti, stj, G);
+      rm[2] = (int64_t)sti * MM_T;
+      rn[2] = (int64_t)stj * MM_T;
     }
+    const int ti = (int)(rm[0] / MM_T), tj = (int)(rn[0] / MM_T);
+    v16f acc[4][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      v8i oa[4], ob[4];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        oa[i] = unpack_fp4(fa[i][s]);
-        ob[i] = unpack_fp4(fb[i][s]);
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][jj][r] = ACC_BASE;
+    for (int c = 0; c < nch; ++c) {
+      const int64_t s = j * nch + c;
+      const int buf = (int)(s & 1);
+      // this lane's fragments: dword 4h + st of each row's chunk at step st,
+      // read just before that step's products
+      const uint32_t* pa0 = (const uint32_t*)&sbuf[buf][wr + l32][2 * h];
+      const uint32_t* pb0 = (const uint32_t*)&sbuf[buf][MM_T + wc + l32][2 * h];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        v8i oa[4], ob[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          oa[i] = unpack_fp4(pa0[32 * i * 2 * MM_CW + st]);
+          ob[i] = unpack_fp4(pb0[32 * i * 2 * MM_CW + st]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            acc[i][jj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(oa[i], ob[jj], acc[i][jj], 4, 4, 0,
+                                                                          SCALE_ONE, 0, SCALE_ONE);
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(oa[i], ob[j], acc[i][j], 4, 4, 0,
-                                                                       SCALE_ONE, 0, SCALE_ONE);
+      // chunk s + 1 into the other buffer (past the end: a buffer no one
+      // reads), then the loads of chunk s + 2
+      GF2MM_STASH(buf ^ 1);
+      const int c2 = c + 2;
+      const int joff = c2 < nch ? 0 : (c2 < 2 * nch ? 1 : 2);
+      GF2MM_FETCH(joff, c2 - joff * nch);
+      if (c + 1 < nch) __syncthreads();
     }
-    if (c + 1 < nch) stash(buf ^ 1);
+    uint32_t par[4][4];
+    parity_masks(acc, par);
+    write_tile(a, par, ti, tj, (LDS uint32_t*)wscr);
     __syncthreads();
   }
-
-  write_tile(a, acc, ti, tj, (LDS uint32_t*)&sbuf[0][0][0]);
+#undef GF2MM_FETCH
+#undef GF2MM_STASH
 }
 
 constexpr int MM_KMAX = 32;  // words of K (per row) the 128 x 128 kernel stages whole
@@ -331,7 +423,7 @@ __global__ __launch_bounds__(M2_BS, 2) void gf2mm_tile2_kernel(MmArgs a) {
   const int64_t t = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
   if (t >= a.n_tiles) return;
   int ti, tj;
-  tile_of(a, t, ti, tj);
+  tile_coords(a, t, ti, tj);
   const int64_t m0 = (int64_t)ti * M2_T, n0 = (int64_t)tj * M2_T;
   const int kw = a.kw0 + a.kw1;
   const int kwq = (kw + 1) & ~1;  // whole 128-bit groups; the pad word is zero
@@ -522,8 +614,9 @@ zx_status launch_gf2mm(MmArgs a, hipStream_t s) {
   // General products with K up to 32 words: 128 x 128 tiles, whole K staged
   // (the parity products: 0.379 -> 0.234 ms for 4096 x 65536 x 1024 bits).
   // The symmetric table keeps 256 x 256 tiles with K in double-buffered
-  // chunks: with 128 x 128 tiles it took 7.3 ms against 5.3 ms (four times
-  // the tiles, each with its mirrored write-out).
+  // chunks: with 128 x 128 tiles it took 7.3 ms against 5.3 ms for the
+  // chunked kernel as it then was (four times the tiles, each with its
+  // mirrored write-out).
   const bool whole = kw <= MM_KMAX && !a.sym;
   const int T = whole ? M2_T : MM_T;
   a.tm = (int32_t)((a.m + T - 1) / T);
@@ -546,7 +639,12 @@ zx_status launch_gf2mm(MmArgs a, hipStream_t s) {
     }
     hipLaunchKernelGGL(gf2mm_tile2_kernel, dim3((unsigned)blocks), dim3(M2_BS), lds, s, a);
   } else {
-    hipLaunchKernelGGL(gf2mm_kernel, dim3((unsigned)blocks), dim3(MM_BS), 0, s, a);
+    // one persistent workgroup per CU, the same count on every XCD
+    const ZxDevice* d = zx_device();
+    if (!d) return ZX_EDEVICE;
+    const int64_t per = (d->n_cu / 8) > 0 ? d->n_cu / 8 : 1;
+    const int64_t g = per < a.per_xcd ? per : a.per_xcd;
+    hipLaunchKernelGGL(gf2mm_kernel, dim3((unsigned)(8 * g)), dim3(MM_BS), 0, s, a);
   }
   ZX_HIP(hipGetLastError());
   return ZX_OK;

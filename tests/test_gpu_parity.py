@@ -25,7 +25,9 @@ U32 = 2.0 ** -24
 
 
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (3, 70, 64), (257, 300, 200), (513, 1000, 130),
-                                   (40, 600, 2000), (300, 257, 63)])
+                                   (40, 600, 2000), (300, 257, 63),
+                                   # beyond 2048 bits: the chunked 256 x 256 kernel, ragged rows and K
+                                   (300, 700, 3000), (1100, 530, 2100), (5, 2049, 4100)])
 def test_gf2_matmul_matches_oracle(zx, m, n, k):
     import torch
     print("gf2_matmul case", m, n, k, flush=True)
