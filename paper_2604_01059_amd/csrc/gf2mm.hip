@@ -18,9 +18,9 @@
 //    B fragments are unpacked the same way and the sum runs over all k.
 //
 //    Two tilings.  The symmetric table (and K beyond 2048 bits): one
-//    persistent workgroup of 256 threads per CU walking 256 x 256 output
-//    tiles, each wavefront a 128 x 128 quarter (4 x 4 blocks of 32 x 32, 256
-//    fp32 accumulators per lane).  The rows' bits go through LDS in chunks of
+//    persistent workgroup of 512 threads per CU walking 256 x 256 output
+//    tiles, each wavefront a 64 x 128 part (2 x 4 blocks of 32 x 32, 128
+//    fp32 accumulators per lane, two wavefronts per SIMD).  The rows' bits go through LDS in chunks of
 //    256 bits (4 words, double buffered): 16 KiB per chunk for the 512 rows
 //    of the tile; the next chunk's rows are loaded while a chunk is
 //    multiplied, across tile boundaries too.  For each 64-bit step of a
@@ -31,8 +31,10 @@
 //    packing (the mirrored tile's row words).  Tiles are dealt to the eight
 //    XCDs in contiguous runs of the tile order, so one XCD's tiles share rows
 //    in its L2.  Row loads are branch-free (the compiler otherwise waits for
-//    each load before issuing the next: 5.25 -> 3.96 ms for the 65536-string
-//    table together with the persistent pipeline).
+//    each load before issuing the next).  65536-string table: 5.25 ms with
+//    one wavefront per SIMD, per-tile workgroups and branching loads; 3.96
+//    ms persistent with branch-free loads; 2.79 ms with two wavefronts per
+//    SIMD.
 //
 // 2. Per setting l: omega^phase8 sqrt(2)^pow * prod_k h(alpha_k, beta_k;
 //    a_kl, b_kl), h of equation phase_pair, phases multiples of pi/4.  One
@@ -47,7 +49,11 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 #define LDS __attribute__((address_space(3)))
 
-constexpr int MM_BS = 256;    // threads per workgroup
+// Waves per workgroup of the 256 x 256 kernel: 8 (each a 64 x 128 part, 128
+// accumulators, two waves per SIMD, so one wave's operand unpacking and
+// loads overlap the other's products): 2.79 ms for the 65536-string table
+// against 3.76 ms with 4 (each a 128 x 128 quarter, one wave per SIMD).
+constexpr int MM_NW = 8;
 constexpr int MM_T = 256;     // output tile edge
 constexpr int MM_CW = 4;      // words per chunk
 constexpr int SCALE_ONE = 128;  // E8M0 2^1: FP4 code 0b0001 (0.5) scaled to 1.0
@@ -113,9 +119,10 @@ constexpr int WAIT_LDS = 0xC07F;
 
 // Parity bits of the 16 accumulator registers of each 32 x 32 block, as
 // one 16-bit mask per block (bit r = register r).
-__device__ __forceinline__ void parity_masks(const v16f (&acc)[4][4], uint32_t (&par)[4][4]) {
+template <int WI>
+__device__ __forceinline__ void parity_masks(const v16f (&acc)[WI][4], uint32_t (&par)[WI][4]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       uint32_t m = 0;
@@ -125,18 +132,22 @@ __device__ __forceinline__ void parity_masks(const v16f (&acc)[4][4], uint32_t (
     }
 }
 
-// Parities out.  Register r of block (i, j) in lane (h, l32) is row
-// 32 i + 8 (r / 4) + 4 h + (r % 4), column 32 j + l32 of the wave's quarter.
-// scratch: this wave's 2 KiB of write-out LDS.
-__device__ __forceinline__ void write_tile(const MmArgs& a, const uint32_t (&par)[4][4], int ti, int tj,
+// Parities out of a wave's 32 WI x 128 part of the 256 x 256 tile (waves
+// laid out two across: rows (wv >> 1) 32 WI, columns (wv & 1) 128).
+// Register r of block (i, j) in lane (h, l32) is row 32 i + 8 (r / 4) +
+// 4 h + (r % 4), column 32 j + l32 of the part.  scratch: 32 WI x 4 dwords
+// of LDS per wave.
+template <int WI>
+__device__ __forceinline__ void write_tile(const MmArgs& a, const uint32_t (&par)[WI][4], int ti, int tj,
                                            LDS uint32_t* scratch) {
+  constexpr int PR = 32 * WI;  // rows of the part
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = (wv >> 1) * 128, wc = (wv & 1) * 128;
+  const int wr = (wv >> 1) * PR, wc = (wv & 1) * 128;
   const int h = lane >> 5, l32 = lane & 31;
   const int64_t m0 = (int64_t)ti * MM_T, n0 = (int64_t)tj * MM_T;
-  LDS uint32_t* rows = scratch + wv * (128 * 4);  // [128 rows][4 dwords]
+  LDS uint32_t* rows = scratch + wv * (PR * 4);  // [PR rows][4 dwords]
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
 #pragma unroll
@@ -145,15 +156,15 @@ __device__ __forceinline__ void write_tile(const MmArgs& a, const uint32_t (&par
         const int row = 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
         if (l32 == 0) rows[row * 4 + j] = (uint32_t)(bal >> (32 * h));
       }
-      // one block's ballots at a time (hoisting all 256 runs out of registers)
+      // one block's ballots at a time (hoisting all of them runs out of registers)
       __builtin_amdgcn_sched_barrier(0);
     }
   __builtin_amdgcn_s_waitcnt(WAIT_LDS);  // LDS only: the next chunks' loads stay in flight
   __builtin_amdgcn_wave_barrier();
-  // row words: lane -> rows lane, lane + 64 of the quarter, two words each
+  // row words: lane -> rows lane (+ 64 p) of the part, two words each
   const int64_t cword = (n0 + wc) / 64;
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < PR / 64; ++p) {
     const int row = lane + 64 * p;
     const int64_t gi = m0 + wr + row;
     if (gi < a.m) {
@@ -169,24 +180,29 @@ __device__ __forceinline__ void write_tile(const MmArgs& a, const uint32_t (&par
   }
   __builtin_amdgcn_wave_barrier();
   if (!a.sym || ti == tj) return;
-  // mirrored tile: row (column 32 j + l32 of the quarter), words over the
-  // quarter's rows; this lane holds rows 32 i + 8 q + 4 h + s (r = 4 q + s),
+  // mirrored tile: row (column 32 j + l32 of the part), words over the
+  // part's rows; this lane holds rows 32 i + 8 q + 4 h + s (r = 4 q + s),
   // so block (i, j)'s mask spreads to bits 8 q + s of a 32-bit word, shifted
-  // by 4 h, and the two lane halves OR together
+  // by 4 h, and the two lane halves OR together; lane half h writes word h
+  // of the part's PR / 64 words
   const int64_t rword = (m0 + wr) / 64;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    uint32_t d[4];
+    uint32_t d[WI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < WI; ++i) {
       const uint32_t x = par[i][j];
       d[i] = ((x & 0xFu) | ((x & 0xF0u) << 4) | ((x & 0xF00u) << 8) | ((x & 0xF000u) << 12)) << (4 * h);
       d[i] |= (uint32_t)__shfl_xor((int)d[i], 32);
     }
-    const uint64_t w = h ? ((uint64_t)d[2] | ((uint64_t)d[3] << 32)) : ((uint64_t)d[0] | ((uint64_t)d[1] << 32));
+    uint64_t w;
+    if constexpr (WI == 4)
+      w = h ? ((uint64_t)d[2] | ((uint64_t)d[3] << 32)) : ((uint64_t)d[0] | ((uint64_t)d[1] << 32));
+    else
+      w = (uint64_t)d[0] | ((uint64_t)d[1] << 32);
     const int64_t gj = n0 + wc + 32 * j + l32;
     const int64_t wcol = rword + h;
-    if (gj < a.n && wcol < a.cw) a.C[gj * a.ldc + wcol] = w;
+    if (h < PR / 64 && gj < a.n && wcol < a.cw) a.C[gj * a.ldc + wcol] = w;
   }
 }
 
@@ -238,10 +254,14 @@ __device__ __forceinline__ void tile_step(const MmArgs& a, int& ti, int& tj, int
 // multiplied, goes to the other LDS buffer, and the loads of chunk s + 2
 // start, so the next tile's first chunk is in flight during a tile's parity
 // write-out (which has LDS of its own).
-__global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void gf2mm_kernel(MmArgs a) {
+  constexpr int BS = 64 * NW;    // threads
+  constexpr int WI = 16 / NW;    // 32-row blocks per wave (4 x 4 or 2 x 4 blocks)
+  constexpr int RPT = 2 * MM_T / BS;  // staged rows per thread per chunk
   // two chunk buffers: [buf][row 0..255 A, 256..511 B][4 words]
   __shared__ __attribute__((aligned(16))) uint64_t sbuf[2][2 * MM_T][MM_CW];
-  __shared__ __attribute__((aligned(16))) uint32_t wscr[4 * 128 * 4];  // write-out rows, per wave
+  __shared__ __attribute__((aligned(16))) uint32_t wscr[NW * 32 * WI * 4];  // write-out rows, per wave
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int G = (int)(gridDim.x >> 3);
   const int64_t t_first = (int64_t)(blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
@@ -268,25 +288,31 @@ __global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
   tile_step(a, sti, stj, G);
   rm[2] = (int64_t)sti * MM_T;
   rn[2] = (int64_t)stj * MM_T;
-  uint64_t ra[MM_CW], rb[MM_CW];
-#define GF2MM_FETCH(JOFF, C)                                                                                   \
-  do {                                                                                                         \
-    const int64_t fm_ = (JOFF) == 0 ? rm[0] : ((JOFF) == 1 ? rm[1] : rm[2]);                                    \
-    const int64_t fn_ = (JOFF) == 0 ? rn[0] : ((JOFF) == 1 ? rn[1] : rn[2]);                                    \
-    _Pragma("unroll") for (int w = 0; w < MM_CW; ++w) {                                                        \
-      ra[w] = row_word(a.a0, a.a1, a.lda, fm_ + tid, a.m, (C) * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);    \
-      rb[w] = row_word(a.b0, a.b1, a.ldb, fn_ + tid, a.n, (C) * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);    \
-    }                                                                                                          \
+  // staged row q (0 .. 511: A rows, then B rows) of thread tid: q = tid + BS k
+  uint64_t rr[RPT][MM_CW];
+#define GF2MM_FETCH(JOFF, C)                                                                                    \
+  do {                                                                                                          \
+    const int64_t fm_ = (JOFF) == 0 ? rm[0] : ((JOFF) == 1 ? rm[1] : rm[2]);                                     \
+    const int64_t fn_ = (JOFF) == 0 ? rn[0] : ((JOFF) == 1 ? rn[1] : rn[2]);                                     \
+    _Pragma("unroll") for (int k = 0; k < RPT; ++k) {                                                           \
+      const int q_ = tid + BS * k;                                                                              \
+      const bool isb_ = q_ >= MM_T; /* the same in the whole wave */                                            \
+      const uint64_t* o0_ = isb_ ? a.b0 : a.a0;                                                                 \
+      const uint64_t* o1_ = isb_ ? a.b1 : a.a1;                                                                 \
+      const int64_t ld_ = isb_ ? a.ldb : a.lda;                                                                 \
+      const int64_t r_ = isb_ ? fn_ + q_ - MM_T : fm_ + q_;                                                     \
+      const int64_t nr_ = isb_ ? a.n : a.m;                                                                     \
+      _Pragma("unroll") for (int w = 0; w < MM_CW; ++w) rr[k][w] =                                              \
+          row_word(o0_, o1_, ld_, r_, nr_, (C) * MM_CW + w, a.kw0, a.kw1, a.mask0, a.mask1);                    \
+    }                                                                                                           \
   } while (0)
-#define GF2MM_STASH(BUF)                                \
-  do {                                                  \
-    _Pragma("unroll") for (int w = 0; w < MM_CW; ++w) { \
-      sbuf[(BUF)][tid][w] = ra[w];                      \
-      sbuf[(BUF)][MM_T + tid][w] = rb[w];               \
-    }                                                   \
+#define GF2MM_STASH(BUF)                                                              \
+  do {                                                                                \
+    _Pragma("unroll") for (int k = 0; k < RPT; ++k)                                   \
+        _Pragma("unroll") for (int w = 0; w < MM_CW; ++w) sbuf[(BUF)][tid + BS * k][w] = rr[k][w]; \
   } while (0)
 
-  const int wr = (wv >> 1) * 128, wc = (wv & 1) * 128;  // this wave's quarter
+  const int wr = (wv >> 1) * (32 * WI), wc = (wv & 1) * 128;  // this wave's part
   const int h = lane >> 5, l32 = lane & 31;
   GF2MM_FETCH(0, 0);
   GF2MM_STASH(0);
@@ -304,9 +330,9 @@ __global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
       rn[2] = (int64_t)stj * MM_T;
     }
     const int ti = (int)(rm[0] / MM_T), tj = (int)(rn[0] / MM_T);
-    v16f acc[4][4];
+    v16f acc[WI][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
@@ -320,14 +346,13 @@ __global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
       const uint32_t* pb0 = (const uint32_t*)&sbuf[buf][MM_T + wc + l32][2 * h];
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        v8i oa[4], ob[4];
+        v8i oa[WI], ob[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          oa[i] = unpack_fp4(pa0[32 * i * 2 * MM_CW + st]);
-          ob[i] = unpack_fp4(pb0[32 * i * 2 * MM_CW + st]);
-        }
+        for (int i = 0; i < WI; ++i) oa[i] = unpack_fp4(pa0[32 * i * 2 * MM_CW + st]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) ob[i] = unpack_fp4(pb0[32 * i * 2 * MM_CW + st]);
+#pragma unroll
+        for (int i = 0; i < WI; ++i)
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj)
             acc[i][jj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(oa[i], ob[jj], acc[i][jj], 4, 4, 0,
@@ -341,9 +366,9 @@ __global__ __launch_bounds__(MM_BS, 1) void gf2mm_kernel(MmArgs a) {
       GF2MM_FETCH(joff, c2 - joff * nch);
       if (c + 1 < nch) __syncthreads();
     }
-    uint32_t par[4][4];
-    parity_masks(acc, par);
-    write_tile(a, par, ti, tj, (LDS uint32_t*)wscr);
+    uint32_t par[WI][4];
+    parity_masks<WI>(acc, par);
+    write_tile<WI>(a, par, ti, tj, (LDS uint32_t*)wscr);
     __syncthreads();
   }
 #undef GF2MM_FETCH
@@ -644,7 +669,7 @@ zx_status launch_gf2mm(MmArgs a, hipStream_t s) {
     if (!d) return ZX_EDEVICE;
     const int64_t per = (d->n_cu / 8) > 0 ? d->n_cu / 8 : 1;
     const int64_t g = per < a.per_xcd ? per : a.per_xcd;
-    hipLaunchKernelGGL(gf2mm_kernel, dim3((unsigned)(8 * g)), dim3(MM_BS), 0, s, a);
+    hipLaunchKernelGGL(gf2mm_kernel<MM_NW>, dim3((unsigned)(8 * g)), dim3(64 * MM_NW), 0, s, a);
   }
   ZX_HIP(hipGetLastError());
   return ZX_OK;
