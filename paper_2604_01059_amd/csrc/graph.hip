@@ -58,7 +58,7 @@ struct Shared {
   int64_t E;           // Hadamard edges among present spiders
   int64_t pow_sqrt2;
   int64_t fill_in;
-  int64_t acc64[4];    // per-round accumulators
+  int64_t acc64[5];    // per-round accumulators ([4]: a team slice's edge count)
   int32_t phase8;
   int32_t n_trace;
   int32_t round;
@@ -80,6 +80,33 @@ struct Shared {
 #define LDSP __attribute__((address_space(3)))
 template <bool LA> struct AdjPtr { using type = uint64_t*; };
 template <> struct AdjPtr<true> { using type = LDSP uint64_t*; };
+
+// A team of workgroups shares the row update of an arena-mode round: the
+// workgroup running the diagram publishes the round here (the selected
+// spiders, their partners and phase contributions, the present and selected
+// masks), and every member, itself included, claims 64-row slices of the
+// update until none is left.  claim = (round sequence << 32) | next slice,
+// taken by compare-and-swap, so a late member can never claim a slice of
+// another round; the running workgroup waits only for slices already
+// claimed, so it finishes alone if no helper comes.  Device-scope release
+// and acquire order the round's data and results around claim and done.
+constexpr int TEAM_SLICE = 64;     // rows per slice
+constexpr int TEAM_MAXW = 128;     // words per row (n <= 8192)
+constexpr int TEAM_MAXS = 64;      // selected spiders of a round
+constexpr int TEAM_MIN_N = 1500;   // diagrams from this size get a team
+struct __attribute__((aligned(256))) TeamBoard {
+  unsigned long long claim;
+  uint32_t done;        // slices finished in the current round
+  uint32_t exit;        // the team's diagrams are done
+  unsigned long long pc;  // edges left on the updated rows (sum over slices)
+  int32_t ns, pivot, n, W;
+  int64_t ldw;
+  uint64_t* adj;
+  int8_t* dk;           // phase increment of each row in the round (n bytes)
+  int16_t slist[TEAM_MAXS], partner[TEAM_MAXS];
+  int8_t kc[TEAM_MAXS];
+  uint64_t alive[TEAM_MAXW], sel[TEAM_MAXW];
+};
 
 template <bool LA>  // LA: the working adjacency is in LDS (else in the arena)
 struct Ctx {
@@ -106,6 +133,7 @@ struct Ctx {
   int pw;                  // words per parameter row (0: no parameters)
   uint64_t* par;           // CURRENT parameter rows, n x pw (global)
   uint8_t* terms;          // recorded terms (global)
+  TeamBoard* tb;           // arena mode with a team (else null)
 };
 
 template <class P>
@@ -176,6 +204,7 @@ __device__ void setup_ctx(Ctx<LA>& c, uint8_t* arena, uint8_t* lds) {
   c.omask = (LDSP uint64_t*)p; p += 8 * W;
   c.scr = nullptr;
   c.scr_words = 0;
+  c.tb = nullptr;
   c.trace = (int32_t*)(arena + c.h->off_trace);
   c.pw = uni(c.h->pw);
   c.par = c.pw ? (uint64_t*)(arena + c.h->off_par) : nullptr;
@@ -599,6 +628,171 @@ constexpr int SPIDER_MAJOR_MAX = 64;
 // then a (row, word) pass XORs the hit contributions, staged in LDS when
 // they fit, and drops the selected columns in the same write.  Each row
 // word is read and written once; each selected-column bit once per row.
+// Slice s of a team round (rows 64 s .. 64 s + 63), whole workgroup: per row
+// the mask of selected spiders it touches and its phase increment, then the
+// (row, word) XOR pass with the selected spiders' rows (not changed by the
+// round), the row's own bit and the selected columns cleared.  Then the
+// slice's edge count, and done, are published.  hm: 64 words of LDS.
+template <int BS>
+__device__ void team_slice(TeamBoard* tb, int slice, LDSP uint64_t* hm, Shared& sh) {
+  const int tid = threadIdx.x;
+  const int n = tb->n, W = tb->W, ns = tb->ns, pivot = tb->pivot;
+  const int64_t ldw = tb->ldw;
+  uint64_t* adj = tb->adj;
+  const int lo = slice * TEAM_SLICE;
+  const int rn = n - lo < TEAM_SLICE ? n - lo : TEAM_SLICE;
+  if (tid == 0) sh.acc64[4] = 0;
+  for (int t = tid; t < rn; t += BS) {
+    const int w = lo + t;
+    uint64_t m = 0;
+    int dk = 0;
+    if (((tb->alive[w >> 6] >> (w & 63)) & 1) && !((tb->sel[w >> 6] >> (w & 63)) & 1)) {
+      const uint64_t* rw = adj + (int64_t)w * ldw;
+      for (int i = 0; i < ns; ++i) {
+        const int x = tb->slist[i];
+        if ((rw[x >> 6] >> (x & 63)) & 1) {
+          m |= 1ull << i;
+          dk += tb->kc[i];
+          if (pivot) {
+            const int pp = tb->partner[i];
+            if ((rw[pp >> 6] >> (pp & 63)) & 1) dk += 2;  // adjacent to both ends
+          }
+        }
+      }
+    }
+    hm[t] = m;
+    tb->dk[w] = (int8_t)(dk & 7);
+  }
+  __syncthreads();
+  int64_t pc = 0;
+  for (int64_t it = tid; it < (int64_t)rn * W; it += BS) {
+    const int t = (int)(it / W), j = (int)(it - (int64_t)t * W);
+    const int w = lo + t;
+    if (!((tb->alive[w >> 6] >> (w & 63)) & 1) || ((tb->sel[w >> 6] >> (w & 63)) & 1)) continue;
+    uint64_t* rw = adj + (int64_t)w * ldw;
+    const uint64_t old = rw[j];
+    uint64_t v = old;
+    uint64_t m = hm[t];
+    while (m) {
+      const int i = __builtin_ctzll(m);
+      m &= m - 1;
+      v ^= adj[(int64_t)tb->slist[i] * ldw + j];
+    }
+    if (j == (w >> 6)) v &= ~(1ull << (w & 63));
+    v &= ~tb->sel[j];
+    if (v != old) rw[j] = v;
+    pc += __popcll(v);
+  }
+  block_add(&sh.acc64[4], pc);
+  __syncthreads();
+}
+
+// After a member's last slice of a round: its row and dk stores are
+// acknowledged in every wave, then one release publishes them with the
+// member's edge count and slice count (one cache write-back per member and
+// round, not per slice).
+template <int BS>
+__device__ void team_publish(TeamBoard* tb, Shared& sh, int64_t pc, uint32_t slices) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0 && slices) {
+    __hip_atomic_fetch_add(&tb->pc, (unsigned long long)pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&tb->done, slices, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Thread 0: claim the next slice of round seq (compare-and-swap); -1 when
+// none is left or the board holds another round.
+__device__ __forceinline__ int team_claim(TeamBoard* tb, uint32_t seq) {
+  unsigned long long c0 = __hip_atomic_load(&tb->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    if ((uint32_t)(c0 >> 32) != seq) return -1;
+    const uint32_t idx = (uint32_t)c0;
+    const int S = (tb->n + TEAM_SLICE - 1) / TEAM_SLICE;
+    if ((int)idx >= S) return -1;
+    if (__hip_atomic_compare_exchange_strong(&tb->claim, &c0, c0 + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return (int)idx;
+  }
+}
+
+constexpr uint64_t TEAM_WAIT_TICKS = 100000000ull * 10;  // 10 s of the 100 MHz clock
+
+// The running workgroup's side of a team round (rounds of at most
+// TEAM_MAXS rewrites): publish, claim slices like any member, wait for the
+// slices others claimed, then take the phase increments and edge counts.
+template <int BS>
+__device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pivot) {
+  TeamBoard* tb = c.tb;
+  const int tid = threadIdx.x, W = c.W, n = c.n, ns = uni(sh.ns);
+  for (int i = tid; i < ns; i += BS) {
+    const int x = c.slist[i];
+    tb->slist[i] = (int16_t)x;
+    tb->partner[i] = pivot ? c.partner[x] : (int16_t)-1;
+    tb->kc[i] = c.kc[x];
+  }
+  for (int j = tid; j < W; j += BS) {
+    tb->alive[j] = c.alive[j];
+    tb->sel[j] = c.sel[j];
+  }
+  if (tid == 0) {
+    tb->ns = ns;
+    tb->pivot = pivot ? 1 : 0;
+    tb->n = n;
+    tb->W = W;
+    tb->ldw = c.ldw;
+    tb->adj = c.adj;
+    tb->pc = 0;
+    tb->done = 0;
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores (and earlier row writes) are acknowledged
+  __syncthreads();                // ... and every other wave's
+  if (tid == 0) {
+    const unsigned long long c0 = __hip_atomic_load(&tb->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t seq = (uint32_t)(c0 >> 32) + 1;
+    sh.key = (int32_t)seq;
+    __hip_atomic_store(&tb->claim, (unsigned long long)seq << 32, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const uint32_t seq = (uint32_t)uni(sh.key);
+  LDSP uint64_t* hm = c.scr;  // 64 words of the free LDS
+  int64_t mypc = 0;
+  uint32_t mine = 0;
+  for (;;) {
+    if (tid == 0) sh.idx = team_claim(tb, seq);
+    __syncthreads();
+    const int sl = uni(sh.idx);
+    __syncthreads();
+    if (sl < 0) break;
+    team_slice<BS>(tb, sl, hm, sh);
+    if (tid == 0) mypc += sh.acc64[4];
+    ++mine;
+  }
+  team_publish<BS>(tb, sh, mypc, mine);
+  if (tid == 0) {
+    // relaxed polls (an acquire per poll would invalidate the caches each
+    // time), then one acquire for everything the members published
+    const uint32_t S = (uint32_t)((n + TEAM_SLICE - 1) / TEAM_SLICE);
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(&tb->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < S) {
+      if (wall_clock64() - t0 > TEAM_WAIT_TICKS) {
+        sh.status = ZX_EDEVICE;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sh.acc64[4] = (int64_t)__hip_atomic_load(&tb->pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  for (int w = tid; w < n; w += BS) {
+    const int d = tb->dk[w];
+    if (d) c.k[w] = (int8_t)((c.k[w] + d) & 7);
+  }
+  if (tid == 0) sh.acc64[3] += sh.acc64[4];
+  __syncthreads();
+}
+
 // Not inlined: its unrolled update would otherwise set the register
 // allocation of the LDS-resident path that shares the kernel.
 template <int BS>
@@ -712,6 +906,10 @@ __device__ __noinline__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool p
 template <int BS, bool LA>
 __device__ bool apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
   if constexpr (!LA) {
+    if (c.tb && uni(sh.ns) <= TEAM_MAXS && c.scr_words >= 64) {
+      apply_round_team<BS>(c, sh, pivot);
+      return true;
+    }
     if (uni(sh.ns) <= SPIDER_MAJOR_MAX && c.scr_words >= 64) {
       apply_round_arena<BS>(c, sh, pivot);
       return true;
@@ -1187,6 +1385,7 @@ struct SimpArgs {
   int32_t fallback;    // learned policy: keep the greedy result where its gate2q is lower
   const uint16_t* wbf;  // learned policy: network (bf16 copy)
   const float* param;   // learned policy: network (fp32 master)
+  TeamBoard* tb;        // arena-mode rounds shared with a team (else null)
 };
 
 // One diagram, start to finish, with the adjacency in LDS (LA) or the arena.
@@ -1212,6 +1411,7 @@ __device__ void run_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Sha
     const int64_t free_bytes = a.lds_cap - (int64_t)(at - lds);
     c.scr = (LDSP uint64_t*)at;
     c.scr_words = free_bytes > 0 ? (int)(free_bytes / 8) : 0;
+    c.tb = c.W <= TEAM_MAXW ? a.tb : nullptr;
   }
   simplify_rounds<BS, LA, LEARN>(c, sh, &pol, a.max_rounds);
   store_state<BS, LA>(c, sh);
@@ -1332,6 +1532,100 @@ void simplify_kernel(uint8_t* const* table, int32_t n_graphs, Queue* q, SimpArgs
     if (idx >= n_graphs) break;
     process_diagram<BS, LEARN>(table[idx], smem_dyn, a, sh);
   }
+}
+
+// ------------------------------------------------------------- teams --
+struct TeamCtl {
+  uint32_t next;  // diagram queue
+  uint32_t pad[63];
+  TeamBoard board[8];
+};
+
+constexpr int64_t TEAM_DK_BYTES = (int64_t)TEAM_MAXW * 64;  // phase increments of up to 8192 rows
+constexpr int64_t TEAM_LDS = 152 * 1024;
+
+__global__ void team_reset(TeamCtl* t, int8_t* dk) {
+  if (threadIdx.x == 0) t->next = 0;
+  if (threadIdx.x < 8) {
+    t->board[threadIdx.x].claim = 0;
+    t->board[threadIdx.x].done = 0;
+    t->board[threadIdx.x].exit = 0;
+    t->board[threadIdx.x].dk = dk + TEAM_DK_BYTES * threadIdx.x;
+  }
+}
+
+// A helper: claim slices of its team's rounds until the team is done.  It
+// waits for a round it has not exhausted yet; a long silence (no round, no
+// exit) ends it too, and the running workgroup then does the slices alone.
+template <int BS>
+__device__ void team_helper(TeamBoard* tb, LDSP uint64_t* hm, Shared& sh) {
+  const int tid = threadIdx.x;
+  uint32_t last = 0;  // the last round this member exhausted
+  for (;;) {
+    // wait (thread 0, relaxed polls) for a round other than `last`, or the end
+    if (tid == 0) {
+      uint32_t seq = 0;
+      const uint64_t t0 = wall_clock64();
+      for (;;) {
+        const unsigned long long c0 = __hip_atomic_load(&tb->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        seq = (uint32_t)(c0 >> 32);
+        if (seq != 0 && seq != last) break;
+        if (__hip_atomic_load(&tb->exit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            wall_clock64() - t0 > TEAM_WAIT_TICKS) {
+          seq = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (seq) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the round's data
+      sh.key = (int32_t)seq;
+    }
+    __syncthreads();
+    const uint32_t seq = (uint32_t)uni(sh.key);
+    __syncthreads();
+    if (seq == 0) break;
+    // claim slices of round seq until none is left, then publish them
+    int64_t mypc = 0;
+    uint32_t mine = 0;
+    for (;;) {
+      if (tid == 0) sh.idx = team_claim(tb, seq);
+      __syncthreads();
+      const int sl = uni(sh.idx);
+      __syncthreads();
+      if (sl < 0) break;
+      team_slice<BS>(tb, sl, hm, sh);
+      if (tid == 0) mypc += sh.acc64[4];
+      ++mine;
+    }
+    team_publish<BS>(tb, sh, mypc, mine);
+    last = seq;
+  }
+}
+
+// Diagrams from TEAM_MIN_N spiders: blocks 8 k + x form team x (k = 0 runs
+// the diagrams the team takes from the queue, k > 0 help with their
+// rounds), so a team's members share one XCD and its L2.
+template <int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1)))
+void team_kernel(uint8_t* const* table, int32_t n_graphs, TeamCtl* ctl, SimpArgs a) {
+  extern __shared__ __align__(16) uint8_t smem_dyn[];
+  __shared__ Shared sh;
+  __shared__ uint64_t hm[TEAM_SLICE];
+  TeamBoard* tb = &ctl->board[blockIdx.x & 7];
+  if ((blockIdx.x >> 3) != 0) {
+    team_helper<BS>(tb, (LDSP uint64_t*)hm, sh);
+    return;
+  }
+  a.tb = tb;
+  for (;;) {
+    if (threadIdx.x == 0) sh.idx = (int32_t)atomicAdd(&ctl->next, 1u);
+    __syncthreads();
+    const int idx = uni(sh.idx);
+    __syncthreads();
+    if (idx >= n_graphs) break;
+    process_diagram<BS, false>(table[idx], smem_dyn, a, sh);
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(&tb->exit, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Rollouts: item i = (state i / per_state, candidate slot i % per_state).
@@ -1851,6 +2145,26 @@ std::map<std::string, int>& tune_cache() {
 
 // ===================================================================== ABI
 
+// Greedy diagrams of TEAM_MIN_N spiders and more: one team of workgroups
+// per XCD, the team buffer allocated and freed in stream order.
+static zx_status launch_teams(uint8_t* const* table, int32_t n, SimpArgs a, hipStream_t s) {
+  const ZxDevice* d = zx_device();
+  if (!d) return ZX_EDEVICE;
+  const size_t bytes = sizeof(TeamCtl) + 8 * (size_t)TEAM_DK_BYTES;
+  void* mem = nullptr;
+  ZX_HIP(hipMallocAsync(&mem, bytes, s));
+  TeamCtl* tc = (TeamCtl*)mem;
+  hipLaunchKernelGGL(team_reset, dim3(1), dim3(64), 0, s, tc, (int8_t*)mem + sizeof(TeamCtl));
+  a.lds_cap = TEAM_LDS;
+  ZX_HIP(hipFuncSetAttribute((const void*)team_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)TEAM_LDS));
+  const int per_xcd = d->n_cu / 8 > 0 ? d->n_cu / 8 : 1;
+  hipLaunchKernelGGL(team_kernel<512>, dim3(8 * per_xcd), dim3(512), (size_t)TEAM_LDS, s, table, n, tc, a);
+  ZX_HIP(hipGetLastError());
+  ZX_HIP(hipFreeAsync(mem, s));
+  return ZX_OK;
+}
+
 struct zx_batch {
   uint8_t** table_dev;  // in the workspace
   Queue* queue;         // in the workspace
@@ -1860,6 +2174,7 @@ struct zx_batch {
   int32_t max_n;
   double mean_n;
   int32_t tuned;        // autotuned variant, -1 if none
+  int32_t n_big;        // the first n_big diagrams (largest first) run with teams
 };
 
 extern "C" int32_t zx_simplify_variants(void) { return kNumVariants; }
@@ -1905,6 +2220,13 @@ extern "C" zx_status zx_batch_prepare(zx_batch** b, zx_graph* const* graphs, int
   }
   B->mean_n = sum / n_graphs;
   B->tuned = -1;
+  // diagrams whose arena-mode rounds a team of workgroups shares
+  B->n_big = 0;
+  while (B->n_big < n_graphs) {
+    const int nn = B->sizes[B->n_big], ww = (nn + 63) / 64;
+    if (nn < TEAM_MIN_N || ww > TEAM_MAXW || aux_bytes(nn, ww) + 1024 > TEAM_LDS) break;
+    ++B->n_big;
+  }
   hipError_t e = hipMemcpyAsync(B->table_dev, B->arenas.data(), (size_t)n_graphs * 8,
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1956,8 +2278,9 @@ static int pick_variant(const zx_batch* b, int tune_id, bool learned) {
 }
 
 static SimpArgs simp_args(const zx_simplify_opts* o) {
-  SimpArgs a;
+  SimpArgs a{};
   a.lds_cap = 0;
+  a.tb = nullptr;
   a.extract = o->extract;
   a.max_rounds = o->max_rounds > 0 ? o->max_rounds : 0;
   a.resume = (o->flags & ZX_RESUME) ? 1 : 0;
@@ -2048,8 +2371,15 @@ extern "C" zx_status zx_batch_simplify(zx_batch* b, const zx_simplify_opts* o, h
     zx_set_error("diagrams too large for simplify variant %d", v);
     return ZX_ECAPACITY;
   }
-  zx_status st = launch_simplify(v, b->table_dev, b->n, b->queue, simp_args(o), learned, s);
-  if (st != ZX_OK) return st;
+  const int32_t n_big = learned ? 0 : b->n_big;
+  if (n_big > 0) {
+    zx_status st = launch_teams(b->table_dev, n_big, simp_args(o), s);
+    if (st != ZX_OK) return st;
+  }
+  if (b->n > n_big) {
+    zx_status st = launch_simplify(v, b->table_dev + n_big, b->n - n_big, b->queue, simp_args(o), learned, s);
+    if (st != ZX_OK) return st;
+  }
   if (o->flags & ZX_SYNC) ZX_HIP(hipStreamSynchronize(s));
   return ZX_OK;
 }
