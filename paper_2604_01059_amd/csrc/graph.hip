@@ -98,6 +98,8 @@ struct __attribute__((aligned(256))) TeamBoard {
   unsigned long long claim;
   uint32_t done;        // slices finished in the current round
   uint32_t exit;        // the team's diagrams are done
+  uint32_t owner;       // serving: 1 while a workgroup runs a diagram with this board
+  uint32_t pad0;
   unsigned long long pc;  // edges left on the updated rows (sum over slices)
   int32_t ns, pivot, n, W;
   int64_t ldw;
@@ -1836,7 +1838,13 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
   __shared__ int64_t claimed;
+  __shared__ uint64_t hm[TEAM_SLICE];
   uint64_t last = wall_clock64();  // used by thread 0 only
+  // Large greedy requests share their round updates with the idle
+  // workgroups of their XCD (the board of blockIdx & 7): an idle workgroup
+  // that sees a round it has not helped with yet takes slices of it.
+  TeamBoard* board = (!LEARN && a.team) ? (TeamBoard*)a.team + (blockIdx.x & 7) : nullptr;
+  uint32_t helped = 0;  // thread 0: the last round this workgroup looked at
   for (;;) {
     // Idle workgroups look for work in device memory: dtail, a copy of the
     // host's ring tail.  One of them at a time (the one holding the poller
@@ -1875,6 +1883,18 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
         // workgroup idle on its own is not enough: under a thin stream of
         // requests most workgroups go without one for a while, and those
         // that left would not come back while others stay busy.)
+        if (board) {
+          const unsigned long long c0 =
+              __hip_atomic_load(&board->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t seq = (uint32_t)(c0 >> 32);
+          if (seq != 0 && seq != helped) {
+            helped = seq;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the round's data
+            sh.key = (int32_t)seq;
+            got = -3;
+            break;
+          }
+        }
         const uint64_t now = wall_clock64();
         const uint64_t act = (uint64_t)__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
@@ -1890,6 +1910,24 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
     const int64_t idx = uni64(claimed);
     __syncthreads();
     if (idx == -2) break;
+    if (idx == -3) {
+      // help with one round of the board's diagram, then look for work again
+      const uint32_t seq = (uint32_t)uni(sh.key);
+      int64_t mypc = 0;
+      uint32_t mine = 0;
+      for (;;) {
+        if (threadIdx.x == 0) sh.idx = team_claim(board, seq);
+        __syncthreads();
+        const int sl = uni(sh.idx);
+        __syncthreads();
+        if (sl < 0) break;
+        team_slice<BS>(board, sl, (LDSP uint64_t*)hm, sh);
+        if (threadIdx.x == 0) mypc += sh.acc64[4];
+        ++mine;
+      }
+      team_publish<BS>(board, sh, mypc, mine);
+      continue;
+    }
     if (idx >= 0) {
       const int64_t slot = idx & (a.cap - 1);
       const uint64_t t_claim = wall_clock64();
@@ -1914,8 +1952,26 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
       __syncthreads();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      process_diagram<BS, LEARN>(arena, smem_dyn, sa, sh);
+      // a large request takes its XCD's board if no other request holds it
+      SimpArgs sr = sa;
+      sr.tb = nullptr;
+      if (board) {
+        const ZxHeader* hh = (const ZxHeader*)arena;
+        if (threadIdx.x == 0) {
+          uint32_t zero = 0;
+          const int nn = hh->n;
+          sh.any = nn >= TEAM_MIN_N && (nn + 63) / 64 <= TEAM_MAXW &&
+                   __hip_atomic_compare_exchange_strong(&board->owner, &zero, 1u, __ATOMIC_RELAXED,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (uni(sh.any)) sr.tb = board;
+        __syncthreads();
+      }
+      process_diagram<BS, LEARN>(arena, smem_dyn, sr, sh);
       __syncthreads();
+      if (sr.tb && threadIdx.x == 0)
+        __hip_atomic_store(&board->owner, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (threadIdx.x == 0) {
         const ZxHeader* h = (const ZxHeader*)arena;
         ZxServeRes* r = &a.res[slot];
@@ -2162,6 +2218,26 @@ static zx_status launch_teams(uint8_t* const* table, int32_t n, SimpArgs a, hipS
   hipLaunchKernelGGL(team_kernel<512>, dim3(8 * per_xcd), dim3(512), (size_t)TEAM_LDS, s, table, n, tc, a);
   ZX_HIP(hipGetLastError());
   ZX_HIP(hipFreeAsync(mem, s));
+  return ZX_OK;
+}
+
+// The serving pool's team area: eight boards and their phase-increment rows.
+size_t zx_team_area_bytes() { return sizeof(TeamBoard) * 8 + 8 * (size_t)TEAM_DK_BYTES; }
+
+__global__ void team_area_init(TeamBoard* b, int8_t* dk) {
+  if (threadIdx.x < 8) {
+    b[threadIdx.x].claim = 0;
+    b[threadIdx.x].done = 0;
+    b[threadIdx.x].exit = 0;
+    b[threadIdx.x].owner = 0;
+    b[threadIdx.x].dk = dk + TEAM_DK_BYTES * threadIdx.x;
+  }
+}
+
+zx_status zx_team_area_init(void* area, hipStream_t s) {
+  hipLaunchKernelGGL(team_area_init, dim3(1), dim3(64), 0, s, (TeamBoard*)area,
+                     (int8_t*)area + sizeof(TeamBoard) * 8);
+  ZX_HIP(hipGetLastError());
   return ZX_OK;
 }
 

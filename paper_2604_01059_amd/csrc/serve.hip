@@ -137,6 +137,7 @@ static zx_status relaunch(zx_server* S) {
   a.stage = S->sh->stage;
   a.stage_bytes = S->sh->stage_bytes;
   a.pad = 0;
+  a.team = S->pool + 256;
   zx_status st = zx_launch_serve(a, S->stream);
   if (st != ZX_OK) return st;
   ZX_HIP(hipEventRecord(S->ended, S->stream));
@@ -156,7 +157,9 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   ZX_CHECK_ARG(o->policy == ZX_POLICY_GREEDY || o->policy == ZX_POLICY_LEARNED, "unknown policy");
   if (o->policy == ZX_POLICY_LEARNED)
     ZX_CHECK_ARG(o->mlp && o->mlp->param && o->mlp->wbf16, "learned policy needs a network");
-  const size_t head = 256;
+  // control block (256 bytes), then the team area of large requests
+  const size_t team_bytes = align256(zx_team_area_bytes());
+  const size_t head = 256 + team_bytes;
   if (pool_bytes < head + 4096) {
     zx_set_error("pool too small");
     return ZX_ECAPACITY;
@@ -201,6 +204,7 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ended, hipEventDisableTiming);
   // control block: head, device copy of the tail, host-poller flag
   if (e == hipSuccess) e = hipMemsetAsync(S->head, 0, 256, S->stream);
+  if (e == hipSuccess && zx_team_area_init(S->pool + 256, S->stream) != ZX_OK) e = hipErrorLaunchFailure;
   if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) {
     zx_set_error("server set-up failed: %s", hipGetErrorString(e));

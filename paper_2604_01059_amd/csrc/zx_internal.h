@@ -141,7 +141,12 @@ struct ZxServeArgs {
   int32_t pad;
   const uint64_t* stage;        // per entry: staged header + SOURCE sections (host memory)
   const uint64_t* stage_bytes;  // per entry: bytes to copy into the arena
+  void* team;                   // device: the pool's team area (boards of large requests), or null
 };
+// The serving pool's team area (large requests share their round updates
+// with idle workgroups): its size, and its initialisation on s.
+size_t zx_team_area_bytes();
+zx_status zx_team_area_init(void* area, hipStream_t s);
 // Launch the resident serving kernel on s (grid: one workgroup per CU).
 zx_status zx_launch_serve(const ZxServeArgs& a, hipStream_t s);
 void zx_clear_error();
