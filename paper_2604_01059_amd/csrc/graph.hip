@@ -94,6 +94,7 @@ constexpr int TEAM_SLICE = 64;     // rows per slice
 constexpr int TEAM_MAXW = 128;     // words per row (n <= 8192)
 constexpr int TEAM_MAXS = 64;      // selected spiders of a round
 constexpr int TEAM_MIN_N = 1500;   // diagrams from this size get a team
+constexpr int SERVE_BOARDS_PER_XCD = 4;  // serving: large requests with a team at once, per XCD
 struct __attribute__((aligned(256))) TeamBoard {
   unsigned long long claim;
   uint32_t done;        // slices finished in the current round
@@ -1843,8 +1844,11 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
   // Large greedy requests share their round updates with the idle
   // workgroups of their XCD (the board of blockIdx & 7): an idle workgroup
   // that sees a round it has not helped with yet takes slices of it.
-  TeamBoard* board = (!LEARN && a.team) ? (TeamBoard*)a.team + (blockIdx.x & 7) : nullptr;
-  uint32_t helped = 0;  // thread 0: the last round this workgroup looked at
+  // (boards x, x + 8, x + 16, x + 24 belong to XCD x = blockIdx & 7)
+  TeamBoard* boards = (!LEARN && a.team) ? (TeamBoard*)a.team : nullptr;
+  const int xcd = blockIdx.x & 7;
+  uint32_t helped[SERVE_BOARDS_PER_XCD] = {};  // thread 0: the last round looked at, per board
+  TeamBoard* board = nullptr;                    // the board being helped, or held
   for (;;) {
     // Idle workgroups look for work in device memory: dtail, a copy of the
     // host's ring tail.  One of them at a time (the one holding the poller
@@ -1883,14 +1887,23 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
         // workgroup idle on its own is not enough: under a thin stream of
         // requests most workgroups go without one for a while, and those
         // that left would not come back while others stay busy.)
-        if (board) {
-          const unsigned long long c0 =
-              __hip_atomic_load(&board->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const uint32_t seq = (uint32_t)(c0 >> 32);
-          if (seq != 0 && seq != helped) {
-            helped = seq;
+        if (boards) {
+          int hb = -1;
+          uint32_t hseq = 0;
+          for (int bi = 0; bi < SERVE_BOARDS_PER_XCD && hb < 0; ++bi) {
+            TeamBoard* bd = boards + xcd + 8 * bi;
+            const unsigned long long c0 = __hip_atomic_load(&bd->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t seq = (uint32_t)(c0 >> 32);
+            if (seq != 0 && seq != helped[bi]) {
+              helped[bi] = seq;
+              hb = bi;
+              hseq = seq;
+            }
+          }
+          if (hb >= 0) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the round's data
-            sh.key = (int32_t)seq;
+            sh.key = (int32_t)hseq;
+            sh.cnt = hb;
             got = -3;
             break;
           }
@@ -1913,6 +1926,7 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
     if (idx == -3) {
       // help with one round of the board's diagram, then look for work again
       const uint32_t seq = (uint32_t)uni(sh.key);
+      board = boards + xcd + 8 * uni(sh.cnt);
       int64_t mypc = 0;
       uint32_t mine = 0;
       for (;;) {
@@ -1955,23 +1969,29 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
       // a large request takes its XCD's board if no other request holds it
       SimpArgs sr = sa;
       sr.tb = nullptr;
-      if (board) {
+      if (boards) {
         const ZxHeader* hh = (const ZxHeader*)arena;
         if (threadIdx.x == 0) {
-          uint32_t zero = 0;
           const int nn = hh->n;
-          sh.any = nn >= TEAM_MIN_N && (nn + 63) / 64 <= TEAM_MAXW &&
-                   __hip_atomic_compare_exchange_strong(&board->owner, &zero, 1u, __ATOMIC_RELAXED,
-                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          int held = -1;
+          if (nn >= TEAM_MIN_N && (nn + 63) / 64 <= TEAM_MAXW)
+            for (int bi = 0; bi < SERVE_BOARDS_PER_XCD && held < 0; ++bi) {
+              uint32_t zero = 0;
+              if (__hip_atomic_compare_exchange_strong(&boards[xcd + 8 * bi].owner, &zero, 1u, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                held = bi;
+            }
+          sh.cnt = held;
         }
         __syncthreads();
-        if (uni(sh.any)) sr.tb = board;
+        const int held = uni(sh.cnt);
+        if (held >= 0) sr.tb = boards + xcd + 8 * held;
         __syncthreads();
       }
       process_diagram<BS, LEARN>(arena, smem_dyn, sr, sh);
       __syncthreads();
       if (sr.tb && threadIdx.x == 0)
-        __hip_atomic_store(&board->owner, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sr.tb->owner, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (threadIdx.x == 0) {
         const ZxHeader* h = (const ZxHeader*)arena;
         ZxServeRes* r = &a.res[slot];
@@ -2222,10 +2242,11 @@ static zx_status launch_teams(uint8_t* const* table, int32_t n, SimpArgs a, hipS
 }
 
 // The serving pool's team area: eight boards and their phase-increment rows.
-size_t zx_team_area_bytes() { return sizeof(TeamBoard) * 8 + 8 * (size_t)TEAM_DK_BYTES; }
+constexpr int SERVE_BOARDS = 8 * SERVE_BOARDS_PER_XCD;
+size_t zx_team_area_bytes() { return sizeof(TeamBoard) * SERVE_BOARDS + SERVE_BOARDS * (size_t)TEAM_DK_BYTES; }
 
 __global__ void team_area_init(TeamBoard* b, int8_t* dk) {
-  if (threadIdx.x < 8) {
+  if (threadIdx.x < SERVE_BOARDS) {
     b[threadIdx.x].claim = 0;
     b[threadIdx.x].done = 0;
     b[threadIdx.x].exit = 0;
@@ -2236,7 +2257,7 @@ __global__ void team_area_init(TeamBoard* b, int8_t* dk) {
 
 zx_status zx_team_area_init(void* area, hipStream_t s) {
   hipLaunchKernelGGL(team_area_init, dim3(1), dim3(64), 0, s, (TeamBoard*)area,
-                     (int8_t*)area + sizeof(TeamBoard) * 8);
+                     (int8_t*)area + sizeof(TeamBoard) * SERVE_BOARDS);
   ZX_HIP(hipGetLastError());
   return ZX_OK;
 }

@@ -103,6 +103,7 @@ struct zx_server {
   zx_simplify_opts opts;
   int32_t max_n;
   int64_t* head;    // device, at the head of the pool
+  uint8_t* team;    // device, the team area after the control block (null in small pools)
   uint8_t* arenas;  // request slices start here
   PoolAlloc alloc;
   uint8_t* staging;  // pinned, coherent host memory
@@ -137,7 +138,7 @@ static zx_status relaunch(zx_server* S) {
   a.stage = S->sh->stage;
   a.stage_bytes = S->sh->stage_bytes;
   a.pad = 0;
-  a.team = S->pool + 256;
+  a.team = S->team;
   zx_status st = zx_launch_serve(a, S->stream);
   if (st != ZX_OK) return st;
   ZX_HIP(hipEventRecord(S->ended, S->stream));
@@ -157,8 +158,9 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   ZX_CHECK_ARG(o->policy == ZX_POLICY_GREEDY || o->policy == ZX_POLICY_LEARNED, "unknown policy");
   if (o->policy == ZX_POLICY_LEARNED)
     ZX_CHECK_ARG(o->mlp && o->mlp->param && o->mlp->wbf16, "learned policy needs a network");
-  // control block (256 bytes), then the team area of large requests
-  const size_t team_bytes = align256(zx_team_area_bytes());
+  // control block (256 bytes), then, in a pool that can hold large requests
+  // (64 MiB and more), the team area through which they share their rounds
+  const size_t team_bytes = pool_bytes >= ((size_t)64 << 20) ? align256(zx_team_area_bytes()) : 0;
   const size_t head = 256 + team_bytes;
   if (pool_bytes < head + 4096) {
     zx_set_error("pool too small");
@@ -204,7 +206,9 @@ extern "C" zx_status zx_server_create(zx_server** out, void* pool, size_t pool_b
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ended, hipEventDisableTiming);
   // control block: head, device copy of the tail, host-poller flag
   if (e == hipSuccess) e = hipMemsetAsync(S->head, 0, 256, S->stream);
-  if (e == hipSuccess && zx_team_area_init(S->pool + 256, S->stream) != ZX_OK) e = hipErrorLaunchFailure;
+  if (e == hipSuccess && team_bytes && zx_team_area_init(S->pool + 256, S->stream) != ZX_OK)
+    e = hipErrorLaunchFailure;
+  S->team = team_bytes ? S->pool + 256 : nullptr;
   if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) {
     zx_set_error("server set-up failed: %s", hipGetErrorString(e));
