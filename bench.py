@@ -534,6 +534,40 @@ def bench_extract(zx, pool, steps=5):
     return out
 
 
+def bench_large(zx, reps=3):
+    """Serving-stream diagrams of 2000 to 8000 spiders, one zx_simplify call each
+    (large diagrams run on a team of workgroups), checked against the oracle's
+    stored results (tests/golden/large_diagrams.json)."""
+    import hashlib
+    import torch
+    from workloads import serve_diagram
+    path = os.path.join(ROOT, "tests", "golden", "large_diagrams.json")
+    es = sorted(json.load(open(path))["entries"], key=lambda e: e["n"])
+    out = {"workload": "serving-stream diagrams (seed 5) of %d to %d spiders, one zx_simplify call each, "
+                       "with the output frontier" % (es[0]["n"], es[-1]["n"]), "diagrams": []}
+    exact = 0
+    for e in es:
+        d = serve_diagram(e["seed"], e["item"])
+        g = zx.Graph.from_diagram(d)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            zx.simplify([g], extract=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        adj, ph, al, info = g.read()
+        ok = (info.status == 0 and info.n_edges == e["n_edges"] and info.rounds == e["rounds"] and
+              info.rowops == e["rowops"] and
+              hashlib.sha256(np.ascontiguousarray(adj.astype("<u8")).tobytes()).hexdigest() == e["sha_adj"])
+        exact += ok
+        out["diagrams"].append({"n": d.n, "rounds": int(info.rounds), "ms": round(min(ts), 2)})
+        log("large: n %d, %.2f ms" % (d.n, min(ts)))
+    out["bit_exact_vs_oracle"] = "%d/%d" % (exact, len(es))
+    return out
+
+
 def _gen_diag(i):
     from workloads import batch_diagram
     return batch_diagram(3, i)
@@ -843,7 +877,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", default="all", choices=["all", "rref", "pauli", "batched", "learned", "serve", "copy",
-                                                      "parity", "sample", "params", "c1", "extract"])
+                                                      "parity", "sample", "params", "c1", "extract", "large"])
     ap.add_argument("--learned-states", type=int, default=200000)
     ap.add_argument("--learned-val-states", type=int, default=8000)
     ap.add_argument("--learned-epochs", type=int, default=8)
@@ -940,6 +974,9 @@ def main():
     if args.only in ("all", "extract"):
         out["extract"] = bench_extract(zx, pool)
         log("extract: %s" % out["extract"])
+    if args.only in ("all", "large"):
+        out["large"] = bench_large(zx)
+        log("large: %s" % out["large"])
     if args.only in ("all", "learned"):
         out["learned"] = bench_learned(zx, args, pool)
         log("learned: %s" % out["learned"])

@@ -81,3 +81,28 @@ def test_serve_large_against_oracle(zx):
         assert r.fill_in == e["fill_in"] and r.rounds == e["rounds"] and r.n_trace == e["n_trace"], ctx
         assert r.rank == e["rank"] and r.rowops == e["rowops"], ctx
     sv.close()
+
+
+def test_mixed_batch_large_and_small(zx):
+    """One batch with large diagrams (run by the team kernel) and small ones
+    (run by the regular kernel after it): every result as the oracle's."""
+    import oracle
+    from workloads import batch_diagram
+    es = [e for e in entries() if e["n"] < 3500]
+    big = [serve_diagram(e["seed"], e["item"]) for e in es]
+    small = [batch_diagram(3, i) for i in range(24)]
+    ds = small[:12] + big + small[12:]
+    gs = [zx.Graph.from_diagram(d) for d in ds]
+    print("mixed batch", [d.n for d in ds], flush=True)
+    zx.simplify(gs, extract=True)
+    for g, e in zip(gs[12:12 + len(big)], es):
+        adj, ph, al, info = g.read()
+        assert info.status == 0 and info.rounds == e["rounds"] and info.rowops == e["rowops"], e["n"]
+        assert digest(adj.astype("<u8")) == e["sha_adj"] and digest(g.trace().astype("<i4")) == e["sha_trace"]
+    for g, d in zip(gs[:12] + gs[12 + len(big):], small):
+        og = oracle.Graph.from_diagram(d)
+        og.simplify()
+        adj, ph, al, info = g.read()
+        assert info.status == 0
+        assert np.array_equal(adj, og.adj) and np.array_equal(ph, og.k) and np.array_equal(al, og.alive)
+        np.testing.assert_array_equal(g.trace(), og.trace)
