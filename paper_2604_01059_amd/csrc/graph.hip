@@ -363,10 +363,14 @@ __device__ bool build_candidates(Ctx<LA>& c, Shared& sh, int kind) {
 
 // Lexicographically-first maximal independent set of the candidates (scan
 // in ascending spider id, take a candidate unless adjacent to one taken).
-// One wavefront, one 64-spider block at a time: lane l checks candidate
-// 64b + l against the spiders taken in earlier blocks (its row AND the taken
-// mask), then the survivors of the block are resolved in ascending order
-// with scalar bit operations on their rows' word b.
+// One wavefront, one 64-spider block at a time.  The wave keeps the union
+// of the taken spiders' rows (lane l: words l and l + 64), so a block's
+// candidates that are adjacent to a spider taken in an earlier block are
+// one word of it; the rest are resolved in ascending order with scalar bit
+// operations on their rows' word b, loaded one block ahead; then the rows
+// of the block's taken spiders are OR-ed into the union, four at a time.
+// Per block, the only wait on memory is for those rows and the next
+// block's words, issued together.
 template <int BS, bool LA>
 __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
   const int W = c.W;
@@ -374,31 +378,22 @@ __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
   __syncthreads();
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
+    // clamped word indices (W <= 128): a lane's words past W are loaded
+    // from word W - 1 and never read
+    const int j0 = lane < W ? lane : W - 1;
+    const int j1 = lane + 64 < W ? lane + 64 : W - 1;
+    uint64_t blk0 = 0, blk1 = 0;
+    uint64_t nxt = ((c.cand[0] >> lane) & 1) ? row_ptr(c, lane)[0] : 0;
     for (int b = 0; b < W; ++b) {
-      const uint64_t cw = c.cand[b];
-      if (!cw) continue;
-      const int u = 64 * b + lane;
-      const bool isc = (cw >> lane) & 1;
-      bool free_ = isc;
-      uint64_t inblk = 0;
-      if (isc) {
-        const auto ru = row_ptr(c, u);
-        if constexpr (LA) {
-          for (int jj = 0; jj < b; ++jj)
-            if (ru[jj] & c.sel[jj]) { free_ = false; break; }
-        } else {
-          // rows in the arena: eight words of u's row per step, loaded together
-          for (int jj = 0; jj < b && free_; jj += 8) {
-            uint64_t hit = 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-              if (jj + q < b) hit |= ru[jj + q] & c.sel[jj + q];
-            free_ = hit == 0;
-          }
-        }
-        inblk = ru[b];
+      const uint64_t cw = uni64((int64_t)c.cand[b]);
+      const uint64_t inblk = nxt;
+      if (b + 1 < W) {
+        const uint64_t cn = c.cand[b + 1];
+        nxt = ((cn >> lane) & 1) ? row_ptr(c, 64 * (b + 1) + lane)[b + 1] : 0;
       }
-      uint64_t R = __ballot(free_);  // survivors, to resolve in order
+      if (!cw) continue;
+      const uint64_t bw = readlane64(b < 64 ? blk0 : blk1, b & 63);
+      uint64_t R = cw & ~bw;  // candidates with no taken neighbour in earlier blocks
       uint64_t taken = 0;
       while (R) {
         const int l = __builtin_ctzll(R);
@@ -406,7 +401,28 @@ __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
         R &= ~(readlane64(inblk, l) | (1ull << l));
       }
       if (lane == 0) c.sel[b] = taken;
-      __builtin_amdgcn_wave_barrier();
+      uint64_t tk = taken;
+      while (tk) {
+        // four taken spiders (repeating the first when fewer are left), so
+        // that the eight loads are issued before one wait
+        int t[4];
+        t[0] = __builtin_ctzll(tk);
+        tk &= tk - 1;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          t[q] = tk ? __builtin_ctzll(tk) : t[0];
+          tk &= tk - 1;
+        }
+        uint64_t a0 = 0, a1 = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const auto rt = row_ptr(c, 64 * b + t[q]);
+          a0 |= rt[j0];
+          a1 |= rt[j1];
+        }
+        blk0 |= a0;
+        blk1 |= a1;
+      }
     }
   }
   __syncthreads();
@@ -509,7 +525,49 @@ __device__ void select_pivots(Ctx<LA>& c, Shared& sh) {
   __syncthreads();
 }
 
-// Per-round bookkeeping over the selected spiders (before the update).
+// List the words of the selected set (sh.nsw entries in c.blocked) and the
+// selected spiders in ascending order (sh.ns entries in c.slist).
+template <int BS, bool LA>
+__device__ void collect_swords(Ctx<LA>& c, Shared& sh) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    LDSP int32_t* sw = (LDSP int32_t*)c.blocked;
+    int cnt = 0, ns = 0;
+    for (int j0 = 0; j0 < c.W; j0 += 64) {
+      const int j = j0 + lane;
+      const uint64_t wd = j < c.W ? c.sel[j] : 0;
+      const bool nz = wd != 0;
+      const uint64_t b = __ballot(nz);
+      if (nz) sw[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] = j;
+      cnt += __popcll(b);
+      // ascending spider list: exclusive prefix of the per-word popcounts
+      const int pc = __popcll(wd);
+      int ex = 0, tot = 0;
+#pragma unroll
+      for (int bit = 0; bit < 7; ++bit) {
+        const uint64_t bb = __ballot((pc >> bit) & 1);
+        ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0)) << bit;
+        tot += __popcll(bb) << bit;
+      }
+      uint64_t m = wd;
+      int pos = ns + ex;
+      while (m) {
+        const int bit = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        c.slist[pos++] = (int16_t)(64 * j + bit);
+      }
+      ns += tot;
+    }
+    if (lane == 0) {
+      sh.nsw = cnt;
+      sh.ns = ns;
+    }
+  }
+  __syncthreads();
+}
+
+// Per-round bookkeeping over the selected spiders (before the update),
+// after listing them (collect_swords).
 // LC: acc64[0] = sum deg, acc64[1] = sum deg(deg-1)/2, acc64[2] = phase sum.
 // Pivot: acc64[0] = sum (deg u + deg v - 1), acc64[1] = sum T_p, acc64[2] = phase.
 // Also fills kc[] and, for pivots, swaps each pair's rows into contributions.
@@ -517,9 +575,10 @@ template <int BS, bool LA>
 __device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_only) {
   const int W = c.W;
   if (threadIdx.x == 0) sh.acc64[0] = sh.acc64[1] = sh.acc64[2] = sh.acc64[3] = 0;
-  __syncthreads();
-  for (int x = c.team; x < c.n; x += c.nteams) {
-    if (!bit_of(c.sel, x)) continue;
+  collect_swords<BS, LA>(c, sh);
+  const int ns = uni(sh.ns);
+  for (int i = c.team; i < ns; i += c.nteams) {
+    const int x = c.slist[i];
     const int p = pivot ? c.partner[x] : -1;
     if (pivot && p < x) continue;  // one team per pair, at its lower end
     auto rx = row_ptr(c, x);
@@ -568,47 +627,6 @@ __device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_onl
   }
   __syncthreads();
   (void)graph_only;
-}
-
-// List the words of the selected set (sh.nsw entries in c.blocked) and the
-// selected spiders in ascending order (sh.ns entries in c.slist).
-template <int BS, bool LA>
-__device__ void collect_swords(Ctx<LA>& c, Shared& sh) {
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    LDSP int32_t* sw = (LDSP int32_t*)c.blocked;
-    int cnt = 0, ns = 0;
-    for (int j0 = 0; j0 < c.W; j0 += 64) {
-      const int j = j0 + lane;
-      const uint64_t wd = j < c.W ? c.sel[j] : 0;
-      const bool nz = wd != 0;
-      const uint64_t b = __ballot(nz);
-      if (nz) sw[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] = j;
-      cnt += __popcll(b);
-      // ascending spider list: exclusive prefix of the per-word popcounts
-      const int pc = __popcll(wd);
-      int ex = 0, tot = 0;
-#pragma unroll
-      for (int bit = 0; bit < 7; ++bit) {
-        const uint64_t bb = __ballot((pc >> bit) & 1);
-        ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0)) << bit;
-        tot += __popcll(bb) << bit;
-      }
-      uint64_t m = wd;
-      int pos = ns + ex;
-      while (m) {
-        const int bit = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        c.slist[pos++] = (int16_t)(64 * j + bit);
-      }
-      ns += tot;
-    }
-    if (lane == 0) {
-      sh.nsw = cnt;
-      sh.ns = ns;
-    }
-  }
-  __syncthreads();
 }
 
 // The rank-|S| update of every present row outside S, by (row, word)
@@ -1021,8 +1039,9 @@ __device__ void delete_selected(Ctx<LA>& c, Shared& sh, bool cols_done) {
       if (v & c.sel[kw]) row[kw] = v & ~c.sel[kw];
     }
   }
-  for (int x = c.team; x < n; x += c.nteams) {
-    if (!bit_of(c.sel, x)) continue;
+  const int ns = uni(sh.ns);
+  for (int i = c.team; i < ns; i += c.nteams) {
+    const int x = c.slist[i];
     auto rx = row_ptr(c, x);
     for (int j = c.tl; j < W; j += c.T) rx[j] = 0;
     if (c.tl == 0) c.k[x] = 0;
@@ -1237,7 +1256,6 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     const int removed = uni(sh.cnt);
     trace_lc_round<BS, LA>(c, sh);
     prepare_round<BS, LA>(c, sh, false, false);
-    collect_swords<BS, LA>(c, sh);
     if (c.pw) {
       terms_round<BS, LA>(c, sh, false);
       param_round<BS, LA>(c, sh, false);
@@ -1269,7 +1287,6 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     const int npairs = uni(sh.cnt);
     if (npairs == 0) break;
     prepare_round<BS, LA>(c, sh, true, false);
-    collect_swords<BS, LA>(c, sh);
     if (c.pw) {
       terms_round<BS, LA>(c, sh, true);
       param_round<BS, LA>(c, sh, true);
@@ -1277,8 +1294,7 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     const bool cc = apply_round<BS, LA>(c, sh, true);
     delete_selected<BS, LA>(c, sh, cc);
     finish_round<BS, LA>(c, sh, 2 * npairs);
-    for (int v = threadIdx.x; v < c.n; v += BS)
-      if (bit_of(c.sel, v)) c.partner[v] = -1;
+    for (int i = threadIdx.x; i < uni(sh.ns); i += BS) c.partner[c.slist[i]] = -1;
     if (threadIdx.x == 0) sh.round++;
     __syncthreads();
   }
@@ -1729,13 +1745,11 @@ __global__ __launch_bounds__(BS) void rollout_kernel(Queue* q, RollArgs a) {
       __syncthreads();
       // the candidate as a one-rewrite round, then the greedy schedule
       prepare_round<BS, true>(c, sh, piv, false);
-      collect_swords<BS, true>(c, sh);
       const bool cc = apply_round<BS, true>(c, sh, piv);
       delete_selected<BS, true>(c, sh, cc);
       finish_round<BS, true>(c, sh, piv ? 2 : 1);
       if (piv) {
-        for (int x = tid; x < c.n; x += BS)
-          if (bit_of(c.sel, x)) c.partner[x] = -1;
+        for (int i = tid; i < uni(sh.ns); i += BS) c.partner[c.slist[i]] = -1;
         __syncthreads();
       }
       simplify_rounds<BS, true, false>(c, sh, nullptr, 0);
@@ -2104,7 +2118,6 @@ __global__ __launch_bounds__(BS) void single_rewrite_kernel(uint8_t* arena, int3
     __syncthreads();
   } else {
     prepare_round<BS, LA>(c, sh, pivot != 0, false);
-    collect_swords<BS, LA>(c, sh);
     terms_round<BS, LA>(c, sh, pivot != 0);
     param_round<BS, LA>(c, sh, pivot != 0);
     const bool cc = apply_round<BS, LA>(c, sh, pivot != 0);
