@@ -643,66 +643,100 @@ __device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_onl
 constexpr int MAXI = 4;
 constexpr int SPIDER_MAJOR_MAX = 64;
 
-// Arena mode (rows in global memory), rounds of at most 64 rewrites.  Rows
-// go in chunks that fit the free LDS: a per-row pass records which selected
-// spiders the row is adjacent to (hit mask) and updates the row's phase;
-// then a (row, word) pass XORs the hit contributions, staged in LDS when
-// they fit, and drops the selected columns in the same write.  Each row
-// word is read and written once; each selected-column bit once per row.
-// Slice s of a team round (rows 64 s .. 64 s + 63), whole workgroup: per row
-// the mask of selected spiders it touches and its phase increment, then the
-// (row, word) XOR pass with the selected spiders' rows (not changed by the
-// round), the row's own bit and the selected columns cleared.  Then the
-// slice's edge count, and done, are published.  hm: 64 words of LDS.
-template <int BS>
-__device__ void team_slice(TeamBoard* tb, int slice, LDSP uint64_t* hm, Shared& sh) {
+// LDS words that team_slice works in.
+constexpr int TEAM_SLICE_LDS = 352;
+
+// Slice s of a team round, whole workgroup: rows 64 s .. 64 s + 63, whose
+// bits in any row are that row's word s.  The adjacency is symmetric and
+// the selected spiders' rows do not change during the round, so the
+// slice's rows adjacent to a selected spider are word s of its row (for a
+// pivot pair (x, p), whose rows prepare_round swapped into contributions,
+// x's neighbours are word s of p's current row and p's those of x's): one
+// word per selected spider (two for pivots), all loaded at once, gives
+// every row's hit mask and phase increment.  Then the (row, word) XOR pass
+// with the hit contributions, the row's own bit and the selected columns
+// cleared, U items per thread loaded before any is used (U = 2 in the
+// running workgroup, whose registers the greedy kernel's occupancy bounds).
+// The slice's edge count goes to sh.acc64[4].  ls: TEAM_SLICE_LDS words of
+// LDS.
+template <int BS, int U>
+__device__ void team_slice(TeamBoard* tb, int slice, LDSP uint64_t* ls, Shared& sh) {
+  static_assert(BS >= 256, "a slice's staging takes 193 threads");
   const int tid = threadIdx.x;
   const int n = tb->n, W = tb->W, ns = tb->ns, pivot = tb->pivot;
   const int64_t ldw = tb->ldw;
   uint64_t* adj = tb->adj;
   const int lo = slice * TEAM_SLICE;
   const int rn = n - lo < TEAM_SLICE ? n - lo : TEAM_SLICE;
-  if (tid == 0) sh.acc64[4] = 0;
-  for (int t = tid; t < rn; t += BS) {
-    const int w = lo + t;
+  LDSP uint64_t* hm = ls;                         // per row: hit mask over the selected list
+  LDSP uint64_t* nb = ls + 64;                    // per selected spider: its rows in the slice
+  LDSP uint64_t* pb = ls + 128;                   // pivots: the partner's rows in the slice
+  LDSP uint64_t* selw = ls + 192;                 // the selected set (W <= 128 words)
+  LDSP uint64_t* act = ls + 320;                  // present, non-selected rows of the slice
+  LDSP int16_t* sl = (LDSP int16_t*)(ls + 321);  // the selected list (64 entries)
+  LDSP int8_t* kc = (LDSP int8_t*)(ls + 337);    // their phase contributions (64 bytes)
+  if (tid < ns) {
+    const int x = tb->slist[tid];
+    const int src = pivot ? tb->partner[tid] : x;
+    nb[tid] = adj[(int64_t)src * ldw + slice];
+    if (pivot) pb[tid] = adj[(int64_t)x * ldw + slice];
+    sl[tid] = (int16_t)x;
+    kc[tid] = tb->kc[tid];
+  } else if (tid >= 64 && tid < 64 + W) {
+    selw[tid - 64] = tb->sel[tid - 64];
+  } else if (tid == 192) {
+    act[0] = tb->alive[slice] & ~tb->sel[slice];
+    sh.acc64[4] = 0;
+  }
+  __syncthreads();
+  const uint64_t am = act[0];
+  if (tid < rn) {
     uint64_t m = 0;
     int dk = 0;
-    if (((tb->alive[w >> 6] >> (w & 63)) & 1) && !((tb->sel[w >> 6] >> (w & 63)) & 1)) {
-      const uint64_t* rw = adj + (int64_t)w * ldw;
+    if ((am >> tid) & 1) {
       for (int i = 0; i < ns; ++i) {
-        const int x = tb->slist[i];
-        if ((rw[x >> 6] >> (x & 63)) & 1) {
+        if ((nb[i] >> tid) & 1) {
           m |= 1ull << i;
-          dk += tb->kc[i];
-          if (pivot) {
-            const int pp = tb->partner[i];
-            if ((rw[pp >> 6] >> (pp & 63)) & 1) dk += 2;  // adjacent to both ends
-          }
+          dk += kc[i];
+          if (pivot && ((pb[i] >> tid) & 1)) dk += 2;  // adjacent to both ends
         }
       }
     }
-    hm[t] = m;
-    tb->dk[w] = (int8_t)(dk & 7);
+    hm[tid] = m;
+    tb->dk[lo + tid] = (int8_t)(dk & 7);
   }
   __syncthreads();
   int64_t pc = 0;
-  for (int64_t it = tid; it < (int64_t)rn * W; it += BS) {
-    const int t = (int)(it / W), j = (int)(it - (int64_t)t * W);
-    const int w = lo + t;
-    if (!((tb->alive[w >> 6] >> (w & 63)) & 1) || ((tb->sel[w >> 6] >> (w & 63)) & 1)) continue;
-    uint64_t* rw = adj + (int64_t)w * ldw;
-    const uint64_t old = rw[j];
-    uint64_t v = old;
-    uint64_t m = hm[t];
-    while (m) {
-      const int i = __builtin_ctzll(m);
-      m &= m - 1;
-      v ^= adj[(int64_t)tb->slist[i] * ldw + j];
+  const int items = rn * W;
+  for (int base = 0; base < items; base += U * BS) {
+    uint64_t old[U];
+    int tt[U], jj[U];
+    bool ok[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int it = base + q * BS + tid;
+      const int itc = it < items ? it : 0;
+      tt[q] = itc / W;
+      jj[q] = itc - tt[q] * W;
+      ok[q] = it < items && ((am >> tt[q]) & 1);
+      old[q] = adj[(int64_t)(lo + tt[q]) * ldw + jj[q]];  // row lo + tt < n: in bounds
     }
-    if (j == (w >> 6)) v &= ~(1ull << (w & 63));
-    v &= ~tb->sel[j];
-    if (v != old) rw[j] = v;
-    pc += __popcll(v);
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (!ok[q]) continue;
+      const int t = tt[q], j = jj[q];
+      uint64_t v = old[q];
+      uint64_t m = hm[t];
+      while (m) {
+        const int i = __builtin_ctzll(m);
+        m &= m - 1;
+        v ^= adj[(int64_t)sl[i] * ldw + j];
+      }
+      if (j == slice) v &= ~(1ull << t);
+      v &= ~selw[j];
+      if (v != old[q]) adj[(int64_t)(lo + t) * ldw + j] = v;
+      pc += __popcll(v);
+    }
   }
   block_add(&sh.acc64[4], pc);
   __syncthreads();
@@ -776,7 +810,7 @@ __device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pi
   }
   __syncthreads();
   const uint32_t seq = (uint32_t)uni(sh.key);
-  LDSP uint64_t* hm = c.scr;  // 64 words of the free LDS
+  LDSP uint64_t* hm = c.scr;  // TEAM_SLICE_LDS words of the free LDS
   int64_t mypc = 0;
   uint32_t mine = 0;
   for (;;) {
@@ -785,7 +819,7 @@ __device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pi
     const int sl = uni(sh.idx);
     __syncthreads();
     if (sl < 0) break;
-    team_slice<BS>(tb, sl, hm, sh);
+    team_slice<BS, 2>(tb, sl, hm, sh);
     if (tid == 0) mypc += sh.acc64[4];
     ++mine;
   }
@@ -814,6 +848,12 @@ __device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pi
   __syncthreads();
 }
 
+// Arena mode (rows in global memory), rounds of at most 64 rewrites.  Rows
+// go in chunks that fit the free LDS: a per-row pass records which selected
+// spiders the row is adjacent to (hit mask) and updates the row's phase;
+// then a (row, word) pass XORs the hit contributions, staged in LDS when
+// they fit, and drops the selected columns in the same write.  Each row
+// word is read and written once; each selected-column bit once per row.
 // Not inlined: its unrolled update would otherwise set the register
 // allocation of the LDS-resident path that shares the kernel.
 template <int BS>
@@ -927,7 +967,7 @@ __device__ __noinline__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool p
 template <int BS, bool LA>
 __device__ bool apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
   if constexpr (!LA) {
-    if (c.tb && uni(sh.ns) <= TEAM_MAXS && c.scr_words >= 64) {
+    if (c.tb && uni(sh.ns) <= TEAM_MAXS && c.scr_words >= TEAM_SLICE_LDS) {
       apply_round_team<BS>(c, sh, pivot);
       return true;
     }
@@ -1612,7 +1652,7 @@ __device__ void team_helper(TeamBoard* tb, LDSP uint64_t* hm, Shared& sh) {
       const int sl = uni(sh.idx);
       __syncthreads();
       if (sl < 0) break;
-      team_slice<BS>(tb, sl, hm, sh);
+      team_slice<BS, 4>(tb, sl, hm, sh);
       if (tid == 0) mypc += sh.acc64[4];
       ++mine;
     }
@@ -1629,7 +1669,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1)))
 void team_kernel(uint8_t* const* table, int32_t n_graphs, TeamCtl* ctl, SimpArgs a) {
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
-  __shared__ uint64_t hm[TEAM_SLICE];
+  __shared__ uint64_t hm[TEAM_SLICE_LDS];
   TeamBoard* tb = &ctl->board[blockIdx.x & 7];
   if ((blockIdx.x >> 3) != 0) {
     team_helper<BS>(tb, (LDSP uint64_t*)hm, sh);
@@ -1853,7 +1893,7 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
   __shared__ int64_t claimed;
-  __shared__ uint64_t hm[TEAM_SLICE];
+  __shared__ uint64_t hm[TEAM_SLICE_LDS];
   uint64_t last = wall_clock64();  // used by thread 0 only
   // Large greedy requests share their round updates with the idle
   // workgroups of their XCD (the board of blockIdx & 7): an idle workgroup
@@ -1949,7 +1989,7 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
         const int sl = uni(sh.idx);
         __syncthreads();
         if (sl < 0) break;
-        team_slice<BS>(board, sl, (LDSP uint64_t*)hm, sh);
+        team_slice<BS, 4>(board, sl, (LDSP uint64_t*)hm, sh);
         if (threadIdx.x == 0) mypc += sh.acc64[4];
         ++mine;
       }
