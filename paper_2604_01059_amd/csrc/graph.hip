@@ -643,8 +643,43 @@ __device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_onl
 constexpr int MAXI = 4;
 constexpr int SPIDER_MAJOR_MAX = 64;
 
-// LDS words that team_slice works in.
-constexpr int TEAM_SLICE_LDS = 352;
+// A team round as a slice sees it; the selected list, partners, phase
+// contributions and the present and selected masks are staged in LDS once
+// per round and member (TEAM_SLICE_LDS words, layout below).
+struct SliceRound {
+  uint64_t* adj;
+  int8_t* dk;
+  int64_t ldw;
+  int n, W, ns, pivot;
+};
+constexpr int TS_NB = 64, TS_PB = 128, TS_SEL = 192, TS_ALIVE = 320;  // words; hit masks at 0
+constexpr int TS_SL = 448, TS_PP = 464, TS_KC = 480;                 // int16, int16, int8 arrays
+constexpr int TEAM_SLICE_LDS = 488;
+
+// A helper's copy of the round on the board (after the acquire that made
+// it visible).  Ends with a barrier.
+template <int BS>
+__device__ SliceRound team_stage_board(TeamBoard* tb, LDSP uint64_t* ls) {
+  SliceRound r;
+  r.adj = tb->adj;
+  r.dk = tb->dk;
+  r.ldw = tb->ldw;
+  r.n = tb->n;
+  r.W = tb->W;
+  r.ns = tb->ns;
+  r.pivot = tb->pivot;
+  const int tid = threadIdx.x;
+  if (tid < r.ns) {
+    ((LDSP int16_t*)(ls + TS_SL))[tid] = tb->slist[tid];
+    ((LDSP int16_t*)(ls + TS_PP))[tid] = tb->partner[tid];
+    ((LDSP int8_t*)(ls + TS_KC))[tid] = tb->kc[tid];
+  } else if (tid >= 64 && tid < 64 + r.W) {
+    ls[TS_SEL + tid - 64] = tb->sel[tid - 64];
+    ls[TS_ALIVE + tid - 64] = tb->alive[tid - 64];
+  }
+  __syncthreads();
+  return r;
+}
 
 // Slice s of a team round, whole workgroup: rows 64 s .. 64 s + 63, whose
 // bits in any row are that row's word s.  The adjacency is symmetric and
@@ -652,79 +687,70 @@ constexpr int TEAM_SLICE_LDS = 352;
 // slice's rows adjacent to a selected spider are word s of its row (for a
 // pivot pair (x, p), whose rows prepare_round swapped into contributions,
 // x's neighbours are word s of p's current row and p's those of x's): one
-// word per selected spider (two for pivots), all loaded at once, gives
-// every row's hit mask and phase increment.  Then the (row, word) XOR pass
-// with the hit contributions, the row's own bit and the selected columns
-// cleared, U items per thread loaded before any is used (U = 2 in the
-// running workgroup, whose registers the greedy kernel's occupancy bounds).
-// The slice's edge count goes to sh.acc64[4].  ls: TEAM_SLICE_LDS words of
-// LDS.
+// word per selected spider (two for pivots) gives every row's hit mask and
+// phase increment.  Those words and the first U (row, word) items of each
+// thread are loaded together, before the hit masks; then the items are
+// XOR-ed with their hit contributions, the row's own bit and the selected
+// columns cleared.  The slice's edge count goes to sh.acc64[4].
 template <int BS, int U>
-__device__ void team_slice(TeamBoard* tb, int slice, LDSP uint64_t* ls, Shared& sh) {
-  static_assert(BS >= 256, "a slice's staging takes 193 threads");
-  const int tid = threadIdx.x;
-  const int n = tb->n, W = tb->W, ns = tb->ns, pivot = tb->pivot;
-  const int64_t ldw = tb->ldw;
-  uint64_t* adj = tb->adj;
+__device__ void team_slice(const SliceRound& r, int slice, LDSP uint64_t* ls, Shared& sh) {
+  static_assert(BS >= 192, "a round's staging takes 192 threads");
+  const int tid = threadIdx.x, W = r.W, ns = r.ns;
+  const int64_t ldw = r.ldw;
+  uint64_t* adj = r.adj;
   const int lo = slice * TEAM_SLICE;
-  const int rn = n - lo < TEAM_SLICE ? n - lo : TEAM_SLICE;
-  LDSP uint64_t* hm = ls;                         // per row: hit mask over the selected list
-  LDSP uint64_t* nb = ls + 64;                    // per selected spider: its rows in the slice
-  LDSP uint64_t* pb = ls + 128;                   // pivots: the partner's rows in the slice
-  LDSP uint64_t* selw = ls + 192;                 // the selected set (W <= 128 words)
-  LDSP uint64_t* act = ls + 320;                  // present, non-selected rows of the slice
-  LDSP int16_t* sl = (LDSP int16_t*)(ls + 321);  // the selected list (64 entries)
-  LDSP int8_t* kc = (LDSP int8_t*)(ls + 337);    // their phase contributions (64 bytes)
-  if (tid < ns) {
-    const int x = tb->slist[tid];
-    const int src = pivot ? tb->partner[tid] : x;
-    nb[tid] = adj[(int64_t)src * ldw + slice];
-    if (pivot) pb[tid] = adj[(int64_t)x * ldw + slice];
-    sl[tid] = (int16_t)x;
-    kc[tid] = tb->kc[tid];
-  } else if (tid >= 64 && tid < 64 + W) {
-    selw[tid - 64] = tb->sel[tid - 64];
-  } else if (tid == 192) {
-    act[0] = tb->alive[slice] & ~tb->sel[slice];
-    sh.acc64[4] = 0;
-  }
-  __syncthreads();
-  const uint64_t am = act[0];
-  if (tid < rn) {
-    uint64_t m = 0;
-    int dk = 0;
-    if ((am >> tid) & 1) {
-      for (int i = 0; i < ns; ++i) {
-        if ((nb[i] >> tid) & 1) {
-          m |= 1ull << i;
-          dk += kc[i];
-          if (pivot && ((pb[i] >> tid) & 1)) dk += 2;  // adjacent to both ends
-        }
-      }
-    }
-    hm[tid] = m;
-    tb->dk[lo + tid] = (int8_t)(dk & 7);
-  }
-  __syncthreads();
-  int64_t pc = 0;
+  const int rn = r.n - lo < TEAM_SLICE ? r.n - lo : TEAM_SLICE;
   const int items = rn * W;
+  LDSP uint64_t* hm = ls;
+  const LDSP int16_t* sl = (const LDSP int16_t*)(ls + TS_SL);
+  const LDSP int16_t* pp = (const LDSP int16_t*)(ls + TS_PP);
+  const LDSP int8_t* kc = (const LDSP int8_t*)(ls + TS_KC);
+  // the selected spiders' words of the slice (spider 0 stands in past ns)
+  const int x = tid < ns ? sl[tid] : 0;
+  const int src = tid < ns && r.pivot ? pp[tid] : x;
+  const uint64_t wa = adj[(int64_t)src * ldw + slice];
+  const uint64_t wb = r.pivot ? adj[(int64_t)x * ldw + slice] : 0;
+  const uint64_t am = ls[TS_ALIVE + slice] & ~ls[TS_SEL + slice];  // present, non-selected rows
+  int64_t pc = 0;
   for (int base = 0; base < items; base += U * BS) {
     uint64_t old[U];
     int tt[U], jj[U];
-    bool ok[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int it = base + q * BS + tid;
       const int itc = it < items ? it : 0;
       tt[q] = itc / W;
       jj[q] = itc - tt[q] * W;
-      ok[q] = it < items && ((am >> tt[q]) & 1);
       old[q] = adj[(int64_t)(lo + tt[q]) * ldw + jj[q]];  // row lo + tt < n: in bounds
+    }
+    if (base == 0) {
+      if (tid < ns) {
+        ls[TS_NB + tid] = wa;
+        ls[TS_PB + tid] = wb;
+      }
+      if (tid == 0) sh.acc64[4] = 0;
+      __syncthreads();
+      if (tid < rn) {
+        uint64_t m = 0;
+        int dk = 0;
+        if ((am >> tid) & 1) {
+          for (int i = 0; i < ns; ++i) {
+            if ((ls[TS_NB + i] >> tid) & 1) {
+              m |= 1ull << i;
+              dk += kc[i];
+              if (r.pivot && ((ls[TS_PB + i] >> tid) & 1)) dk += 2;  // adjacent to both ends
+            }
+          }
+        }
+        hm[tid] = m;
+        r.dk[lo + tid] = (int8_t)(dk & 7);
+      }
+      __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      if (!ok[q]) continue;
       const int t = tt[q], j = jj[q];
+      if (base + q * BS + tid >= items || !((am >> t) & 1)) continue;
       uint64_t v = old[q];
       uint64_t m = hm[t];
       while (m) {
@@ -733,7 +759,7 @@ __device__ void team_slice(TeamBoard* tb, int slice, LDSP uint64_t* ls, Shared& 
         v ^= adj[(int64_t)sl[i] * ldw + j];
       }
       if (j == slice) v &= ~(1ull << t);
-      v &= ~selw[j];
+      v &= ~ls[TS_SEL + j];
       if (v != old[q]) adj[(int64_t)(lo + t) * ldw + j] = v;
       pc += __popcll(v);
     }
@@ -780,16 +806,31 @@ template <int BS>
 __device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pivot) {
   TeamBoard* tb = c.tb;
   const int tid = threadIdx.x, W = c.W, n = c.n, ns = uni(sh.ns);
+  LDSP uint64_t* ls = c.scr;  // TEAM_SLICE_LDS words of the free LDS
   for (int i = tid; i < ns; i += BS) {
     const int x = c.slist[i];
+    const int16_t p = pivot ? c.partner[x] : (int16_t)-1;
     tb->slist[i] = (int16_t)x;
-    tb->partner[i] = pivot ? c.partner[x] : (int16_t)-1;
+    tb->partner[i] = p;
     tb->kc[i] = c.kc[x];
+    ((LDSP int16_t*)(ls + TS_SL))[i] = (int16_t)x;
+    ((LDSP int16_t*)(ls + TS_PP))[i] = p;
+    ((LDSP int8_t*)(ls + TS_KC))[i] = c.kc[x];
   }
   for (int j = tid; j < W; j += BS) {
     tb->alive[j] = c.alive[j];
     tb->sel[j] = c.sel[j];
+    ls[TS_ALIVE + j] = c.alive[j];
+    ls[TS_SEL + j] = c.sel[j];
   }
+  SliceRound r;
+  r.adj = c.adj;
+  r.dk = tb->dk;
+  r.ldw = c.ldw;
+  r.n = n;
+  r.W = W;
+  r.ns = ns;
+  r.pivot = pivot ? 1 : 0;
   if (tid == 0) {
     tb->ns = ns;
     tb->pivot = pivot ? 1 : 0;
@@ -806,20 +847,21 @@ __device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pi
     const unsigned long long c0 = __hip_atomic_load(&tb->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t seq = (uint32_t)(c0 >> 32) + 1;
     sh.key = (int32_t)seq;
-    __hip_atomic_store(&tb->claim, (unsigned long long)seq << 32, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // published with slice 0 already taken, by this workgroup
+    __hip_atomic_store(&tb->claim, ((unsigned long long)seq << 32) | 1u, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   const uint32_t seq = (uint32_t)uni(sh.key);
-  LDSP uint64_t* hm = c.scr;  // TEAM_SLICE_LDS words of the free LDS
   int64_t mypc = 0;
   uint32_t mine = 0;
-  for (;;) {
-    if (tid == 0) sh.idx = team_claim(tb, seq);
+  for (bool first = true;; first = false) {
+    if (tid == 0) sh.idx = first ? 0 : team_claim(tb, seq);
     __syncthreads();
     const int sl = uni(sh.idx);
     __syncthreads();
     if (sl < 0) break;
-    team_slice<BS, 2>(tb, sl, hm, sh);
+    team_slice<BS, 2>(r, sl, ls, sh);
     if (tid == 0) mypc += sh.acc64[4];
     ++mine;
   }
@@ -840,9 +882,18 @@ __device__ __noinline__ void apply_round_team(Ctx<false>& c, Shared& sh, bool pi
     sh.acc64[4] = (int64_t)__hip_atomic_load(&tb->pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  for (int w = tid; w < n; w += BS) {
-    const int d = tb->dk[w];
-    if (d) c.k[w] = (int8_t)((c.k[w] + d) & 7);
+  // phase increments, eight rows per load (bytes from n on are not this
+  // diagram's)
+  const uint64_t* dk8 = (const uint64_t*)tb->dk;
+  for (int q = tid; 8 * q < n; q += BS) {
+    uint64_t d = dk8[q];
+    if (8 * q + 8 > n) d &= (1ull << (8 * (n - 8 * q))) - 1;
+    while (d) {
+      const int b = __builtin_ctzll(d) >> 3;
+      const int w = 8 * q + b;
+      c.k[w] = (int8_t)((c.k[w] + (int)((d >> (8 * b)) & 0xff)) & 7);
+      d &= ~(0xffull << (8 * b));
+    }
   }
   if (tid == 0) sh.acc64[3] += sh.acc64[4];
   __syncthreads();
@@ -1644,6 +1695,9 @@ __device__ void team_helper(TeamBoard* tb, LDSP uint64_t* hm, Shared& sh) {
     __syncthreads();
     if (seq == 0) break;
     // claim slices of round seq until none is left, then publish them
+    // (a round finished meanwhile leaves no slice to claim, so a copy of a
+    // later round's data is never used)
+    const SliceRound r = team_stage_board<BS>(tb, hm);
     int64_t mypc = 0;
     uint32_t mine = 0;
     for (;;) {
@@ -1652,7 +1706,7 @@ __device__ void team_helper(TeamBoard* tb, LDSP uint64_t* hm, Shared& sh) {
       const int sl = uni(sh.idx);
       __syncthreads();
       if (sl < 0) break;
-      team_slice<BS, 4>(tb, sl, hm, sh);
+      team_slice<BS, 8>(r, sl, hm, sh);
       if (tid == 0) mypc += sh.acc64[4];
       ++mine;
     }
@@ -1981,6 +2035,7 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
       // help with one round of the board's diagram, then look for work again
       const uint32_t seq = (uint32_t)uni(sh.key);
       board = boards + xcd + 8 * uni(sh.cnt);
+      const SliceRound r = team_stage_board<BS>(board, (LDSP uint64_t*)hm);
       int64_t mypc = 0;
       uint32_t mine = 0;
       for (;;) {
@@ -1989,7 +2044,7 @@ __global__ __launch_bounds__(BS) void serve_kernel(ZxServeArgs a, SimpArgs sa) {
         const int sl = uni(sh.idx);
         __syncthreads();
         if (sl < 0) break;
-        team_slice<BS, 4>(board, sl, (LDSP uint64_t*)hm, sh);
+        team_slice<BS, 8>(r, sl, (LDSP uint64_t*)hm, sh);
         if (threadIdx.x == 0) mypc += sh.acc64[4];
         ++mine;
       }
