@@ -409,8 +409,10 @@ def _oracle_c1(seed):
 
 def bench_c1(zx):
     """One diagram (8 qubits, 64 spiders, p = 0.1), seeds 1..1000: latency of
-    one launch per diagram, kernel only (HIP events) and end to end (host
-    clock around launch and result read), against the oracle on one core."""
+    one launch per diagram, kernel only (HIP events around the launch, queued
+    behind a spin so that host launch work is not counted) and end to end
+    (host clock around launch and result read), against the oracle on one
+    core."""
     import torch
     from workloads import single_diagram
     ds = [single_diagram(s) for s in range(1, 1001)]
@@ -423,14 +425,30 @@ def bench_c1(zx):
     kern, e2e = [], []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # Kernel time: a spin on the stream holds it while the host queues the
+    # launch, so that the events bracket device time alone (with an idle
+    # stream, the first event would also count the host's launch work).
+    cycles = 20000
+    for _ in range(12):
+        e0.record(stream)
+        torch.cuda._sleep(cycles)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if e0.elapsed_time(e1) >= 0.3:
+            break
+        cycles *= 2
     for g, b in zip(gs, bs):
-        t0 = time.perf_counter()
+        torch.cuda._sleep(cycles)
         e0.record(stream)
         b.run(extract=True)
         e1.record(stream)
+        torch.cuda.synchronize()
+        kern.append(e0.elapsed_time(e1) * 1e-3)
+        # end to end: host clock around the launch and the result read
+        t0 = time.perf_counter()
+        b.run(extract=True)
         info = g.info()  # synchronises
         e2e.append(time.perf_counter() - t0)
-        kern.append(e0.elapsed_time(e1) * 1e-3)
         assert info.status == 0
     exact = 0
     cpu = []

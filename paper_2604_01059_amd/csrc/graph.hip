@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1018,9 +1019,11 @@ __device__ __noinline__ void apply_round_arena(Ctx<false>& c, Shared& sh, bool p
 template <int BS, bool LA>
 __device__ bool apply_round(Ctx<LA>& c, Shared& sh, bool pivot) {
   if constexpr (!LA) {
-    if (c.tb && uni(sh.ns) <= TEAM_MAXS && c.scr_words >= TEAM_SLICE_LDS) {
-      apply_round_team<BS>(c, sh, pivot);
-      return true;
+    if constexpr (BS >= 256) {
+      if (c.tb && uni(sh.ns) <= TEAM_MAXS && c.scr_words >= TEAM_SLICE_LDS) {
+        apply_round_team<BS>(c, sh, pivot);
+        return true;
+      }
     }
     if (uni(sh.ns) <= SPIDER_MAJOR_MAX && c.scr_words >= 64) {
       apply_round_arena<BS>(c, sh, pivot);
@@ -1312,11 +1315,196 @@ __device__ __noinline__ void param_round(Ctx<LA>& c, Shared& sh, bool pivot) {
 #include "policy_dev.h"
 
 // ----------------------------------------------------------- simplify --
+// Diagrams of at most 64 spiders without parameters, greedy schedule: the
+// same rounds as simplify_rounds, run by one wavefront with the adjacency
+// in registers (lane v holds row v and phase k_v), so that a round costs a
+// few dozen wave instructions instead of a chain of LDS round trips and
+// barriers.  Candidate masks are ballots; the independent set and the
+// pivot pairs are chosen in ascending spider order with scalar bit
+// operations on rows read by v_readlane; every selected spider's update is
+// a uniform loop step that the rows it touches apply under their own mask.
+// Selected spiders are pairwise non-adjacent (pivot ends: not adjacent to
+// another pair's ends), so the rows they touch are read before the round's
+// updates change anything.  The state goes back to LDS for store_state and
+// the frontier.
+template <int BS>
+__device__ __noinline__ void simplify_rounds_tiny(Ctx<true>& c, Shared& sh, int max_rounds) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, n = c.n;
+    const bool mine = lane < n;
+    uint64_t row = mine ? c.adj[(int64_t)lane * c.ldw] : 0;
+    int k = mine ? c.k[lane] : 0;
+    uint64_t alive = c.alive[0];
+    const uint64_t bnd = c.bnd[0];
+    const uint64_t self = 1ull << lane;
+    int64_t E = sh.E, pw2 = sh.pow_sqrt2, fill = sh.fill_in;
+    int phase8 = sh.phase8, nt = sh.n_trace, round = sh.round, status = 0;
+    const int round_cap = round + n + 1;
+    for (int kind = 0; kind < 2; ++kind) {  // local complementation, then pivots
+      for (;;) {
+        if (max_rounds > 0 && round >= max_rounds) break;
+        if (round > round_cap) {
+          status = ZX_EDEVICE;
+          break;
+        }
+        const bool isc = mine && ((alive >> lane) & 1) && !((bnd >> lane) & 1) && ((k & 3) == (kind == 0 ? 2 : 0));
+        const uint64_t cand = __ballot(isc);
+        if (!cand) break;
+        uint64_t sel = 0;
+        int npairs = 0;
+        int partner = -1;  // this lane's pivot partner
+        if (kind == 0) {
+          // lexicographically-first maximal independent set
+          uint64_t R = cand;
+          while (R) {
+            const int u = __builtin_ctzll(R);
+            sel |= 1ull << u;
+            R &= ~(readlane64(row, u) | (1ull << u));
+          }
+        } else {
+          // pivot pairs: ascending u, its lowest unblocked candidate
+          // neighbour v above it; the pair blocks both neighbourhoods
+          uint64_t blocked = 0, P = cand;
+          while (P) {
+            const int u = __builtin_ctzll(P);
+            P &= P - 1;
+            if ((blocked >> u) & 1) continue;
+            const uint64_t ru = readlane64(row, u);
+            const uint64_t t = ru & cand & ~blocked & ~((2ull << u) - 1);
+            if (!t) continue;
+            const int v = __builtin_ctzll(t);
+            const uint64_t rv = readlane64(row, v);
+            blocked |= ru | rv | (1ull << u) | (1ull << v);
+            sel |= (1ull << u) | (1ull << v);
+            if (lane == u) partner = v;
+            if (lane == v) partner = u;
+            if (lane == 0 && c.trace) {
+              int32_t* e = c.trace + 4 * (int64_t)(nt + npairs);
+              e[0] = round;
+              e[1] = 1;
+              e[2] = u;
+              e[3] = v;
+            }
+            ++npairs;
+          }
+          if (npairs == 0) break;
+        }
+        const int removed = kind == 0 ? __popcll(sel) : 2 * npairs;
+        const bool is_sel = (sel >> lane) & 1;
+        if (kind == 0) {
+          if (is_sel && c.trace) {
+            int32_t* e = c.trace + 4 * (int64_t)(nt + __popcll(sel & (self - 1)));
+            e[0] = round;
+            e[1] = 0;
+            e[2] = lane;
+            e[3] = -1;
+          }
+          nt += removed;
+        } else {
+          nt += npairs;
+        }
+        // bookkeeping over the selected spiders (prepare_round's sums) and
+        // each selected lane's contribution row and phase contribution
+        int64_t s0 = 0, s1 = 0, s2 = 0;
+        uint64_t contrib = 0;
+        int kc = 0;
+        // the lane's partner row and phase (pivots; a per-lane source: shuffles)
+        const uint64_t prow = wave_shfl64(row, partner < 0 ? lane : partner, 64);
+        const int pk = __shfl(k, partner < 0 ? lane : partner, 64);
+        if (is_sel) {
+          if (kind == 0) {
+            const int dx = __popcll(row);
+            s0 = dx;
+            s1 = (int64_t)dx * (dx - 1) / 2;
+            s2 = k == 2 ? 1 : 7;
+            contrib = row;
+            kc = (8 - k) & 7;
+          } else {
+            contrib = prow & ~self;  // contribution of x: row of its partner minus x
+            kc = pk;
+            if (lane < partner) {
+              const int dx = __popcll(row), dp = __popcll(prow), common = __popcll(row & prow);
+              const int64_t A = dx - 1, B = dp - 1;
+              s0 = dx + dp - 1;
+              s1 = A * B - (int64_t)common * common;
+              s2 = 4 * ((k / 4) * (pk / 4));
+            }
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          s0 += __shfl_xor(s0, o, 64);
+          s1 += __shfl_xor(s1, o, 64);
+          s2 += __shfl_xor(s2, o, 64);
+        }
+        // the update: rows of present, non-selected spiders, by the selected
+        // spiders they touch (tested on the rows before the round)
+        const bool upd = mine && ((alive >> lane) & 1) && !is_sel;
+        const uint64_t hit = upd ? (row & sel) : 0;
+        int dk = 0;
+        uint64_t S = sel;
+        while (S) {
+          const int x = __builtin_ctzll(S);
+          S &= S - 1;
+          const uint64_t cx = readlane64(contrib, x);
+          const int kcx = __builtin_amdgcn_readlane(kc, x);
+          const int px = __builtin_amdgcn_readlane(partner, x);
+          if ((hit >> x) & 1) {
+            row ^= cx;
+            dk += kcx;
+            if (kind == 1 && ((hit >> px) & 1)) dk += 2;  // adjacent to both ends
+          }
+        }
+        if (upd) {
+          row &= ~self & ~sel;
+          k = (k + dk) & 7;
+        }
+        if (is_sel) {
+          row = 0;
+          k = 0;
+        }
+        alive &= ~sel;
+        int pc = __popcll(row);
+        for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+        // finish_round
+        const int64_t e_after = pc / 2;
+        pw2 += (e_after - E) + removed;
+        phase8 = (int)((phase8 + s2) & 7);
+        const int64_t others_before = E - s0;
+        fill += (s1 + (e_after - others_before)) / 2;
+        E = e_after;
+        ++round;
+      }
+      if (status) break;
+    }
+    if (mine) {
+      c.adj[(int64_t)lane * c.ldw] = row;
+      c.k[lane] = (int8_t)k;
+    }
+    if (lane == 0) {
+      c.alive[0] = alive;
+      sh.E = E;
+      sh.pow_sqrt2 = pw2;
+      sh.fill_in = fill;
+      sh.phase8 = phase8;
+      sh.n_trace = nt;
+      sh.round = round;
+      if (status) sh.status = status;
+    }
+  }
+  __syncthreads();
+}
+
 // Rounds until the fixed point, or until sh.round reaches max_rounds (> 0).
 // LEARN: candidates taken in the network's priority order (pol), else the
 // canonical order.
 template <int BS, bool LA, bool LEARN>
 __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds) {
+  if constexpr (LA && !LEARN) {
+    if (c.W == 1 && c.pw == 0) {
+      simplify_rounds_tiny<BS>(c, sh, max_rounds);
+      return;
+    }
+  }
   // every round deletes at least one spider: more than n + 1 rounds from
   // here would be a defect, reported instead of looping on
   const int round_cap = uni(sh.round) + c.n + 1;
@@ -1634,8 +1822,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(LEARN ? 1 : 
 void simplify_kernel(uint8_t* const* table, int32_t n_graphs, Queue* q, SimpArgs a) {
   extern __shared__ __align__(16) uint8_t smem_dyn[];
   __shared__ Shared sh;
-  for (;;) {
-    if (threadIdx.x == 0) sh.idx = (int32_t)atomicAdd(&q->next, 1u);
+  // q null: a grid of n_graphs workgroups, diagram blockIdx.x each
+  for (int k = 0;; ++k) {
+    if (threadIdx.x == 0)
+      sh.idx = q ? (int32_t)atomicAdd(&q->next, 1u) : (k == 0 ? (int32_t)blockIdx.x : n_graphs);
     __syncthreads();
     const int idx = uni(sh.idx);
     __syncthreads();
@@ -2282,7 +2472,9 @@ const Variant kVariants[] = {
     {256, 32 * 1024, "bs256-lds32k"},   {256, 64 * 1024, "bs256-lds64k"},
     {256, 96 * 1024, "bs256-lds96k"},   {256, 152 * 1024, "bs256-lds152k"},
     {512, 64 * 1024, "bs512-lds64k"},   {512, 152 * 1024, "bs512-lds152k"},
+    {64, 32 * 1024, "bs64-lds32k"},  // one wavefront: greedy schedule, small diagrams
 };
+constexpr int kOneWaveVariant = 6;
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 1;
 
@@ -2292,18 +2484,35 @@ zx_status launch_simplify_bs(uint8_t* const* table, int32_t n, Queue* q, const S
   const ZxDevice* d = zx_device();
   if (!d) return ZX_EDEVICE;
   const void* fn = (const void*)simplify_kernel<BS, LEARN>;
-  ZX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_cap));
+  // the LDS attribute and the occupancy, once per device and LDS size (one
+  // diagram per launch spends most of its time on the host otherwise)
+  static std::map<std::pair<int, int64_t>, int> occ;
+  static std::mutex occ_mu;
+  std::lock_guard<std::mutex> lock(occ_mu);
+  const std::pair<int, int64_t> key(d->id, a.lds_cap);
+  auto it = occ.find(key);
   int per_cu = 0;
-  ZX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BS, (size_t)a.lds_cap));
+  if (it != occ.end()) {
+    per_cu = it->second;
+  } else {
+    ZX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_cap));
+    ZX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BS, (size_t)a.lds_cap));
+    occ[key] = per_cu;
+  }
   if (per_cu < 1) {
     zx_set_error("simplify variant does not fit a CU");
     return ZX_ECAPACITY;
   }
   int grid = per_cu * d->n_cu;
-  if (grid > n) grid = n;
-  hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, s, q);
-  hipLaunchKernelGGL((simplify_kernel<BS, LEARN>), dim3(grid), dim3(BS), (size_t)a.lds_cap, s, table, n,
-                     q, a);
+  if (grid >= n) {
+    // a workgroup per diagram: no queue
+    hipLaunchKernelGGL((simplify_kernel<BS, LEARN>), dim3(n), dim3(BS), (size_t)a.lds_cap, s, table, n,
+                       (Queue*)nullptr, a);
+  } else {
+    hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, s, q);
+    hipLaunchKernelGGL((simplify_kernel<BS, LEARN>), dim3(grid), dim3(BS), (size_t)a.lds_cap, s, table, n,
+                       q, a);
+  }
   ZX_HIP(hipGetLastError());
   return ZX_OK;
 }
@@ -2312,6 +2521,13 @@ zx_status launch_simplify(int variant, uint8_t* const* table, int32_t n, Queue* 
                           bool learned, hipStream_t s) {
   const Variant& v = kVariants[variant];
   a.lds_cap = v.lds_cap;
+  if (v.bs == 64) {
+    if (learned) {
+      zx_set_error("variant %s runs the greedy schedule only", v.name);
+      return ZX_EINVAL;
+    }
+    return launch_simplify_bs<64, false>(table, n, q, a, s);
+  }
   if (v.bs == 256)
     return learned ? launch_simplify_bs<256, true>(table, n, q, a, s)
                    : launch_simplify_bs<256, false>(table, n, q, a, s);
@@ -2462,6 +2678,7 @@ static std::string size_class(const zx_batch* b) {
 static bool variant_fits_n(int max_n, int v, bool learned) {
   const ZxDevice* d = zx_device();
   if (!d || kVariants[v].lds_cap > (int64_t)d->lds_per_block) return false;
+  if (learned && kVariants[v].bs < 256) return false;
   if (max_n > 32767 || (max_n + 63) / 64 > MAXW) return false;
   const int W = (max_n + 63) / 64;
   const int64_t need = aux_bytes(max_n, W) + (learned ? pol_bytes(max_n, kVariants[v].bs) : 0);
@@ -2571,7 +2788,13 @@ extern "C" zx_status zx_batch_simplify(zx_batch* b, const zx_simplify_opts* o, h
                "ZX_FALLBACK compares whole schedules: no max_rounds, no ZX_RESUME");
   int v = pick_variant(b, o->tune_id, learned);
   // with the fallback, diagrams beyond the learned policy's LDS budget run greedy
-  if (fb && !variant_fits(b, v, true) && o->tune_id < 0) v = pick_variant(b, o->tune_id, false);
+  if (fb && !variant_fits(b, v, true) && o->tune_id < 0) {
+    v = pick_variant(b, o->tune_id, false);
+    if (kVariants[v].bs < 256) {  // the learned kernel does not come in one wavefront
+      const int w = pick_variant_n(b->max_n, false);
+      v = w >= 0 ? w : kDefaultVariant;
+    }
+  }
   if (!variant_fits(b, v, learned && !fb)) {
     zx_set_error("diagrams too large for simplify variant %d", v);
     return ZX_ECAPACITY;
