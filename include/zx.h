@@ -226,7 +226,12 @@ typedef struct {
   const zx_mlp* mlp;    /* ZX_POLICY_LEARNED: the scoring network */
 } zx_simplify_opts;
 
-/* Number of kernel variants and a short description of variant id. */
+/* Number of kernel variants and a short description of variant id
+ * ("bs<threads>-lds<KiB>k").  The one-wavefront variant (bs64) runs the
+ * greedy schedule only: with ZX_POLICY_LEARNED it is refused as too small
+ * (ZX_ECAPACITY).  Without a tune_id, a batch of up to 256 diagrams of at
+ * most 64 spiders takes it; such diagrams without parameters run their
+ * whole greedy simplification and frontier in one wavefront's registers. */
 int32_t zx_simplify_variants(void);
 const char* zx_simplify_variant_name(int32_t id);
 

@@ -1325,170 +1325,192 @@ __device__ __noinline__ void param_round(Ctx<LA>& c, Shared& sh, bool pivot) {
 // a uniform loop step that the rows it touches apply under their own mask.
 // Selected spiders are pairwise non-adjacent (pivot ends: not adjacent to
 // another pair's ends), so the rows they touch are read before the round's
-// updates change anything.  The state goes back to LDS for store_state and
-// the frontier.
+// updates change anything.
+struct Tiny {
+  uint64_t row;  // this lane's row
+  int k;         // this lane's phase (units of pi/4)
+  uint64_t alive, bnd;
+  int64_t E, pw2, fill;
+  int phase8, nt, round, status;
+};
+
+__device__ __forceinline__ void tiny_rounds(Tiny& st, int n, int32_t* trace, int max_rounds) {
+  const int lane = threadIdx.x;
+  const bool mine = lane < n;
+  const uint64_t self = 1ull << lane;
+  const int round_cap = st.round + n + 1;
+  for (int kind = 0; kind < 2; ++kind) {  // local complementation, then pivots
+    for (;;) {
+      if (max_rounds > 0 && st.round >= max_rounds) break;
+      if (st.round > round_cap) {
+        st.status = ZX_EDEVICE;
+        break;
+      }
+      const bool isc = mine && ((st.alive >> lane) & 1) && !((st.bnd >> lane) & 1) &&
+                       ((st.k & 3) == (kind == 0 ? 2 : 0));
+      const uint64_t cand = __ballot(isc);
+      if (!cand) break;
+      uint64_t sel = 0;
+      int npairs = 0;
+      int partner = -1;  // this lane's pivot partner
+      if (kind == 0) {
+        // lexicographically-first maximal independent set
+        uint64_t R = cand;
+        while (R) {
+          const int u = __builtin_ctzll(R);
+          sel |= 1ull << u;
+          R &= ~(readlane64(st.row, u) | (1ull << u));
+        }
+      } else {
+        // pivot pairs: ascending u, its lowest unblocked candidate neighbour
+        // v above it; the pair blocks both neighbourhoods
+        uint64_t blocked = 0, P = cand;
+        while (P) {
+          const int u = __builtin_ctzll(P);
+          P &= P - 1;
+          if ((blocked >> u) & 1) continue;
+          const uint64_t ru = readlane64(st.row, u);
+          const uint64_t t = ru & cand & ~blocked & ~((2ull << u) - 1);
+          if (!t) continue;
+          const int v = __builtin_ctzll(t);
+          const uint64_t rv = readlane64(st.row, v);
+          blocked |= ru | rv | (1ull << u) | (1ull << v);
+          sel |= (1ull << u) | (1ull << v);
+          if (lane == u) partner = v;
+          if (lane == v) partner = u;
+          if (lane == 0 && trace) {
+            int32_t* e = trace + 4 * (int64_t)(st.nt + npairs);
+            e[0] = st.round;
+            e[1] = 1;
+            e[2] = u;
+            e[3] = v;
+          }
+          ++npairs;
+        }
+        if (npairs == 0) break;
+      }
+      const int removed = kind == 0 ? __popcll(sel) : 2 * npairs;
+      const bool is_sel = (sel >> lane) & 1;
+      if (kind == 0) {
+        if (is_sel && trace) {
+          int32_t* e = trace + 4 * (int64_t)(st.nt + __popcll(sel & (self - 1)));
+          e[0] = st.round;
+          e[1] = 0;
+          e[2] = lane;
+          e[3] = -1;
+        }
+        st.nt += removed;
+      } else {
+        st.nt += npairs;
+      }
+      // bookkeeping over the selected spiders (prepare_round's sums), and
+      // each selected lane's contribution row and phase contribution; the
+      // partner's row and phase come by shuffle (a per-lane source)
+      int64_t s0 = 0, s1 = 0, s2 = 0;
+      uint64_t contrib = 0;
+      int kc = 0;
+      const uint64_t prow = wave_shfl64(st.row, partner < 0 ? lane : partner, 64);
+      const int pk = __shfl(st.k, partner < 0 ? lane : partner, 64);
+      if (is_sel) {
+        if (kind == 0) {
+          const int dx = __popcll(st.row);
+          s0 = dx;
+          s1 = (int64_t)dx * (dx - 1) / 2;
+          s2 = st.k == 2 ? 1 : 7;
+          contrib = st.row;
+          kc = (8 - st.k) & 7;
+        } else {
+          contrib = prow & ~self;  // contribution of x: its partner's row minus x
+          kc = pk;
+          if (lane < partner) {
+            const int dx = __popcll(st.row), dp = __popcll(prow), common = __popcll(st.row & prow);
+            const int64_t A = dx - 1, B = dp - 1;
+            s0 = dx + dp - 1;
+            s1 = A * B - (int64_t)common * common;
+            s2 = 4 * ((st.k / 4) * (pk / 4));
+          }
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+      }
+      // the update: rows of present, non-selected spiders, by the selected
+      // spiders they touch (tested on the rows before the round)
+      const bool upd = mine && ((st.alive >> lane) & 1) && !is_sel;
+      const uint64_t hit = upd ? (st.row & sel) : 0;
+      int dk = 0;
+      uint64_t S = sel;
+      while (S) {
+        const int x = __builtin_ctzll(S);
+        S &= S - 1;
+        const uint64_t cx = readlane64(contrib, x);
+        const int kcx = __builtin_amdgcn_readlane(kc, x);
+        const int px = __builtin_amdgcn_readlane(partner, x);
+        if ((hit >> x) & 1) {
+          st.row ^= cx;
+          dk += kcx;
+          if (kind == 1 && ((hit >> px) & 1)) dk += 2;  // adjacent to both ends
+        }
+      }
+      if (upd) {
+        st.row &= ~self & ~sel;
+        st.k = (st.k + dk) & 7;
+      }
+      if (is_sel) {
+        st.row = 0;
+        st.k = 0;
+      }
+      st.alive &= ~sel;
+      int pc = __popcll(st.row);
+      for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+      // finish_round
+      const int64_t e_after = pc / 2;
+      st.pw2 += (e_after - st.E) + removed;
+      st.phase8 = (int)((st.phase8 + s2) & 7);
+      const int64_t others_before = st.E - s0;
+      st.fill += (s1 + (e_after - others_before)) / 2;
+      st.E = e_after;
+      ++st.round;
+    }
+    if (st.status) break;
+  }
+}
+
+// The rounds only, from and back to the LDS state (for callers that keep
+// the rest of the pipeline in LDS).
 template <int BS>
 __device__ __noinline__ void simplify_rounds_tiny(Ctx<true>& c, Shared& sh, int max_rounds) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x, n = c.n;
     const bool mine = lane < n;
-    uint64_t row = mine ? c.adj[(int64_t)lane * c.ldw] : 0;
-    int k = mine ? c.k[lane] : 0;
-    uint64_t alive = c.alive[0];
-    const uint64_t bnd = c.bnd[0];
-    const uint64_t self = 1ull << lane;
-    int64_t E = sh.E, pw2 = sh.pow_sqrt2, fill = sh.fill_in;
-    int phase8 = sh.phase8, nt = sh.n_trace, round = sh.round, status = 0;
-    const int round_cap = round + n + 1;
-    for (int kind = 0; kind < 2; ++kind) {  // local complementation, then pivots
-      for (;;) {
-        if (max_rounds > 0 && round >= max_rounds) break;
-        if (round > round_cap) {
-          status = ZX_EDEVICE;
-          break;
-        }
-        const bool isc = mine && ((alive >> lane) & 1) && !((bnd >> lane) & 1) && ((k & 3) == (kind == 0 ? 2 : 0));
-        const uint64_t cand = __ballot(isc);
-        if (!cand) break;
-        uint64_t sel = 0;
-        int npairs = 0;
-        int partner = -1;  // this lane's pivot partner
-        if (kind == 0) {
-          // lexicographically-first maximal independent set
-          uint64_t R = cand;
-          while (R) {
-            const int u = __builtin_ctzll(R);
-            sel |= 1ull << u;
-            R &= ~(readlane64(row, u) | (1ull << u));
-          }
-        } else {
-          // pivot pairs: ascending u, its lowest unblocked candidate
-          // neighbour v above it; the pair blocks both neighbourhoods
-          uint64_t blocked = 0, P = cand;
-          while (P) {
-            const int u = __builtin_ctzll(P);
-            P &= P - 1;
-            if ((blocked >> u) & 1) continue;
-            const uint64_t ru = readlane64(row, u);
-            const uint64_t t = ru & cand & ~blocked & ~((2ull << u) - 1);
-            if (!t) continue;
-            const int v = __builtin_ctzll(t);
-            const uint64_t rv = readlane64(row, v);
-            blocked |= ru | rv | (1ull << u) | (1ull << v);
-            sel |= (1ull << u) | (1ull << v);
-            if (lane == u) partner = v;
-            if (lane == v) partner = u;
-            if (lane == 0 && c.trace) {
-              int32_t* e = c.trace + 4 * (int64_t)(nt + npairs);
-              e[0] = round;
-              e[1] = 1;
-              e[2] = u;
-              e[3] = v;
-            }
-            ++npairs;
-          }
-          if (npairs == 0) break;
-        }
-        const int removed = kind == 0 ? __popcll(sel) : 2 * npairs;
-        const bool is_sel = (sel >> lane) & 1;
-        if (kind == 0) {
-          if (is_sel && c.trace) {
-            int32_t* e = c.trace + 4 * (int64_t)(nt + __popcll(sel & (self - 1)));
-            e[0] = round;
-            e[1] = 0;
-            e[2] = lane;
-            e[3] = -1;
-          }
-          nt += removed;
-        } else {
-          nt += npairs;
-        }
-        // bookkeeping over the selected spiders (prepare_round's sums) and
-        // each selected lane's contribution row and phase contribution
-        int64_t s0 = 0, s1 = 0, s2 = 0;
-        uint64_t contrib = 0;
-        int kc = 0;
-        // the lane's partner row and phase (pivots; a per-lane source: shuffles)
-        const uint64_t prow = wave_shfl64(row, partner < 0 ? lane : partner, 64);
-        const int pk = __shfl(k, partner < 0 ? lane : partner, 64);
-        if (is_sel) {
-          if (kind == 0) {
-            const int dx = __popcll(row);
-            s0 = dx;
-            s1 = (int64_t)dx * (dx - 1) / 2;
-            s2 = k == 2 ? 1 : 7;
-            contrib = row;
-            kc = (8 - k) & 7;
-          } else {
-            contrib = prow & ~self;  // contribution of x: row of its partner minus x
-            kc = pk;
-            if (lane < partner) {
-              const int dx = __popcll(row), dp = __popcll(prow), common = __popcll(row & prow);
-              const int64_t A = dx - 1, B = dp - 1;
-              s0 = dx + dp - 1;
-              s1 = A * B - (int64_t)common * common;
-              s2 = 4 * ((k / 4) * (pk / 4));
-            }
-          }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-          s0 += __shfl_xor(s0, o, 64);
-          s1 += __shfl_xor(s1, o, 64);
-          s2 += __shfl_xor(s2, o, 64);
-        }
-        // the update: rows of present, non-selected spiders, by the selected
-        // spiders they touch (tested on the rows before the round)
-        const bool upd = mine && ((alive >> lane) & 1) && !is_sel;
-        const uint64_t hit = upd ? (row & sel) : 0;
-        int dk = 0;
-        uint64_t S = sel;
-        while (S) {
-          const int x = __builtin_ctzll(S);
-          S &= S - 1;
-          const uint64_t cx = readlane64(contrib, x);
-          const int kcx = __builtin_amdgcn_readlane(kc, x);
-          const int px = __builtin_amdgcn_readlane(partner, x);
-          if ((hit >> x) & 1) {
-            row ^= cx;
-            dk += kcx;
-            if (kind == 1 && ((hit >> px) & 1)) dk += 2;  // adjacent to both ends
-          }
-        }
-        if (upd) {
-          row &= ~self & ~sel;
-          k = (k + dk) & 7;
-        }
-        if (is_sel) {
-          row = 0;
-          k = 0;
-        }
-        alive &= ~sel;
-        int pc = __popcll(row);
-        for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
-        // finish_round
-        const int64_t e_after = pc / 2;
-        pw2 += (e_after - E) + removed;
-        phase8 = (int)((phase8 + s2) & 7);
-        const int64_t others_before = E - s0;
-        fill += (s1 + (e_after - others_before)) / 2;
-        E = e_after;
-        ++round;
-      }
-      if (status) break;
-    }
+    Tiny st;
+    st.row = mine ? c.adj[(int64_t)lane * c.ldw] : 0;
+    st.k = mine ? c.k[lane] : 0;
+    st.alive = c.alive[0];
+    st.bnd = c.bnd[0];
+    st.E = sh.E;
+    st.pw2 = sh.pow_sqrt2;
+    st.fill = sh.fill_in;
+    st.phase8 = sh.phase8;
+    st.nt = sh.n_trace;
+    st.round = sh.round;
+    st.status = 0;
+    tiny_rounds(st, n, c.trace, max_rounds);
     if (mine) {
-      c.adj[(int64_t)lane * c.ldw] = row;
-      c.k[lane] = (int8_t)k;
+      c.adj[(int64_t)lane * c.ldw] = st.row;
+      c.k[lane] = (int8_t)st.k;
     }
     if (lane == 0) {
-      c.alive[0] = alive;
-      sh.E = E;
-      sh.pow_sqrt2 = pw2;
-      sh.fill_in = fill;
-      sh.phase8 = phase8;
-      sh.n_trace = nt;
-      sh.round = round;
-      if (status) sh.status = status;
+      c.alive[0] = st.alive;
+      sh.E = st.E;
+      sh.pow_sqrt2 = st.pw2;
+      sh.fill_in = st.fill;
+      sh.phase8 = st.phase8;
+      sh.n_trace = st.nt;
+      sh.round = st.round;
+      if (st.status) sh.status = st.status;
     }
   }
   __syncthreads();
@@ -1686,10 +1708,119 @@ struct SimpArgs {
   TeamBoard* tb;        // arena-mode rounds shared with a team (else null)
 };
 
+// A whole greedy run of such a diagram in one wavefront's registers: the
+// state from the arena (SOURCE, or CURRENT to resume), the rounds, the
+// write-back of the CURRENT section and header, and the output frontier's
+// Gauss-Jordan elimination (rows = the outputs' spiders; pivot = the lowest
+// (leading column, row) pair among the rows not yet placed, swapped into
+// place; every other row holding the column is reduced and counted).  The
+// arena ends as run_diagram leaves it.
+template <int BS>
+__device__ __noinline__ void run_tiny(uint8_t* arena, const SimpArgs& a, Shared& sh) {
+  ZxHeader* h = (ZxHeader*)arena;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int n = h->n, q = h->n_out;
+    const bool mine = lane < n;
+    const bool src = !a.resume;
+    const uint64_t* adj0 = (const uint64_t*)(arena + (src ? h->off_src_adj : h->off_adj));
+    const int8_t* ph0 = (const int8_t*)(arena + (src ? h->off_src_phase : h->off_phase));
+    const int32_t* outs = (const int32_t*)(arena + h->off_out);
+    Tiny st;
+    st.row = mine ? adj0[lane] : 0;
+    st.k = mine ? ph0[lane] : 0;
+    st.alive = src ? (n == 64 ? ~0ull : ((1ull << n) - 1)) : *(const uint64_t*)(arena + h->off_alive);
+    st.bnd = *(const uint64_t*)(arena + h->off_bndmask);
+    const int out_sp = lane < q ? outs[lane] : 0;
+    st.pw2 = src ? 0 : h->pow_sqrt2;
+    st.phase8 = src ? 0 : h->phase8;
+    st.fill = src ? 0 : h->fill_in;
+    st.nt = src ? 0 : h->n_trace;
+    st.round = src ? 0 : h->rounds;
+    st.status = 0;
+    int pc = __popcll(st.row);
+    for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+    st.E = pc / 2;
+    tiny_rounds(st, n, (int32_t*)(arena + h->off_trace), a.max_rounds);
+    // CURRENT section and header
+    if (mine) {
+      ((uint64_t*)(arena + h->off_adj))[lane] = st.row;
+      ((int8_t*)(arena + h->off_phase))[lane] = (int8_t)st.k;
+    }
+    if (lane == 0) {
+      *(uint64_t*)(arena + h->off_alive) = st.alive;
+      h->pow_sqrt2 = st.pw2;
+      h->phase8 = st.phase8 & 7;
+      h->fill_in = st.fill;
+      h->n_edges = st.E;
+      h->n_alive = __popcll(st.alive);
+      h->n_trace = st.nt;
+      h->rounds = st.round;
+      if (st.status) zx_dev_fail(&h->status, st.status);
+    }
+    int rank = -1;
+    int64_t ops = 0;
+    if (a.extract && q > 0) {
+      // output frontier: row r = the row of output r's spider, present
+      // columns not attached to an output
+      uint64_t om = 0;
+      {
+        uint64_t b = lane < q ? (1ull << out_sp) : 0;
+        for (int o = 32; o > 0; o >>= 1) b |= wave_shfl64(b, lane ^ o, 64);
+        om = b;
+      }
+      uint64_t m = wave_shfl64(st.row, out_sp, 64) & st.alive & ~om;
+      if (lane >= q) m = 0;
+      int piv = -1;  // pivot column of row `lane` once placed
+      int cur = 0;
+      constexpr int NOKEY = 0x7fffffff;
+      while (cur < q) {
+        int key = (lane >= cur && m) ? ((__builtin_ctzll(m) << 15) | lane) : NOKEY;
+        for (int o = 32; o > 0; o >>= 1) key = min(key, __shfl_xor(key, o, 64));
+        key = uni(key);
+        if (key == NOKEY) break;
+        const int col = key >> 15, r = key & 0x7fff;
+        if (r != cur) {
+          const uint64_t mr = readlane64(m, r), mc = readlane64(m, cur);
+          if (lane == r) m = mc;
+          if (lane == cur) m = mr;
+        }
+        const uint64_t pr = readlane64(m, cur);
+        const bool hit = lane < q && lane != cur && ((m >> col) & 1);
+        ops += __popcll(__ballot(hit));
+        if (hit) m ^= pr;
+        if (lane == cur) piv = col;
+        ++cur;
+      }
+      rank = cur;
+      if (lane < q) {
+        ((uint64_t*)(arena + h->off_front))[lane] = m;
+        ((int32_t*)(arena + h->off_fpiv))[lane] = lane < cur ? piv : -1;
+      }
+    }
+    if (lane == 0) {
+      h->rank = rank;
+      h->rowops = ops;
+      h->policy_used = ZX_POLICY_GREEDY;
+      sh.E = st.E;
+      sh.rowops = ops;
+      sh.rank = rank;
+      sh.status = st.status;
+    }
+  }
+  __syncthreads();
+}
+
 // One diagram, start to finish, with the adjacency in LDS (LA) or the arena.
 template <int BS, bool LA, bool LEARN>
 __device__ void run_diagram(uint8_t* arena, uint8_t* lds, const SimpArgs& a, Shared& sh) {
   ZxHeader* h = (ZxHeader*)arena;
+  if constexpr (LA && !LEARN) {
+    if (uni(h->W) == 1 && uni(h->pw) == 0) {
+      run_tiny<BS>(arena, a, sh);
+      return;
+    }
+  }
   Ctx<LA> c;
   setup_ctx<BS, LA>(c, arena, lds);
   load_state<BS, LA>(c, sh, !a.resume);
@@ -2694,6 +2825,9 @@ static int pick_variant(const zx_batch* b, int tune_id, bool learned) {
     if (b->tuned >= 0) return b->tuned;
     auto it = tune_cache().find(size_class(b));
     if (it != tune_cache().end()) return it->second;
+    // a few diagrams of at most 64 spiders run in one wavefront's registers:
+    // one-wave workgroups, each on its own CU
+    if (b->max_n <= 64 && b->n <= 256 && variant_fits(b, kOneWaveVariant, false)) return kOneWaveVariant;
   }
   const int v = pick_variant_n(b->max_n, learned);
   return v >= 0 ? v : kDefaultVariant;
