@@ -33,6 +33,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -2717,6 +2718,40 @@ zx_status zx_team_area_init(void* area, hipStream_t s) {
   return ZX_OK;
 }
 
+// How many of the largest diagrams (sizes descending) to give teams.  The
+// team kernel runs before the one-workgroup kernel and takes the whole GPU,
+// so the teamed diagrams are serialised over the eight teams: a prefix pays
+// when the largest diagrams would otherwise set the batch's time on one
+// workgroup each.  Times from measured fits on this hardware (one
+// workgroup: about 16.7 ms x (n / 2012)^3; a team: about 10.2 ms x
+// (n / 2012)^1.6); the prefix minimises the teams' makespan (largest first,
+// each to the least loaded team) plus the largest remaining diagram's time
+// on one workgroup.
+static int32_t team_prefix(const int32_t* sizes, int32_t n_graphs) {
+  int32_t eligible = 0;
+  while (eligible < n_graphs) {
+    const int nn = sizes[eligible], ww = (nn + 63) / 64;
+    if (nn < TEAM_MIN_N || ww > TEAM_MAXW || aux_bytes(nn, ww) + 1024 > TEAM_LDS) break;
+    ++eligible;
+  }
+  auto one_wg = [](int nn) { const double r = nn / 2012.0; return 16.7 * r * r * r; };
+  auto team = [](int nn) { return 10.2 * pow(nn / 2012.0, 1.6); };
+  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t best = 0;
+  double best_t = n_graphs > 0 ? one_wg(sizes[0]) : 0.0;
+  for (int32_t k = 1; k <= eligible; ++k) {
+    double* m = std::min_element(load, load + 8);
+    *m += team(sizes[k - 1]);
+    const double rest = k < n_graphs ? one_wg(sizes[k]) : 0.0;
+    const double t = *std::max_element(load, load + 8) + rest;
+    if (t < best_t) {
+      best_t = t;
+      best = k;
+    }
+  }
+  return best;
+}
+
 struct zx_batch {
   uint8_t** table_dev;  // in the workspace
   Queue* queue;         // in the workspace
@@ -2773,12 +2808,7 @@ extern "C" zx_status zx_batch_prepare(zx_batch** b, zx_graph* const* graphs, int
   B->mean_n = sum / n_graphs;
   B->tuned = -1;
   // diagrams whose arena-mode rounds a team of workgroups shares
-  B->n_big = 0;
-  while (B->n_big < n_graphs) {
-    const int nn = B->sizes[B->n_big], ww = (nn + 63) / 64;
-    if (nn < TEAM_MIN_N || ww > TEAM_MAXW || aux_bytes(nn, ww) + 1024 > TEAM_LDS) break;
-    ++B->n_big;
-  }
+  B->n_big = team_prefix(B->sizes.data(), n_graphs);
   hipError_t e = hipMemcpyAsync(B->table_dev, B->arenas.data(), (size_t)n_graphs * 8,
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
