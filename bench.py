@@ -117,11 +117,12 @@ def bench_rref(zx, args):
     r = int(rank.item())
     pv = piv.cpu().numpy()
     last_strip = int(pv[r - 1]) // 64 if r > 0 else 0
+    strips32 = int(pv[r - 1]) // 32 + 1 if r > 0 else 0  # the kernel's 32-column strips up to the last pivot
     nbytes = rref_algorithmic_bytes(m, nw, last_strip)
     Rh = zx.to_host_words(R)
     timeline = strip_timeline(zx, ws, m) if args.rref_strips else None
     return dict(A=A, R=Rh, rank=r, piv=pv, ms=ms, wall_ms=1e3 * wall / args.steps, bytes=nbytes,
-                last_strip=last_strip, m=m, n=n, timeline=timeline)
+                last_strip=last_strip, strips32=strips32, m=m, n=n, timeline=timeline)
 
 
 def cpu_model():
@@ -950,7 +951,8 @@ def main():
         out.update(value=round(gbs, 2), unit="GB/s", ms_per_step=round(res["ms"], 4))
         out["config"] = {"workload": "gf2_rref 4096x16384 Bernoulli(1/2) seed 21 (full RREF)",
                          "m": 4096, "n_cols": 16384, "rank": res["rank"],
-                         "strips_with_pivots": res["last_strip"] + 1,
+                         "word_columns_with_pivots": res["last_strip"] + 1,
+                         "strips_32_columns_to_last_pivot": res["strips32"],
                          "algorithmic_bytes_per_step": res["bytes"]}
         out["pct_hbm_peak"] = round(100 * gbs / HBM_PEAK_GBS, 2)
         traffic = rref_traffic_bytes()
@@ -960,7 +962,10 @@ def main():
                                            "copy-calibrated) for gf2.hip " + gf2_source_hash()
                                            + ("" if traffic else " (not measured for this source)"),
                            "kernel": "rref_kernel (+ rref_init)", "avg_launch_ms": round(res["ms"], 4),
-                           "wall_ms_per_step": round(res["wall_ms"], 4)}
+                           "wall_ms_per_step": round(res["wall_ms"], 4),
+                           # the limiter: the serial chain of strip reductions and hand-offs
+                           "serial_chain": {"strips": res["strips32"],
+                                            "us_per_strip": round(1e3 * res["ms"] / max(1, res["strips32"]), 2)}}
         log("rref: %.4f ms/step, %.1f GB/s algorithmic (%.1f%% of 8 TB/s), rank %d" %
             (res["ms"], gbs, 100 * gbs / HBM_PEAK_GBS, res["rank"]))
         if res["timeline"]:

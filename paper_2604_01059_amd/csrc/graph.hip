@@ -363,6 +363,58 @@ __device__ bool build_candidates(Ctx<LA>& c, Shared& sh, int kind) {
   return uni(sh.any) != 0;
 }
 
+// One wavefront, after the round's selection (c.sel): the selected
+// spiders' count (sh.cnt), with lc_trace their trace entries in ascending
+// order, the list of the selected set's words (sh.nsw entries in c.blocked)
+// and of the selected spiders in ascending order (sh.ns entries in
+// c.slist).  The caller's barrier publishes them.
+template <bool LA>
+__device__ void list_selected_wave(Ctx<LA>& c, Shared& sh, bool lc_trace) {
+  const int lane = threadIdx.x & 63;
+  LDSP int32_t* sw = (LDSP int32_t*)c.blocked;
+  int cnt = 0, ns = 0;
+  const int nt0 = sh.n_trace, round = sh.round;
+  for (int j0 = 0; j0 < c.W; j0 += 64) {
+    const int j = j0 + lane;
+    const uint64_t wd = j < c.W ? c.sel[j] : 0;
+    const bool nz = wd != 0;
+    const uint64_t b = __ballot(nz);
+    if (nz) sw[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] = j;
+    cnt += __popcll(b);
+    // exclusive prefix of the per-word popcounts, by bit planes
+    const int pc = __popcll(wd);
+    int ex = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 7; ++bit) {
+      const uint64_t bb = __ballot((pc >> bit) & 1);
+      ex += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0)) << bit;
+      tot += __popcll(bb) << bit;
+    }
+    uint64_t m = wd;
+    int pos = ns + ex;
+    while (m) {
+      const int bit = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      c.slist[pos] = (int16_t)(64 * j + bit);
+      if (lc_trace && c.trace) {
+        int32_t* e = c.trace + 4 * (int64_t)(nt0 + pos);
+        e[0] = round;
+        e[1] = 0;
+        e[2] = 64 * j + bit;
+        e[3] = -1;
+      }
+      ++pos;
+    }
+    ns += tot;
+  }
+  if (lane == 0) {
+    sh.nsw = cnt;
+    sh.ns = ns;
+    sh.cnt = ns;
+    if (lc_trace && c.trace) sh.n_trace = nt0 + ns;
+  }
+}
+
 // Lexicographically-first maximal independent set of the candidates (scan
 // in ascending spider id, take a candidate unless adjacent to one taken).
 // One wavefront, one 64-spider block at a time.  The wave keeps the union
@@ -372,7 +424,8 @@ __device__ bool build_candidates(Ctx<LA>& c, Shared& sh, int kind) {
 // operations on their rows' word b, loaded one block ahead; then the rows
 // of the block's taken spiders are OR-ed into the union, four at a time.
 // Per block, the only wait on memory is for those rows and the next
-// block's words, issued together.
+// block's words, issued together.  The same wavefront then counts, traces
+// and lists the set (list_selected_wave), before the one closing barrier.
 template <int BS, bool LA>
 __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
   const int W = c.W;
@@ -426,6 +479,8 @@ __device__ void lfmis(Ctx<LA>& c, Shared& sh) {
         blk1 |= a1;
       }
     }
+    __builtin_amdgcn_wave_barrier();
+    list_selected_wave(c, sh, true);
   }
   __syncthreads();
 }
@@ -569,15 +624,19 @@ __device__ void collect_swords(Ctx<LA>& c, Shared& sh) {
 }
 
 // Per-round bookkeeping over the selected spiders (before the update),
-// after listing them (collect_swords).
+// after listing them (collect_swords, unless listed: done with the
+// selection).
 // LC: acc64[0] = sum deg, acc64[1] = sum deg(deg-1)/2, acc64[2] = phase sum.
 // Pivot: acc64[0] = sum (deg u + deg v - 1), acc64[1] = sum T_p, acc64[2] = phase.
 // Also fills kc[] and, for pivots, swaps each pair's rows into contributions.
 template <int BS, bool LA>
-__device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_only) {
+__device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool listed) {
   const int W = c.W;
   if (threadIdx.x == 0) sh.acc64[0] = sh.acc64[1] = sh.acc64[2] = sh.acc64[3] = 0;
-  collect_swords<BS, LA>(c, sh);
+  if (listed)
+    __syncthreads();
+  else
+    collect_swords<BS, LA>(c, sh);
   const int ns = uni(sh.ns);
   for (int i = c.team; i < ns; i += c.nteams) {
     const int x = c.slist[i];
@@ -628,7 +687,6 @@ __device__ void prepare_round(Ctx<LA>& c, Shared& sh, bool pivot, bool graph_onl
     }
   }
   __syncthreads();
-  (void)graph_only;
 }
 
 // The rank-|S| update of every present row outside S, by (row, word)
@@ -1142,7 +1200,7 @@ __device__ void delete_selected(Ctx<LA>& c, Shared& sh, bool cols_done) {
     if (c.tl == 0) c.k[x] = 0;
     for (int q = c.tl; q < c.pw; q += c.T) c.par[(int64_t)x * c.pw + q] = 0;
   }
-  __syncthreads();
+  // (the column pass above reads the selected set, not the present one)
   for (int j = threadIdx.x; j < W; j += BS) c.alive[j] &= ~c.sel[j];
   __syncthreads();
 }
@@ -1547,26 +1605,27 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
       sort_keys_desc<BS>(*pol, C);
       select_lc_priority<BS, LA>(c, sh, *pol, C);
     } else {
-      lfmis<BS, LA>(c, sh);
+      lfmis<BS, LA>(c, sh);  // also counts, traces and lists the set
     }
-    if (threadIdx.x == 0) sh.cnt = 0;
-    __syncthreads();
-    int cnt = 0;
-    for (int j = threadIdx.x; j < c.W; j += BS) cnt += __popcll(c.sel[j]);
-    if (cnt) atomicAdd(&sh.cnt, cnt);
-    __syncthreads();
+    if constexpr (LEARN) {
+      if (threadIdx.x == 0) sh.cnt = 0;
+      __syncthreads();
+      int cnt = 0;
+      for (int j = threadIdx.x; j < c.W; j += BS) cnt += __popcll(c.sel[j]);
+      if (cnt) atomicAdd(&sh.cnt, cnt);
+      __syncthreads();
+      trace_lc_round<BS, LA>(c, sh);
+    }
     const int removed = uni(sh.cnt);
-    trace_lc_round<BS, LA>(c, sh);
-    prepare_round<BS, LA>(c, sh, false, false);
+    prepare_round<BS, LA>(c, sh, false, !LEARN);
     if (c.pw) {
       terms_round<BS, LA>(c, sh, false);
       param_round<BS, LA>(c, sh, false);
     }
     const bool cc = apply_round<BS, LA>(c, sh, false);
     delete_selected<BS, LA>(c, sh, cc);
+    if (threadIdx.x == 0) sh.round++;  // published by finish_round's barrier
     finish_round<BS, LA>(c, sh, removed);
-    if (threadIdx.x == 0) sh.round++;
-    __syncthreads();
   }
   // pivot rounds
   for (;;) {
