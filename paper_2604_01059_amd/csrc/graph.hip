@@ -364,12 +364,12 @@ __device__ bool build_candidates(Ctx<LA>& c, Shared& sh, int kind) {
 }
 
 // One wavefront, after the round's selection (c.sel): the selected
-// spiders' count (sh.cnt), with lc_trace their trace entries in ascending
+// spiders' count (sh.cnt, with set_cnt), with lc_trace their trace entries in ascending
 // order, the list of the selected set's words (sh.nsw entries in c.blocked)
 // and of the selected spiders in ascending order (sh.ns entries in
 // c.slist).  The caller's barrier publishes them.
 template <bool LA>
-__device__ void list_selected_wave(Ctx<LA>& c, Shared& sh, bool lc_trace) {
+__device__ void list_selected_wave(Ctx<LA>& c, Shared& sh, bool lc_trace, bool set_cnt = true) {
   const int lane = threadIdx.x & 63;
   LDSP int32_t* sw = (LDSP int32_t*)c.blocked;
   int cnt = 0, ns = 0;
@@ -410,7 +410,7 @@ __device__ void list_selected_wave(Ctx<LA>& c, Shared& sh, bool lc_trace) {
   if (lane == 0) {
     sh.nsw = cnt;
     sh.ns = ns;
-    sh.cnt = ns;
+    if (set_cnt) sh.cnt = ns;
     if (lc_trace && c.trace) sh.n_trace = nt0 + ns;
   }
 }
@@ -578,6 +578,8 @@ __device__ void select_pivots(Ctx<LA>& c, Shared& sh) {
       sh.cnt = npairs;
       sh.n_trace = nt;
     }
+    __builtin_amdgcn_wave_barrier();
+    list_selected_wave(c, sh, false, false);  // the lists prepare_round takes
   }
   __syncthreads();
 }
@@ -1647,17 +1649,16 @@ __device__ void simplify_rounds(Ctx<LA>& c, Shared& sh, Pol* pol, int max_rounds
     }
     const int npairs = uni(sh.cnt);
     if (npairs == 0) break;
-    prepare_round<BS, LA>(c, sh, true, false);
+    prepare_round<BS, LA>(c, sh, true, true);  // lists built with the selection
     if (c.pw) {
       terms_round<BS, LA>(c, sh, true);
       param_round<BS, LA>(c, sh, true);
     }
     const bool cc = apply_round<BS, LA>(c, sh, true);
     delete_selected<BS, LA>(c, sh, cc);
-    finish_round<BS, LA>(c, sh, 2 * npairs);
     for (int i = threadIdx.x; i < uni(sh.ns); i += BS) c.partner[c.slist[i]] = -1;
-    if (threadIdx.x == 0) sh.round++;
-    __syncthreads();
+    if (threadIdx.x == 0) sh.round++;  // both published by finish_round's barrier
+    finish_round<BS, LA>(c, sh, 2 * npairs);
   }
 }
 
