@@ -388,6 +388,13 @@ __device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN, bool pivot) 
 
 // Bitonic sort of p.key[0..P) descending, P = next power of two >= C
 // (entries C..P-1 are set to 0 and sort last).
+// Bitonic sort of the C keys (padded with zeros to a power of two),
+// descending.  Element i is handled by thread i mod BS, so the partners of a
+// step of distance below 64 are in the same wavefront.  Between two such
+// steps only the wavefront's LDS accesses need ordering; a block barrier
+// follows every step of distance 64 or more and every step that precedes
+// one (the last step of a merge whose next merge starts at distance 64 or
+// more).
 template <int BS>
 __device__ void sort_keys_desc(Pol& p, int C) {
   int P = 1;
@@ -407,17 +414,27 @@ __device__ void sort_keys_desc(Pol& p, int C) {
           }
         }
       }
-      __syncthreads();
+      const int next_j = j > 1 ? j >> 1 : k;  // the next step's distance (next merge: 2k, from k)
+      if (j >= 64 || next_j >= 64) {
+        __syncthreads();
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
     }
+  __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t key_index(uint64_t k) { return 0xffffffffu - (uint32_t)k; }
 
 // LC round in priority order: take each candidate unless adjacent to one
-// taken before it.  One wavefront, 64 candidates of the order at a time:
-// lane l tests its candidate against the spiders taken in earlier blocks,
-// builds its adjacency to the block's other candidates, and the block is
-// resolved in order with scalar bit operations.
+// taken before it.  One wavefront, 64 candidates of the order at a time.
+// The wavefront keeps the union of the taken spiders' rows (lane l: words l
+// and l + 64), so a candidate adjacent to a spider taken in an earlier
+// block is one bit of it.  The block's free candidates are then taken in
+// order; each taken spider x drops the later ones adjacent to it (lane m
+// reads bit u_m of x's row), and its row joins the union.
 template <int BS, bool LA>
 __device__ void select_lc_priority(Ctx<LA>& c, Shared& sh, Pol& p, int C) {
   const int W = c.W;
@@ -425,31 +442,49 @@ __device__ void select_lc_priority(Ctx<LA>& c, Shared& sh, Pol& p, int C) {
   __syncthreads();
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
+    // clamped word indices (W <= 128): a lane's words past W are loaded
+    // from word W - 1 and never read
+    const int j0 = lane < W ? lane : W - 1;
+    const int j1 = lane + 64 < W ? lane + 64 : W - 1;
+    uint64_t blk0 = 0, blk1 = 0;
     for (int b = 0; b < C; b += 64) {
       const int e = b + lane;
       const int u = e < C ? (int)p.list[key_index(p.key[e])] : -1;
-      const int cnt = C - b < 64 ? C - b : 64;
-      bool fr = u >= 0;
-      uint64_t nb = 0;
-      if (fr) {
-        const auto ru = row_ptr(c, u);
-        for (int j = 0; j < W; ++j)
-          if (ru[j] & c.sel[j]) {
-            fr = false;
-            break;
-          }
-      }
-      for (int m = 0; m < cnt; ++m) {
-        const int x = __builtin_amdgcn_readlane(u, m);
-        if (u >= 0) nb |= (uint64_t)((row_ptr(c, u)[x >> 6] >> (x & 63)) & 1) << m;
-      }
-      uint64_t R = __ballot(fr), taken = 0;
+      const int wi = u >= 0 ? (u >> 6) : 0;  // u's word (word 0 stands in past C)
+      const uint64_t b0 = wave_shfl64(blk0, wi & 63, 64), b1 = wave_shfl64(blk1, wi & 63, 64);
+      const uint64_t bw = wi < 64 ? b0 : b1;
+      uint64_t R = __ballot(u >= 0 && !((bw >> (u & 63)) & 1));
+      uint64_t taken = 0;
       while (R) {
         const int l = __builtin_ctzll(R);
         taken |= 1ull << l;
-        R &= ~(readlane64(nb, l) | (1ull << l));
+        R &= ~(1ull << l);
+        const int x = __builtin_amdgcn_readlane(u, l);
+        const bool adj = u >= 0 && ((row_ptr(c, x)[wi] >> (u & 63)) & 1);
+        R &= ~__ballot(adj);
       }
       if ((taken >> lane) & 1) atomicOr((unsigned long long*)&c.sel[u >> 6], 1ull << (u & 63));
+      // the taken rows join the union, four at a time
+      uint64_t tk = taken;
+      while (tk) {
+        int t[4];
+        t[0] = __builtin_ctzll(tk);
+        tk &= tk - 1;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          t[q] = tk ? __builtin_ctzll(tk) : t[0];
+          tk &= tk - 1;
+        }
+        uint64_t a0 = 0, a1 = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const auto rt = row_ptr(c, __builtin_amdgcn_readlane(u, t[q]));
+          a0 |= rt[j0];
+          a1 |= rt[j1];
+        }
+        blk0 |= a0;
+        blk1 |= a1;
+      }
       __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_wave_barrier();
     }
