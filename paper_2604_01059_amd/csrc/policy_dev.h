@@ -301,7 +301,7 @@ __device__ void two_hop32(Ctx<LA>& c, const LDSP uint32_t* list, int base, int C
     const bool vin = v < n;
     const auto rv = row_ptr(c, vin ? v : 0);
     const int wj = jb >> 1;
-    uint64_t ax = xr >= 0 ? rx[wj] : 0;
+    uint64_t ax = rx[wj] & (xr >= 0 ? ~0ull : 0ull);
     if (xr >= 0 && (xr >> 6) == wj) ax |= 1ull << (xr & 63);
     pol_v8i bo = bits_fp4(h == (jb & 1) && vin ? 1u << l32 : 0u);
     bo[0] *= 15;  // nibble 0xF: -6
@@ -311,11 +311,27 @@ __device__ void two_hop32(Ctx<LA>& c, const LDSP uint32_t* list, int base, int C
     pol_v16f acc = {};
     acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bits_fp4((uint32_t)(ax >> (32 * h))), bo, acc, 4, 4, 0,
                                                           128, 0, 138);
-    for (int ks = 0; ks < W; ++ks) {
-      const uint32_t ad = xr >= 0 ? (uint32_t)(rx[ks] >> (32 * h)) : 0u;
-      const uint32_t bd = vin ? (uint32_t)(rv[ks] >> (32 * h)) : 0u;
-      acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bits_fp4(ad), bits_fp4(bd), acc, 4, 4, 0, 128, 0, 128);
+    // rows rx and rv are always in range (row 0 stands in), so their words
+    // are loaded without branches, four steps' worth before the first is used
+    const uint32_t am = xr >= 0 ? 0xffffffffu : 0u, bm = vin ? 0xffffffffu : 0u;
+    int ks = 0;
+    for (; ks + 4 <= W; ks += 4) {
+      uint64_t ra[4], rb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[q] = rx[ks + q];
+        rb[q] = rv[ks + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bits_fp4((uint32_t)(ra[q] >> (32 * h)) & am),
+                                                              bits_fp4((uint32_t)(rb[q] >> (32 * h)) & bm), acc, 4,
+                                                              4, 0, 128, 0, 128);
     }
+    for (; ks < W; ++ks)
+      acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(bits_fp4((uint32_t)(rx[ks] >> (32 * h)) & am),
+                                                            bits_fp4((uint32_t)(rv[ks] >> (32 * h)) & bm), acc, 4, 4,
+                                                            0, 128, 0, 128);
     // register r of lane (h, l32): candidate 8 (r / 4) + 4 h + r % 4, spider 32 jb + l32
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -386,10 +402,8 @@ __device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN, bool pivot) 
   }
 }
 
-// Bitonic sort of p.key[0..P) descending, P = next power of two >= C
-// (entries C..P-1 are set to 0 and sort last).
-// Bitonic sort of the C keys (padded with zeros to a power of two),
-// descending.  Element i is handled by thread i mod BS, so the partners of a
+// Bitonic sort of the C keys (padded with zeros to a power of two, which
+// sort last), descending.  Element i is handled by thread i mod BS, so the partners of a
 // step of distance below 64 are in the same wavefront.  Between two such
 // steps only the wavefront's LDS accesses need ordering; a block barrier
 // follows every step of distance 64 or more and every step that precedes
