@@ -345,6 +345,58 @@ __device__ void two_hop32(Ctx<LA>& c, const LDSP uint32_t* list, int base, int C
     if (lane == r) th[r] = cnt[r];
 }
 
+// Features of a block of up to 32 candidates (list entries base..base+cnt)
+// into fb (32 rows of IN), one endpoint per lane, the two-hop counts given
+// (th; pivots: first ends th[0..32), second ends th[32..64), ends in el).
+// Lane r (r < 32) takes candidate r's first endpoint, lane 32 + r a pivot's
+// second endpoint: degree, boundary and input neighbours by popcounts over
+// the endpoint's row, the phase bits, in the same arithmetic as
+// endpoint_features.
+template <bool LA>
+__device__ void block_features(Ctx<LA>& c, const Pol& p, int base, int cnt, bool pivot, float invN,
+                               LDSP uint16_t* fb, const LDSP int32_t* th, const LDSP uint32_t* el) {
+  const int lane = threadIdx.x & 63, r = lane & 31, second = lane >> 5, W = c.W;
+  int x = -1;
+  if (r < cnt) {
+    if (pivot)
+      x = (int)el[32 * second + r];
+    else if (second == 0)
+      x = (int)p.list[base + r];
+  }
+  LDSP uint16_t* f = fb + r * zxmlp::IN;
+  if (x >= 0) {
+    const auto rx = row_ptr(c, x);
+    int deg = 0, bn = 0, pn = 0;
+#pragma unroll 4
+    for (int j = 0; j < W; ++j) {
+      const uint64_t w = rx[j];
+      deg += __popcll(w);
+      bn += __popcll(w & c.bnd[j]);
+      pn += __popcll(w & c.inm[j]);
+    }
+    const int t = th[pivot ? 32 * second + r : r];
+    const int k = c.k[x];
+    LDSP uint16_t* fo = f + 7 * second;
+    fo[0] = zxmlp::to_bf16((float)deg * invN);
+    fo[1] = zxmlp::to_bf16((k & 3) == 0 ? 1.f : 0.f);
+    fo[2] = zxmlp::to_bf16((k & 3) == 2 ? 1.f : 0.f);
+    fo[3] = zxmlp::to_bf16((k & 1) ? 1.f : 0.f);
+    fo[4] = zxmlp::to_bf16((float)bn * invN);
+    fo[5] = zxmlp::to_bf16((float)t * invN);
+    fo[6] = zxmlp::to_bf16((float)pn * invN);
+  }
+  if (second == 0) {
+    if (r < cnt) {
+      if (!pivot)
+        for (int q = 7; q < 14; ++q) f[q] = 0;
+      f[14] = zxmlp::to_bf16(pivot ? 1.f : 0.f);
+      f[15] = zxmlp::to_bf16(1.f);
+    } else {
+      for (int q = 0; q < zxmlp::IN; ++q) f[q] = 0;
+    }
+  }
+}
+
 // Order-preserving map of a float onto uint32.
 __device__ __forceinline__ uint32_t float_order(float x) {
   const uint32_t u = __float_as_uint(x);
@@ -376,17 +428,7 @@ __device__ void policy_score(Ctx<LA>& c, Pol& p, int C, float invN, bool pivot) 
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    for (int r = 0; r < 32; ++r) {
-      LDSP uint16_t* f = fb + r * zxmlp::IN;
-      if (r < cnt) {
-        if (pivot)
-          pivot_features(c, uni((int)el[r]), uni((int)el[32 + r]), invN, f, uni(tb[r]), uni(tb[32 + r]));
-        else
-          candidate_features(c, (int)p.list[base + r], invN, f, uni(tb[r]));
-      } else if (lane < zxmlp::IN) {
-        f[lane] = 0;
-      }
-    }
+    block_features(c, p, base, cnt, pivot, invN, fb, tb, el);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     float s[16];
