@@ -41,6 +41,8 @@ RREF_TRAFFIC = {
     "33a1b390f0dd9346": {"fetch_kib": 25724.2, "write_kib": 11388.3},
     # the same kernels with the allocation-free entry point beside them
     "de70e2edf8bc1717": {"fetch_kib": 25725.0, "write_kib": 11388.3},
+    # the strip reduction at raised wave priority
+    "1692da521e87034f": {"fetch_kib": 25722.2, "write_kib": 11388.3},
 }
 METRIC = "GF(2) elim GB/s (% HBM peak); diagrams simplified/sec batched vs plain, bit-exact"
 
